@@ -1,0 +1,296 @@
+#!/usr/bin/env python3
+"""Throughput of the batched periodic-graph hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic crystals:
+  cutoff multigraph build (bounds, plan, image tables, count, scan, fill)
+  + KNN multigraph build (bounds, plan, image tables, ordered-stack select)
+  + edge geometry forward on the cutoff edges
+  + upstream gradient of the loss sum_e w_e exp(-(l_e - 3)^2) (torch, elementwise)
+  + edge geometry backward to fractional coordinates and lattices.
+
+Default workload: 4096 structures, 1..128 atoms (log-uniform), cell lengths
+2.5-20 A, angles 30-150 deg, cutoff 8 A, k = 16, one launch sequence per graph
+type for the whole batch. Prints one JSON line (see the fields below).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--config 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# algorithmic work per unit: bytes per edge / flops per candidate
+BYTES_PER_EDGE_FILL = 24.0     # src, dst (4+4), image (12), length (4)
+BYTES_PER_EDGE_GEOM = 36.0     # read src, dst, image (20) + write vec, length (16)  /  read grads (16)
+FLOPS_PER_CANDIDATE = 8.0      # 3 add + 1 mul + 2 fma (= 8 flops) per (source, destination, image)
+
+
+def _parse(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4])
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-structure launch baseline")
+    ap.add_argument("--plain-structures", type=int, default=1024,
+                    help="structures timed in the per-structure form (rate is per structure)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (profiler counter calibration)")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args(argv)
+
+
+def _log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(batch, seconds: float):
+    """The FP64 oracle on a bounded prefix of the batch (cutoff + KNN + geometry
+    + its VJP), in a process pool on the host's cores. Returns the dict for the
+    JSON line."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+
+    cores = min(os.cpu_count() or 1, 16)
+    # size the sample from a quick single-structure timing
+    def run(structs, procs):
+        t0 = time.perf_counter()
+        g = oracle.cutoff_graph64(batch.lattices, batch.frac, batch.batch_ptr, batch.cutoff,
+                                  structures=structs, processes=procs)
+        oracle.knn_graph64(batch.lattices, batch.frac, batch.batch_ptr, batch.k, structures=structs,
+                           processes=procs)
+        v, ln = oracle.edge_geometry64(batch.lattices, batch.frac, batch.batch_ptr, g.src, g.dst, g.image)
+        oracle.edge_geometry_vjp64(batch.lattices, batch.frac, batch.batch_ptr, g.src, g.dst, g.image,
+                                   None, np.ones_like(ln))
+        return time.perf_counter() - t0, g.num_edges
+
+    probe = list(range(0, batch.B, max(1, batch.B // 64)))[:64]
+    dt, _ = run(probe, cores)
+    per = dt / len(probe)
+    S = int(min(batch.B, max(len(probe), seconds / max(per, 1e-6))))
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(batch.B, S, replace=False).tolist()) if S < batch.B else list(range(batch.B))
+    dt, E = run(sample, cores)
+    return {"value": len(sample) / dt, "unit": "structures/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sample)} of {batch.B} structures drawn uniformly (seed 0), FP64 numpy "
+                      f"cutoff+KNN+geometry+VJP, {E} cutoff edges, {dt:.1f} s wall on {cores} processes",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main(argv=None):
+    args = _parse(argv)
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the batch shards over GPUs "
+                                   "by structure with no communication (see DESIGN.md), and no "
+                                   "multi-GPU figure is produced", "n_gpus": args.gpus}))
+        return 2
+    import numpy as np
+    import torch
+
+    from paper_2307_05380_amd import _lib, graph, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    batch = inputs.make_config(args.config)
+    B, N, k, c = batch.B, batch.N, batch.k, batch.cutoff
+    L = torch.from_numpy(batch.lattices).to(dev)
+    X = torch.from_numpy(batch.frac).to(dev)
+    P = torch.from_numpy(batch.batch_ptr).to(dev)
+    _log(args, f"workload config{args.config}: B={B} N={N} cutoff={c} k={k}")
+
+    # ---- sizing (untimed): exact edge count and image-table sizes
+    g0 = graph.cutoff_graph(L, X, P, c)
+    E = g0.num_edges
+    cut_images = g0.report.images_needed
+    k0 = graph.knn_graph(L, X, P, k)
+    knn_images = k0.report.images_needed
+    del g0, k0
+    cb = graph.CutoffBuilder(B, N, E, cut_images, dev)
+    kb = graph.KnnBuilder(B, N, k, knn_images, dev)
+    geo = graph.GeometryRunner(B, N, dev)
+    vec = torch.empty((E, 3), dtype=torch.float32, device=dev)
+    length = torch.empty(E, dtype=torch.float32, device=dev)
+    w = torch.from_numpy(inputs.loss_weights(E)).to(dev)
+    gf = torch.empty_like(X)
+    gL = torch.empty_like(L)
+    glen = torch.empty(E, dtype=torch.float32, device=dev)
+    tmp = torch.empty(E, dtype=torch.float32, device=dev)
+
+    def step():
+        cb.run(L, X, P, c)
+        kb.run(L, X, P)
+        geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length)
+        # d loss / d l = -2 w (l - 3) exp(-(l - 3)^2)   (the model's part)
+        torch.sub(length, 3.0, out=tmp)
+        torch.mul(tmp, tmp, out=glen)
+        glen.neg_().exp_().mul_(tmp).mul_(w).mul_(-2.0)
+        geo.backward(L, X, P, cb.src, cb.dst, cb.image, None, glen, gf, gL)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rep_c = cb.report()
+    rep_k = kb.report()
+    assert rep_c.num_edges == E and not (rep_c.flags & ~_lib.MG_FLAG_KNN_EXTENDED), rep_c
+    _lib.profile_enable(True)
+    _lib.profile_read()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _lib.profile_enable(False)
+    phases = _lib.profile_read()
+    ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    ms_step_ev = ev0.elapsed_time(ev1) / max(args.steps, 1)
+
+    # ---- roofline of every phase; the dominant one goes into "roofline"
+    per = {}
+    work = {
+        "cutoff.fill": ("hbm", BYTES_PER_EDGE_FILL * E),
+        "cutoff.count": ("alu", FLOPS_PER_CANDIDATE * rep_c.candidates),
+        "knn.select": ("alu", FLOPS_PER_CANDIDATE * rep_k.candidates),
+        "geometry.fwd": ("hbm", BYTES_PER_EDGE_GEOM * E),
+        "geometry.bwd": ("hbm", BYTES_PER_EDGE_GEOM * E),
+    }
+    for name, (ms, cnt) in phases.items():
+        avg = ms / max(cnt, 1)
+        d = {"ms_avg": round(avg, 5), "launches": cnt}
+        if name in work:
+            bound, amount = work[name]
+            if bound == "hbm":
+                ach = amount / (avg * 1e-3) / 1e9
+                d.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(ach / HBM_PEAK_GBS, 4))
+            else:
+                ach = amount / (avg * 1e-3) / 1e12
+                d.update(bound="alu", achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                         frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4))
+        per[name] = d
+    dom = max((n for n in per if n in work), key=lambda n: per[n]["ms_avg"], default=None)
+    roof = None
+    if dom:
+        d = per[dom]
+        roof = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+                "unit": d["unit"], "frac": d["frac"], "traffic": None}
+
+    # ---- per-structure launch form (the plain method, one launch sequence per structure)
+    plain = None
+    if not args.no_plain:
+        plain = plain_form(args, batch, L, X, P, cb, dev)
+
+    out = {
+        "metric": "structures/s & edges/s, batched cutoff+KNN build fwd+bwd vs plain; % roofline",
+        "value": round(B / (ms_step / 1e3), 1),
+        "unit": "structures/s",
+        "edges_per_s": round((E + N * k) / (ms_step / 1e3), 1),
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "ms_per_step_events": round(ms_step_ev, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"config{args.config}: {B} structures, {N} atoms, cutoff {c} A, k {k}, "
+                               "one batched launch sequence per graph type",
+                   "structures": B, "atoms": N, "cutoff_edges": E, "knn_edges": N * k, "cutoff": c, "k": k},
+        "roofline": roof,
+        "phases": per,
+        "plain": plain,
+        "vs_plain": round((B / (ms_step / 1e3)) / plain["value"], 2) if plain else None,
+        "report": {"cutoff_candidates": rep_c.candidates, "cutoff_images": rep_c.images_needed,
+                   "knn_candidates": rep_k.candidates, "knn_images": rep_k.images_needed,
+                   "knn_extended_sources": rep_k.knn_extended},
+    }
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        bb = torch.empty_like(a)
+        bb.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = n * 4
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
+        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 2)
+    print(json.dumps(out))
+    return 0
+
+
+def plain_form(args, batch, L, X, P, cb, dev):
+    """The same kernels launched once per structure: every structure gets its own
+    cutoff call, KNN call, geometry forward and backward (outputs written at the
+    batched offsets). Times the first `plain_structures` structures."""
+    import numpy as np
+    import torch
+
+    from paper_2307_05380_amd import graph
+
+    S = min(args.plain_structures, batch.B)
+    ptr = batch.batch_ptr
+    row = cb.row_ptr.cpu().numpy()
+    k = batch.k
+    nmax = int(np.diff(ptr).max())
+    local_ptr = torch.tensor([[0, int(ptr[s + 1] - ptr[s])] for s in range(S)], dtype=torch.int64, device=dev)
+    cap_max = int(max(row[ptr[s + 1]] - row[ptr[s]] for s in range(S)))
+    cbs = graph.CutoffBuilder(1, nmax, max(cap_max, 1), 1 << 16, dev)
+    kbs = graph.KnnBuilder(1, nmax, k, 1 << 16, dev)
+    geo = graph.GeometryRunner(1, nmax, dev)
+    vec = torch.empty((max(cap_max, 1), 3), device=dev)
+    ln = torch.empty(max(cap_max, 1), device=dev)
+    gf = torch.empty((nmax, 3), device=dev)
+    gL = torch.empty((1, 3, 3), device=dev)
+    glen = torch.ones(max(cap_max, 1), device=dev)
+    lib = cbs.lib
+    from paper_2307_05380_amd.graph import _ptr, _stream
+    import ctypes
+
+    def one(s):
+        a0, a1 = int(ptr[s]), int(ptr[s + 1])
+        n = a1 - a0
+        Ls = L[s:s + 1]
+        Xs = X[a0:a1]
+        ps = local_ptr[s]
+        cbs.N = n
+        kbs.N = n
+        cbs.run(Ls, Xs, ps, batch.cutoff)
+        kbs.run(Ls, Xs, ps)
+        e = int(row[a1] - row[a0])
+        if e:
+            geo.N = n
+            geo.forward(Ls, Xs, ps, cbs.src[:e], cbs.dst[:e], cbs.image[:e], vec, ln)
+            geo.backward(Ls, Xs, ps, cbs.src[:e], cbs.dst[:e], cbs.image[:e], None, glen, gf, gL)
+
+    for s in range(min(8, S)):
+        one(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(S):
+        one(s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": round(S / dt, 1), "unit": "structures/s", "structures": S,
+            "form": "one launch sequence per structure (same kernels), first S structures of the batch"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,207 @@
+/*
+ * matgraph.h - periodic cutoff / k-nearest-neighbour multigraphs of crystal
+ * batches on AMD MI355X (gfx950), C ABI of libmatgraph.so.
+ *
+ * What the library computes (arxiv 2307.05380):
+ *  - the crystallographic graph of Sec. 2.1, Definition def6: for a material
+ *    (rho, x) with n atoms, the edges are the triplets (i, j, t) with t in Z^3
+ *    such that || rho (x_j - x_i + t) || < c.  It is a multigraph: a pair may
+ *    carry several edges and an atom has edges to its own images (Sec. 1).
+ *    The self-image (i, i, 0) is not an edge.
+ *  - the k-nearest-neighbour graph, the special case of Definition def6 where
+ *    every source keeps exactly its k nearest (j, t) (Sec. 1 and the remark
+ *    after Definition def6; Sec. 2.2, Algorithms 1 and 2).
+ *  - edge vectors and lengths and their backward pass, so that a model can move
+ *    the geometry and rebuild the graph inside its forward pass (abstract,
+ *    Sec. 4).
+ *
+ * Conventions shared by every call
+ *  - lattices: float32 [B][3][3], ROW k is lattice vector a_k in Angstrom; the
+ *    paper's rho is the transpose. Cartesian = frac @ lattice.
+ *  - frac: float32 [N][3] fractional coordinates. Values outside [0, 1) are
+ *    accepted; edges follow Definition def6 applied to the coordinates as given
+ *    and t is relative to them.
+ *  - batch_ptr: int64 [B+1], non-decreasing, batch_ptr[0] = 0, batch_ptr[B] = N.
+ *    Structure b owns atoms batch_ptr[b] .. batch_ptr[b+1]-1.
+ *  - an edge is (src, dst, image t) with int32 global atom indices and int32
+ *    image components; its vector is (frac[dst] - frac[src] + t) @ lattice[b].
+ *  - all pointers are DEVICE pointers unless marked [host]. The caller owns
+ *    every buffer; the library never allocates or frees memory on these calls
+ *    (scratch space comes from the caller's workspace), so they can be
+ *    captured into a HIP graph.
+ *  - every compute call is asynchronous on `stream` (a hipStream_t; NULL means
+ *    the default stream). Host-detectable errors return a non-zero mg_status
+ *    immediately, enqueue nothing, and set mg_last_error(). Conditions found on
+ *    the device never abort: they set bits of mg_report.flags.
+ *  - distances are computed in FP32 from FP64-derived per-pair and per-image
+ *    offsets; the per-structure image bounds are computed in FP64 on the GPU.
+ */
+#ifndef MATGRAPH_H
+#define MATGRAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_ABI_VERSION 1
+
+typedef int32_t mg_status;
+enum {
+    MG_OK = 0,
+    MG_ERR_INVALID_ARG = 1,   /* null required pointer, bad size, bad cutoff / k ... */
+    MG_ERR_WORKSPACE = 2,     /* workspace pointer null or smaller than the fixed part */
+    MG_ERR_HIP = 3,           /* a HIP runtime call failed (message in mg_last_error) */
+    MG_ERR_UNSUPPORTED = 4    /* the request exceeds a documented limit */
+};
+
+/* Bits of mg_report.flags (set on the device, never cleared by the library
+ * except at the start of a call). */
+enum {
+    MG_FLAG_CAPACITY = 1u,      /* cutoff: more edges than `capacity`; nothing was written past
+                                   capacity, mg_report.num_edges holds the exact count */
+    MG_FLAG_SINGULAR = 2u,      /* a lattice with |det| < 1e-9 * |a1||a2||a3|: that structure has no edges */
+    MG_FLAG_NONFINITE = 4u,     /* a NaN/Inf lattice entry or coordinate: that structure has no edges */
+    MG_FLAG_IMAGES = 8u,        /* the workspace's image table was too small: the graph is incomplete;
+                                   mg_report.images_needed holds the entries required */
+    MG_FLAG_RANGE = 16u,        /* an image offset beyond |t_k| <= 511 or a KNN key space beyond 2^32
+                                   would be needed: that structure (or source) has no edges */
+    MG_FLAG_KNN_EXTENDED = 32u  /* informational: some KNN sources needed the extended search */
+};
+
+/* Device-resident summary written by the graph calls (64 bytes). */
+typedef struct mg_report {
+    int64_t num_edges;       /* edges the inputs define (cutoff: exact even if > capacity; KNN: N*k) */
+    int64_t images_needed;   /* image-table entries the batch needs (see mg_*_workspace_bytes) */
+    int64_t candidates;      /* (source, destination, image) candidates evaluated by the main sweep */
+    int64_t knn_extended;    /* KNN sources resolved by the extended search */
+    uint32_t flags;          /* MG_FLAG_* */
+    uint32_t reserved[7];
+} mg_report;
+
+/* Bits of `opts`. */
+enum {
+    MG_OPT_DEFAULT = 0,
+    MG_OPT_CELL_LIST_OFF = 2,   /* never use cell lists (large structures use the image sweep) */
+    MG_OPT_CELL_LIST_FORCE = 4  /* use cell lists for every structure where they apply */
+};
+
+/* ABI version of the loaded library (MG_ABI_VERSION). */
+int32_t mg_abi_version(void);
+
+/* [host] Message of the last non-OK status returned on this thread ("" if none). */
+const char* mg_last_error(void);
+
+/* Workspace bytes for mg_cutoff_graph on B structures / N atoms with room for
+ * `image_capacity` image-table entries (16 bytes each). The table holds, per
+ * structure, the lattice translations whose cell can reach within the cutoff;
+ * a cutoff call sets MG_FLAG_IMAGES and reports images_needed when the batch
+ * needs more. Returns 0 for negative arguments. */
+size_t mg_cutoff_workspace_bytes(int32_t B, int64_t N, int64_t image_capacity);
+
+/* Workspace bytes for mg_knn_graph (same meaning of image_capacity; k in 1..64). */
+size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_capacity);
+
+/* Workspace bytes for mg_edge_geometry / mg_edge_geometry_backward. */
+size_t mg_geometry_workspace_bytes(int32_t B, int64_t N);
+
+/*
+ * Periodic cutoff multigraph (Definition def6 with a constant cutoff c_i = cutoff).
+ *
+ *  cutoff        > 0 and finite, Angstrom; the test is strict (length < cutoff).
+ *  capacity      number of edge slots in src/dst/image/length (>= 0).
+ *  src, dst      int32 [capacity]; image int32 [capacity][3]; length float32 [capacity].
+ *  row_ptr       int64 [N+1] or NULL: edges of source i are row_ptr[i] .. row_ptr[i+1]-1
+ *                (edges are grouped by ascending src; the order inside a source is
+ *                deterministic but unspecified).
+ *  report        one mg_report (device), overwritten.
+ *  workspace     device scratch of workspace_bytes (see mg_cutoff_workspace_bytes);
+ *                its contents are not needed between calls.
+ *  opts          MG_OPT_* bits.
+ * Errors: MG_ERR_INVALID_ARG for null inputs/outputs (outputs may be NULL only when
+ * capacity == 0), B < 0, N < 0, N > INT32_MAX, bad cutoff; MG_ERR_WORKSPACE if the
+ * workspace is smaller than mg_cutoff_workspace_bytes(B, N, 0).
+ */
+mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                          int32_t B, int64_t N, float cutoff, int64_t capacity,
+                          int32_t* src, int32_t* dst, int32_t* image, float* length,
+                          int64_t* row_ptr, mg_report* report,
+                          void* workspace, size_t workspace_bytes, int32_t opts, void* stream);
+
+/*
+ * Periodic k-nearest-neighbour multigraph (Sec. 1; Sec. 2.2 Algorithms 1-2).
+ * Every source gets exactly k edges: the k smallest (length, dst, t0, t1, t2) keys,
+ * compared on the FP32 length, then the global dst index, then t lexicographically
+ * (signed, ascending). Edge e = i*k + r is the r-th edge of source i in that order.
+ *  k             1..64.
+ *  src, dst      int32 [N*k]; image int32 [N*k][3]; length float32 [N*k].
+ * Errors as for mg_cutoff_graph; MG_ERR_INVALID_ARG for k outside 1..64.
+ */
+mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                       int32_t B, int64_t N, int32_t k,
+                       int32_t* src, int32_t* dst, int32_t* image, float* length,
+                       mg_report* report, void* workspace, size_t workspace_bytes,
+                       int32_t opts, void* stream);
+
+/*
+ * Edge vectors and lengths: vec_e = (frac[dst_e] - frac[src_e] + t_e) @ lattice[b(src_e)],
+ * length_e = ||vec_e|| (the norm inside Definition def6). Computed in FP64, stored FP32.
+ *  E             number of edges (>= 0).
+ *  num_edges     int64 [1] device value or NULL: when given, only the first
+ *                min(E, *num_edges) edges are processed (capacity-sized buffers).
+ *  vec           float32 [E][3] or NULL; length float32 [E] or NULL.
+ * src/dst must index atoms of the same structure (not checked).
+ */
+mg_status mg_edge_geometry(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                           int32_t B, int64_t N, const int32_t* src, const int32_t* dst,
+                           const int32_t* image, int64_t E, const int64_t* num_edges,
+                           float* vec, float* length,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Backward of mg_edge_geometry with the edge set held fixed (abstract, Sec. 4):
+ *   g_e = grad_vec_e + grad_length_e * vec_e / length_e   (0 when length_e = 0)
+ *   grad_frac[dst_e]  += g_e lattice^T,  grad_frac[src_e] -= g_e lattice^T
+ *   grad_lattice[b]   += f_e^T g_e,      f_e = frac[dst_e] - frac[src_e] + t_e
+ *  grad_vec      float32 [E][3] or NULL; grad_length float32 [E] or NULL.
+ *  grad_frac     float32 [N][3] or NULL, overwritten (FP32 atomics: summation order varies).
+ *  grad_lattice  float32 [B][3][3] or NULL, overwritten (accumulated in FP64).
+ */
+mg_status mg_edge_geometry_backward(const float* lattices, const float* frac,
+                                    const int64_t* batch_ptr, int32_t B, int64_t N,
+                                    const int32_t* src, const int32_t* dst, const int32_t* image,
+                                    int64_t E, const int64_t* num_edges,
+                                    const float* grad_vec, const float* grad_length,
+                                    float* grad_frac, float* grad_lattice,
+                                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- launch tuning and profiling (host-side state, per process) ---------- */
+
+/* Tunable launch parameters of the sweeps; 0 in a field keeps the current value. */
+typedef struct mg_tuning {
+    int32_t cutoff_wgs_per_cu;    /* persistent workgroups per CU for the cutoff sweeps */
+    int32_t cutoff_slots;         /* destination atoms per lane per image step (1, 2 or 4) */
+    int32_t knn_wgs_per_cu;       /* persistent workgroups per CU for the KNN sweep */
+    int32_t knn_lambda_x4;        /* KNN first-search radius targets (lambda_x4/4)*k + 6 candidates */
+    int32_t reserved[4];
+} mg_tuning;
+
+/* [host] Read / replace the tuning parameters used by later calls. */
+mg_status mg_get_tuning(mg_tuning* out);
+mg_status mg_set_tuning(const mg_tuning* in);
+
+/* [host] Phase timing: when enabled, every kernel phase of the calls above is
+ * bracketed by hipEvents on the call's stream. mg_profile_read synchronises the
+ * recorded events, and for up to `max` phases writes a NUL-terminated name
+ * (32 bytes each) into names[i*32], the summed milliseconds into ms[i] and the
+ * number of launches into count[i]; it returns the number of phases and clears
+ * the record. Profiling adds event records, so leave it off outside measurements. */
+mg_status mg_profile_enable(int32_t on);
+int32_t mg_profile_read(char* names, double* ms, int64_t* count, int32_t max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MATGRAPH_H */

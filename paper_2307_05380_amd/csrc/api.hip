@@ -1,0 +1,488 @@
+// C ABI of libmatgraph (declared in include/matgraph.h): argument validation,
+// workspace carving, launch sequencing, tuning state and phase profiling.
+// No entry point allocates device memory; every kernel is enqueued on the
+// caller's stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mg_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+mg_status fail(mg_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+mg_status hip_fail(hipError_t e, const char* what) {
+    return fail(MG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+std::mutex g_mu;
+mg_tuning g_tune = {8, 2, 8, 6, {0, 0, 0, 0}};
+
+mg_tuning tuning() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_tune;
+}
+
+// ----------------------------------------------------------------- profiling
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one kernel phase with events on the launch stream when profiling is on.
+class Phase {
+  public:
+    Phase(const char* name, hipStream_t s) : s_(s) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_prof) return;
+        rec_.name = name;
+        rec_.a = take_event();
+        rec_.b = take_event();
+        if (rec_.a && rec_.b && hipEventRecord(rec_.a, s_) == hipSuccess) on_ = true;
+    }
+    ~Phase() {
+        if (!on_) return;
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (hipEventRecord(rec_.b, s_) == hipSuccess) g_recs.push_back(rec_);
+    }
+
+  private:
+    hipStream_t s_;
+    ProfRec rec_;
+    bool on_ = false;
+};
+
+template <typename F>
+hipError_t phase(const char* name, hipStream_t s, F&& f) {
+    Phase p(name, s);
+    return f();
+}
+
+// ---------------------------------------------------------------- workspace
+
+struct Carver {
+    char* base;
+    size_t used = 0;
+    template <typename T>
+    T* take(size_t count) {
+        used = mg::align_up(used, 256);
+        T* p = reinterpret_cast<T*>(base ? base + used : nullptr);
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+struct CutoffWs {
+    mg::Counters* ctr;
+    mg::StructInfo* info;
+    int64_t* item_off;
+    uint32_t* counts;
+    int64_t* offsets;
+    int64_t* bsum;
+    mg::ImageEntry* table;
+    int64_t table_cap;
+    size_t fixed;
+};
+
+CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
+    Carver c{static_cast<char*>(ws)};
+    CutoffWs w;
+    w.ctr = c.take<mg::Counters>(1);
+    w.info = c.take<mg::StructInfo>((size_t)B);
+    w.item_off = c.take<int64_t>((size_t)B + 1);
+    w.counts = c.take<uint32_t>((size_t)N);
+    w.offsets = c.take<int64_t>((size_t)N + 1);
+    w.bsum = c.take<int64_t>((size_t)mg::scan_block_count(N) + 1);
+    w.table = c.take<mg::ImageEntry>(0);
+    w.fixed = c.used;
+    w.table_cap = bytes > w.fixed ? (int64_t)((bytes - w.fixed) / sizeof(mg::ImageEntry)) : 0;
+    return w;
+}
+
+struct KnnWs {
+    mg::Counters* ctr;
+    mg::StructInfo* info;
+    int64_t* item_off;
+    int32_t* atom_struct;
+    int32_t* ext_list;
+    mg::ImageEntry* table;
+    int64_t table_cap;
+    size_t fixed;
+};
+
+KnnWs carve_knn(void* ws, size_t bytes, int B, int64_t N) {
+    Carver c{static_cast<char*>(ws)};
+    KnnWs w;
+    w.ctr = c.take<mg::Counters>(1);
+    w.info = c.take<mg::StructInfo>((size_t)B);
+    w.item_off = c.take<int64_t>((size_t)B + 1);
+    w.atom_struct = c.take<int32_t>((size_t)N);
+    w.ext_list = c.take<int32_t>((size_t)N);
+    w.table = c.take<mg::ImageEntry>(0);
+    w.fixed = c.used;
+    w.table_cap = bytes > w.fixed ? (int64_t)((bytes - w.fixed) / sizeof(mg::ImageEntry)) : 0;
+    return w;
+}
+
+struct GeomWs {
+    int32_t* atom_struct;
+    double* acc;
+    size_t fixed;
+};
+
+GeomWs carve_geom(void* ws, int B, int64_t N) {
+    Carver c{static_cast<char*>(ws)};
+    GeomWs w;
+    w.atom_struct = c.take<int32_t>((size_t)N);
+    w.acc = c.take<double>((size_t)B * 9);
+    w.fixed = mg::align_up(c.used, 256);
+    return w;
+}
+
+// Smallest float y with sqrtf(y) >= c, so that l2 < y  <=>  sqrtf(l2) < c.
+float cutoff_threshold(float c) {
+    float y = c * c;
+    if (std::sqrt(y) >= c) {
+        for (;;) {
+            const float d = std::nextafter(y, 0.0f);
+            if (d <= 0.0f || std::sqrt(d) < c) break;
+            y = d;
+        }
+    } else {
+        while (std::sqrt(y) < c) y = std::nextafter(y, INFINITY);
+    }
+    return y;
+}
+
+mg_status check_common(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
+                       int64_t N) {
+    if (B < 0) return fail(MG_ERR_INVALID_ARG, "B must be >= 0 (got %d)", B);
+    if (N < 0 || N > (int64_t)INT32_MAX) return fail(MG_ERR_INVALID_ARG, "N must be in [0, 2^31) (got %lld)", (long long)N);
+    if (B == 0 && N != 0) return fail(MG_ERR_INVALID_ARG, "N must be 0 when B == 0");
+    if (!batch_ptr) return fail(MG_ERR_INVALID_ARG, "batch_ptr is NULL");
+    if (B > 0 && !lattices) return fail(MG_ERR_INVALID_ARG, "lattices is NULL");
+    if (N > 0 && !frac) return fail(MG_ERR_INVALID_ARG, "frac is NULL");
+    return MG_OK;
+}
+
+}  // namespace
+
+// ============================================================== public ABI
+
+extern "C" {
+
+int32_t mg_abi_version(void) { return MG_ABI_VERSION; }
+
+const char* mg_last_error(void) { return g_err.c_str(); }
+
+size_t mg_cutoff_workspace_bytes(int32_t B, int64_t N, int64_t image_capacity) {
+    if (B < 0 || N < 0 || image_capacity < 0) return 0;
+    CutoffWs w = carve_cutoff(nullptr, 0, B, N);
+    return w.fixed + (size_t)image_capacity * sizeof(mg::ImageEntry);
+}
+
+size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_capacity) {
+    if (B < 0 || N < 0 || image_capacity < 0 || k < 1 || k > 64) return 0;
+    KnnWs w = carve_knn(nullptr, 0, B, N);
+    return w.fixed + (size_t)image_capacity * sizeof(mg::ImageEntry);
+}
+
+size_t mg_geometry_workspace_bytes(int32_t B, int64_t N) {
+    if (B < 0 || N < 0) return 0;
+    return carve_geom(nullptr, B, N).fixed;
+}
+
+mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                          int32_t B, int64_t N, float cutoff, int64_t capacity, int32_t* src,
+                          int32_t* dst, int32_t* image, float* length, int64_t* row_ptr,
+                          mg_report* report, void* workspace, size_t workspace_bytes, int32_t opts,
+                          void* stream) {
+    g_err.clear();
+    mg_status st = check_common(lattices, frac, batch_ptr, B, N);
+    if (st != MG_OK) return st;
+    if (!(cutoff > 0.0f) || !std::isfinite(cutoff))
+        return fail(MG_ERR_INVALID_ARG, "cutoff must be finite and > 0 (got %g)", (double)cutoff);
+    if (capacity < 0) return fail(MG_ERR_INVALID_ARG, "capacity must be >= 0");
+    if (capacity > 0 && (!src || !dst || !image || !length))
+        return fail(MG_ERR_INVALID_ARG, "src/dst/image/length must be non-NULL when capacity > 0");
+    if (!report) return fail(MG_ERR_INVALID_ARG, "report is NULL");
+    if (opts & ~(MG_OPT_CELL_LIST_OFF | MG_OPT_CELL_LIST_FORCE))
+        return fail(MG_ERR_INVALID_ARG, "unknown opts bits 0x%x", opts);
+    if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    CutoffWs w = carve_cutoff(workspace, workspace_bytes, B, N);
+    if (workspace_bytes < w.fixed)
+        return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    workspace_bytes, w.fixed);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const mg_tuning tu = tuning();
+    const float c2 = cutoff_threshold(cutoff);
+    int64_t* offs = row_ptr ? row_ptr : w.offsets;
+    const int grid = mg::device_cu_count() * (tu.cutoff_wgs_per_cu > 0 ? tu.cutoff_wgs_per_cu : 8);
+    hipError_t e;
+    if ((e = mg::launch_zero_report(report, w.ctr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
+    if ((e = phase("cutoff.bounds", s, [&] {
+             return mg::launch_bounds(lattices, batch_ptr, frac, B, N, cutoff, 0, 0.f, w.info, w.ctr,
+                                      report, 0, s);
+         })) != hipSuccess)
+        return hip_fail(e, "bounds");
+    if ((e = phase("cutoff.plan", s, [&] {
+             return mg::launch_struct_scan(B, w.info, w.item_off, w.ctr, report, w.table_cap, s);
+         })) != hipSuccess)
+        return hip_fail(e, "plan");
+    if ((e = phase("cutoff.images", s, [&] { return mg::launch_images(B, w.info, w.table, w.table_cap, s); })) !=
+        hipSuccess)
+        return hip_fail(e, "images");
+    if ((e = phase("cutoff.count", s, [&] {
+             return mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.table, frac, c2, w.counts, offs,
+                                            capacity, src, dst, image, length, w.ctr, report, grid,
+                                            tu.cutoff_slots, s);
+         })) != hipSuccess)
+        return hip_fail(e, "count");
+    if ((e = phase("cutoff.scan", s, [&] {
+             return mg::launch_scan_counts(w.counts, N, offs, w.bsum, capacity, report, s);
+         })) != hipSuccess)
+        return hip_fail(e, "scan");
+    if ((e = phase("cutoff.fill", s, [&] {
+             return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.table, frac, c2, w.counts, offs,
+                                            capacity, src, dst, image, length, w.ctr, report, grid,
+                                            tu.cutoff_slots, s);
+         })) != hipSuccess)
+        return hip_fail(e, "fill");
+    return MG_OK;
+}
+
+mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
+                       int64_t N, int32_t k, int32_t* src, int32_t* dst, int32_t* image,
+                       float* length, mg_report* report, void* workspace, size_t workspace_bytes,
+                       int32_t opts, void* stream) {
+    g_err.clear();
+    mg_status st = check_common(lattices, frac, batch_ptr, B, N);
+    if (st != MG_OK) return st;
+    if (k < 1 || k > 64) return fail(MG_ERR_INVALID_ARG, "k must be in 1..64 (got %d)", k);
+    if ((int64_t)N * k > (int64_t)INT32_MAX * 2)
+        return fail(MG_ERR_UNSUPPORTED, "N*k = %lld is too large", (long long)N * k);
+    if (N > 0 && (!src || !dst || !image || !length))
+        return fail(MG_ERR_INVALID_ARG, "src/dst/image/length must be non-NULL");
+    if (!report) return fail(MG_ERR_INVALID_ARG, "report is NULL");
+    if (opts & ~(MG_OPT_CELL_LIST_OFF | MG_OPT_CELL_LIST_FORCE))
+        return fail(MG_ERR_INVALID_ARG, "unknown opts bits 0x%x", opts);
+    if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    KnnWs w = carve_knn(workspace, workspace_bytes, B, N);
+    if (workspace_bytes < w.fixed)
+        return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    workspace_bytes, w.fixed);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const mg_tuning tu = tuning();
+    const float lambda = (tu.knn_lambda_x4 > 0 ? tu.knn_lambda_x4 : 6) / 4.0f;
+    const int grid = mg::device_cu_count() * (tu.knn_wgs_per_cu > 0 ? tu.knn_wgs_per_cu : 8);
+    hipError_t e;
+    if ((e = mg::launch_zero_report(report, w.ctr, N * (int64_t)k, s)) != hipSuccess) return hip_fail(e, "zero");
+    if ((e = phase("knn.bounds", s, [&] {
+             return mg::launch_bounds(lattices, batch_ptr, frac, B, N, 0.f, k, lambda, w.info, w.ctr,
+                                      report, 1, s);
+         })) != hipSuccess)
+        return hip_fail(e, "bounds");
+    if ((e = phase("knn.plan", s, [&] {
+             return mg::launch_struct_scan(B, w.info, w.item_off, w.ctr, report, w.table_cap, s);
+         })) != hipSuccess)
+        return hip_fail(e, "plan");
+    if ((e = phase("knn.images", s, [&] { return mg::launch_images(B, w.info, w.table, w.table_cap, s); })) !=
+        hipSuccess)
+        return hip_fail(e, "images");
+    if ((e = phase("knn.atoms", s, [&] { return mg::launch_atom_struct(batch_ptr, B, N, w.atom_struct, s); })) !=
+        hipSuccess)
+        return hip_fail(e, "atom map");
+    if ((e = phase("knn.select", s, [&] {
+             return mg::launch_knn(B, N, k, w.info, w.table, frac, w.atom_struct, src, dst, image, length,
+                                   w.ext_list, w.ctr, report, grid, s);
+         })) != hipSuccess)
+        return hip_fail(e, "knn");
+    if ((e = phase("knn.extended", s, [&] {
+             return mg::launch_knn_extended(B, N, k, w.info, frac, w.atom_struct, src, dst, image, length,
+                                            w.ext_list, w.ctr, report, mg::device_cu_count() * 2, s);
+         })) != hipSuccess)
+        return hip_fail(e, "knn extended");
+    return MG_OK;
+}
+
+static mg_status check_edges(const int32_t* src, const int32_t* dst, const int32_t* image, int64_t E) {
+    if (E < 0) return fail(MG_ERR_INVALID_ARG, "E must be >= 0");
+    if (E > 0 && (!src || !dst || !image)) return fail(MG_ERR_INVALID_ARG, "src/dst/image is NULL");
+    return MG_OK;
+}
+
+mg_status mg_edge_geometry(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                           int32_t B, int64_t N, const int32_t* src, const int32_t* dst,
+                           const int32_t* image, int64_t E, const int64_t* num_edges, float* vec,
+                           float* length, void* workspace, size_t workspace_bytes, void* stream) {
+    g_err.clear();
+    mg_status st = check_common(lattices, frac, batch_ptr, B, N);
+    if (st != MG_OK) return st;
+    if ((st = check_edges(src, dst, image, E)) != MG_OK) return st;
+    if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    GeomWs w = carve_geom(workspace, B, N);
+    if (workspace_bytes < w.fixed)
+        return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    workspace_bytes, w.fixed);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = phase("geometry.atoms", s, [&] { return mg::launch_atom_struct(batch_ptr, B, N, w.atom_struct, s); })) !=
+        hipSuccess)
+        return hip_fail(e, "atom map");
+    if ((e = phase("geometry.fwd", s, [&] {
+             return mg::launch_geometry_fwd(lattices, frac, w.atom_struct, N, src, dst, image, E, num_edges,
+                                            vec, length, s);
+         })) != hipSuccess)
+        return hip_fail(e, "geometry");
+    return MG_OK;
+}
+
+mg_status mg_edge_geometry_backward(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                                    int32_t B, int64_t N, const int32_t* src, const int32_t* dst,
+                                    const int32_t* image, int64_t E, const int64_t* num_edges,
+                                    const float* grad_vec, const float* grad_length, float* grad_frac,
+                                    float* grad_lattice, void* workspace, size_t workspace_bytes,
+                                    void* stream) {
+    g_err.clear();
+    mg_status st = check_common(lattices, frac, batch_ptr, B, N);
+    if (st != MG_OK) return st;
+    if ((st = check_edges(src, dst, image, E)) != MG_OK) return st;
+    if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    GeomWs w = carve_geom(workspace, B, N);
+    if (workspace_bytes < w.fixed)
+        return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    workspace_bytes, w.fixed);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = phase("geometry.atoms", s, [&] { return mg::launch_atom_struct(batch_ptr, B, N, w.atom_struct, s); })) !=
+        hipSuccess)
+        return hip_fail(e, "atom map");
+    if ((e = phase("geometry.bwd", s, [&] {
+             return mg::launch_geometry_bwd(lattices, frac, w.atom_struct, B, N, src, dst, image, E, num_edges,
+                                            grad_vec, grad_length, grad_frac, grad_lattice, w.acc, s);
+         })) != hipSuccess)
+        return hip_fail(e, "geometry backward");
+    return MG_OK;
+}
+
+mg_status mg_get_tuning(mg_tuning* out) {
+    if (!out) return fail(MG_ERR_INVALID_ARG, "out is NULL");
+    *out = tuning();
+    return MG_OK;
+}
+
+mg_status mg_set_tuning(const mg_tuning* in) {
+    if (!in) return fail(MG_ERR_INVALID_ARG, "in is NULL");
+    if (in->cutoff_slots != 0 && in->cutoff_slots != 1 && in->cutoff_slots != 2 && in->cutoff_slots != 4)
+        return fail(MG_ERR_INVALID_ARG, "cutoff_slots must be 1, 2 or 4");
+    if (in->cutoff_wgs_per_cu < 0 || in->cutoff_wgs_per_cu > 64 || in->knn_wgs_per_cu < 0 ||
+        in->knn_wgs_per_cu > 64)
+        return fail(MG_ERR_INVALID_ARG, "workgroups per CU must be in 0..64");
+    if (in->knn_lambda_x4 < 0 || in->knn_lambda_x4 > 64)
+        return fail(MG_ERR_INVALID_ARG, "knn_lambda_x4 must be in 0..64");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (in->cutoff_wgs_per_cu) g_tune.cutoff_wgs_per_cu = in->cutoff_wgs_per_cu;
+    if (in->cutoff_slots) g_tune.cutoff_slots = in->cutoff_slots;
+    if (in->knn_wgs_per_cu) g_tune.knn_wgs_per_cu = in->knn_wgs_per_cu;
+    if (in->knn_lambda_x4) g_tune.knn_lambda_x4 = in->knn_lambda_x4;
+    return MG_OK;
+}
+
+mg_status mg_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof = on != 0;
+    return MG_OK;
+}
+
+int32_t mg_profile_read(char* names, double* ms, int64_t* count, int32_t max) {
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        recs.swap(g_recs);
+    }
+    std::vector<std::string> nm;
+    std::vector<double> tot;
+    std::vector<int64_t> cnt;
+    for (auto& r : recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            size_t q = 0;
+            while (q < nm.size() && nm[q] != r.name) ++q;
+            if (q == nm.size()) {
+                nm.push_back(r.name);
+                tot.push_back(0.0);
+                cnt.push_back(0);
+            }
+            tot[q] += t;
+            cnt[q] += 1;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& r : recs) {
+            g_pool.push_back(r.a);
+            g_pool.push_back(r.b);
+        }
+    }
+    const int32_t m = (int32_t)nm.size();
+    for (int32_t q = 0; q < m && q < max; ++q) {
+        if (names) {
+            std::strncpy(names + 32 * q, nm[q].c_str(), 31);
+            names[32 * q + 31] = 0;
+        }
+        if (ms) ms[q] = tot[q];
+        if (count) count[q] = cnt[q];
+    }
+    return m;
+}
+
+}  // extern "C"
+
+namespace mg {
+
+int device_cu_count() {
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+        cache[dev] = cu;
+    }
+    return cache[dev];
+}
+
+}  // namespace mg

@@ -1,0 +1,418 @@
+// k-nearest-neighbour multigraph (Sec. 1; Sec. 2.2, Algorithms 1 and 2).
+//
+// One wave per source atom. The candidates (j, t) of the source are streamed
+// in (j, t-lexicographic) order; a candidate survives when its FP32 length is
+// below the current threshold and is appended to a per-wave LDS buffer: the
+// paper's ordered stack ("concatenate new data, sort by distance, keep the
+// k nearest"), kept on chip. When the buffer is full it is sorted (bitonic,
+// in registers across the 64 lanes), cut to the k smallest keys and the
+// threshold drops to the k-th length, so the buffer only ever holds plausible
+// neighbours. Keys are (length bits << 32 | candidate ordinal); the ordinal
+// j * I + image_index follows (dst, t) order because image tables are built in
+// lexicographic t order, which gives the tie order (length, dst, t).
+//
+// Search area (Algorithm 1). The first pass enumerates the image table built
+// for a radius R0 from the structure's density (about lambda * k candidates
+// expected). A source whose stack holds at least k keys is exact: every
+// candidate shorter than R0 lies in the table. Sources with fewer than k
+// survivors are queued for the extended pass, which enumerates the full image
+// box of radius 2 R0, 4 R0, ... (images computed on the fly in FP64) until k
+// are found inside the radius - the expanding search of Algorithm 1 with the
+// termination test "k-th distance inside the evaluated area".
+//
+// Every wave-level decision (loop bounds, stack size, threshold, the sort
+// branch) is taken on values made explicitly uniform with readfirstlane, every
+// helper that shuffles across lanes is force-inlined (no device calls), work is
+// pulled with wave_ticket (the first active lane takes the ticket, so every
+// iteration advances the queue) and the extended search is capped at
+// KNN_MAX_ATTEMPTS radius doublings: every wave reaches its exit.
+#include "mg_internal.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int KNN_WAVES = 4;
+constexpr int KNN_JC = 256;    // destinations staged in LDS per chunk
+constexpr int KNN_CAP = 256;   // ordered-stack capacity per wave (keys)
+constexpr int KNN_MAX_ATTEMPTS = 24;
+
+struct KnnShared {
+    float4 p[KNN_WAVES][KNN_JC];
+    uint64_t buf[KNN_WAVES][KNN_CAP];
+};
+
+__device__ __forceinline__ int ufirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float ufirstf(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of 64*M keys held as v[r] of lane l = element r*64 + l.
+template <int M>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&v)[M], int lane) {
+#pragma unroll
+    for (int size = 2; size <= WAVE * M; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= WAVE) {
+                const int rs = stride / WAVE;
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    if ((r & rs) == 0) {
+                        const int p = r | rs;
+                        const bool asc = (((r * WAVE) & size) == 0);
+                        const uint64_t a = v[r], b = v[p];
+                        const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+                        v[r] = asc ? lo : hi;
+                        v[p] = asc ? hi : lo;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    const uint64_t o = shfl_xor_u64(v[r], stride);
+                    const bool asc = (((r * WAVE + lane) & size) == 0);
+                    const bool lower = (lane & stride) == 0;
+                    const bool take_min = (lower == asc);
+                    const uint64_t mn = v[r] < o ? v[r] : o, mx = v[r] < o ? o : v[r];
+                    v[r] = take_min ? mn : mx;
+                }
+            }
+        }
+    }
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t sorted_rank(const uint64_t* buf, int cnt, int lane) {
+    uint64_t v[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int e = r * WAVE + lane;
+        v[r] = e < cnt ? buf[e] : ~0ull;
+    }
+    bitonic_sort<M>(v, lane);
+    return v[0];
+}
+
+// Key of rank `lane` among buf[0..cnt) (cnt uniform, <= KNN_CAP).
+__device__ __forceinline__ uint64_t sorted_head(const uint64_t* buf, int cnt, int lane) {
+    if (cnt <= WAVE) return sorted_rank<1>(buf, cnt, lane);
+    if (cnt <= 2 * WAVE) return sorted_rank<2>(buf, cnt, lane);
+    return sorted_rank<4>(buf, cnt, lane);
+}
+
+__device__ __forceinline__ float key_len(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32)); }
+
+__device__ __forceinline__ float thr_from_len(float l) { return l * l * (1.0f + 3e-6f) + 1e-30f; }
+
+__device__ __forceinline__ void write_invalid(int64_t i, int k, int lane, int32_t* __restrict__ src,
+                                              int32_t* __restrict__ dst, int32_t* __restrict__ image,
+                                              float* __restrict__ length) {
+    if (lane < k) {
+        const int64_t e = i * k + lane;
+        src[e] = (int32_t)i;
+        dst[e] = -1;
+        image[3 * e] = image[3 * e + 1] = image[3 * e + 2] = 0;
+        length[e] = __builtin_inff();
+    }
+}
+
+// Image set of one search: either a structure's table (lexicographic) or the
+// full box [-n0..n0] x [-n1..n1] x [-n2..n2] enumerated in the same order.
+struct ImageSet {
+    const ImageEntry* tab;   // table, or nullptr for the box
+    uint32_t I;              // number of images
+    int zidx;                // index of t = 0
+    int n0, n1, n2;          // box half ranges (box only)
+};
+
+__device__ __forceinline__ void image_t(const ImageSet& S, uint32_t img, int& t0, int& t1, int& t2) {
+    if (S.tab) {
+        const int32_t tpk = S.tab[img].tpk;
+        t0 = unpack_t0(tpk);
+        t1 = unpack_t1(tpk);
+        t2 = unpack_t2(tpk);
+    } else {
+        const uint32_t w1 = 2 * S.n1 + 1, w2 = 2 * S.n2 + 1;
+        t2 = (int)(img % w2) - S.n2;
+        const uint32_t rr = img / w2;
+        t1 = (int)(rr % w1) - S.n1;
+        t0 = (int)(rr / w1) - S.n0;
+    }
+}
+
+// Stream every candidate (j, t) of source il through the ordered stack with the
+// initial threshold tau2. Returns the uniform number of keys left in buf.
+__device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int n, int il, int64_t atom0,
+                                       const double* L, double xi0, double xi1, double xi2,
+                                       const float* __restrict__ frac, float4* P, uint64_t* buf, int lane) {
+    int cnt = 0;
+    const uint32_t I = S.I;
+    const float invI = 1.0f / (float)I;
+    for (int jc0 = 0; jc0 < n; jc0 += KNN_JC) {
+        const int nj = min(KNN_JC, n - jc0);
+        wave_lds_sync();
+        for (int jj = lane; jj < nj; jj += WAVE) {
+            const int64_t aj = atom0 + jc0 + jj;
+            double d0 = (double)frac[3 * aj] - xi0;
+            double d1 = (double)frac[3 * aj + 1] - xi1;
+            double d2 = (double)frac[3 * aj + 2] - xi2;
+            d0 -= rint(d0);
+            d1 -= rint(d1);
+            d2 -= rint(d2);
+            P[jj] = make_float4((float)(d0 * L[0] + d1 * L[3] + d2 * L[6]),
+                                (float)(d0 * L[1] + d1 * L[4] + d2 * L[7]),
+                                (float)(d0 * L[2] + d1 * L[5] + d2 * L[8]),
+                                __int_as_float(jc0 + jj == il ? 1 : 0));
+        }
+        wave_lds_sync();
+        const uint32_t nq = (uint32_t)nj * I;
+        for (uint32_t b0 = 0; b0 < nq; b0 += WAVE) {
+            const uint32_t ql = b0 + (uint32_t)lane;
+            const bool valid = ql < nq;
+            uint32_t jl = (uint32_t)((float)ql * invI);
+            if (jl * I > ql) --jl;
+            if ((jl + 1) * I <= ql) ++jl;
+            const uint32_t img = ql - jl * I;
+            bool pass = false;
+            float l2 = 0.0f;
+            if (valid) {
+                const float4 pp = P[jl];
+                float sx, sy, sz;
+                if (S.tab) {
+                    const ImageEntry e = S.tab[img];
+                    sx = e.sx;
+                    sy = e.sy;
+                    sz = e.sz;
+                } else {
+                    int t0, t1, t2;
+                    image_t(S, img, t0, t1, t2);
+                    sx = (float)(t0 * L[0] + t1 * L[3] + t2 * L[6]);
+                    sy = (float)(t0 * L[1] + t1 * L[4] + t2 * L[7]);
+                    sz = (float)(t0 * L[2] + t1 * L[5] + t2 * L[8]);
+                }
+                const float dx = pp.x + sx, dy = pp.y + sy, dz = pp.z + sz;
+                l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                pass = l2 < tau2 && !(__float_as_int(pp.w) != 0 && (int)img == S.zidx);
+            }
+            uint64_t m = ballot(pass);
+            int c = ufirst(__popcll(m));
+            if (c == 0) continue;
+            if (cnt + c > KNN_CAP) {
+                // the stack is full: keep the k smallest keys, lower the threshold
+                wave_lds_sync();
+                const uint64_t v0 = sorted_rank<KNN_CAP / WAVE>(buf, cnt, lane);
+                wave_lds_sync();
+                if (lane < k) buf[lane] = v0;
+                const uint64_t kth = readlane_u64(v0, k - 1);
+                tau2 = ufirstf(fminf(tau2, thr_from_len(key_len(kth))));
+                cnt = k;
+                pass = pass && l2 < tau2;
+                m = ballot(pass);
+                c = ufirst(__popcll(m));
+                wave_lds_sync();
+            }
+            if (pass)
+                buf[cnt + (int)mbcnt(m)] =
+                    ((uint64_t)__float_as_uint(sqrtf(l2)) << 32) | (uint64_t)((uint32_t)(jc0 + jl) * I + img);
+            cnt = ufirst(cnt + c);
+        }
+    }
+    wave_lds_sync();
+    return cnt;
+}
+
+// Sort the stack and write the k edges of source i (requires cnt >= k).
+__device__ __forceinline__ void emit(const ImageSet& S, int cnt, int k, int64_t i, int64_t atom0,
+                                     double xi0, double xi1, double xi2, const float* __restrict__ frac,
+                                     const uint64_t* buf, int lane, int32_t* __restrict__ src,
+                                     int32_t* __restrict__ dst, int32_t* __restrict__ image,
+                                     float* __restrict__ length) {
+    const uint64_t key = sorted_head(buf, cnt, lane);
+    if (lane < k) {
+        const uint32_t qv = (uint32_t)key;
+        const uint32_t j = qv / S.I;
+        const uint32_t img = qv - j * S.I;
+        int t0, t1, t2;
+        image_t(S, img, t0, t1, t2);
+        const int64_t aj = atom0 + j;
+        const double d0 = (double)frac[3 * aj] - xi0, d1 = (double)frac[3 * aj + 1] - xi1,
+                     d2 = (double)frac[3 * aj + 2] - xi2;
+        const int64_t e = i * k + lane;
+        src[e] = (int32_t)i;
+        dst[e] = (int32_t)aj;
+        image[3 * e] = t0 - (int)rint(d0);
+        image[3 * e + 1] = t1 - (int)rint(d1);
+        image[3 * e + 2] = t2 - (int)rint(d2);
+        length[e] = key_len(key);
+    }
+}
+
+}  // namespace
+
+// First pass: every source, with its structure's image table (radius R0).
+__global__ __launch_bounds__(256) void k_knn_first(int64_t N, int k, const StructInfo* __restrict__ info,
+                                                   const ImageEntry* __restrict__ table,
+                                                   const float* __restrict__ frac,
+                                                   const int32_t* __restrict__ atom_struct,
+                                                   int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                                                   int32_t* __restrict__ image, float* __restrict__ length,
+                                                   int32_t* __restrict__ ext_list, Counters* __restrict__ ctr,
+                                                   mg_report* __restrict__ rep) {
+    __shared__ KnnShared sh;
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    float4* P = sh.p[wv];
+    uint64_t* buf = sh.buf[wv];
+    const uint32_t bad = MG_FLAG_SINGULAR | MG_FLAG_NONFINITE | MG_FLAG_RANGE | MG_FLAG_IMAGES;
+    for (;;) {
+        const int64_t i = (int64_t)wave_ticket(&ctr->ticket[2]);
+        if (i >= N) break;
+        const int s = ufirst(atom_struct[i]);
+        const StructInfo* si = info + s;
+        const int n = si->n;
+        const int64_t atom0 = si->atom0;
+        const int il = (int)(i - atom0);
+        const bool ok = si->box != 0 && si->images > 0 && si->zero_img >= 0 && (si->flags & bad) == 0;
+        if (!ok) {
+            write_invalid(i, k, lane, src, dst, image, length);
+            continue;
+        }
+        double L[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) L[r] = si->L[r];
+        const double xi0 = frac[3 * i], xi1 = frac[3 * i + 1], xi2 = frac[3 * i + 2];
+        ImageSet S;
+        S.tab = table + si->img_off;
+        S.I = (uint32_t)si->images;
+        S.zidx = si->zero_img;
+        S.n0 = S.n1 = S.n2 = 0;
+        if ((uint64_t)n * S.I >= 4294967296ull) {
+            if (lane == 0) atomicOr(&rep->flags, (uint32_t)MG_FLAG_RANGE);
+            write_invalid(i, k, lane, src, dst, image, length);
+            continue;
+        }
+        const double R = (double)si->Rs;
+        const float tau2 = (float)(R * R) * (1.0f + 3e-6f);
+        const int cnt = collect(S, tau2, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
+        if (cnt >= k) {
+            emit(S, cnt, k, i, atom0, xi0, xi1, xi2, frac, buf, lane, src, dst, image, length);
+        } else if (lane == 0) {
+            const uint32_t pos = atomicAdd(&ctr->knn2_count, 1u);
+            ext_list[pos] = (int32_t)i;
+            atomicAdd((unsigned long long*)&rep->knn_extended, 1ull);
+            atomicOr(&rep->flags, (uint32_t)MG_FLAG_KNN_EXTENDED);
+        }
+    }
+}
+
+// Extended pass: the queued sources, full image boxes of radius 2 R0, 4 R0, ...
+__global__ __launch_bounds__(256) void k_knn_extended(int k, const StructInfo* __restrict__ info,
+                                                      const float* __restrict__ frac,
+                                                      const int32_t* __restrict__ atom_struct,
+                                                      int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                                                      int32_t* __restrict__ image, float* __restrict__ length,
+                                                      const int32_t* __restrict__ ext_list,
+                                                      Counters* __restrict__ ctr, mg_report* __restrict__ rep) {
+    __shared__ KnnShared sh;
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    float4* P = sh.p[wv];
+    uint64_t* buf = sh.buf[wv];
+    const uint32_t total = (uint32_t)ufirst((int)ctr->knn2_count);
+    for (;;) {
+        const uint32_t q = wave_ticket(&ctr->ticket[3]);
+        if (q >= total) break;
+        const int64_t i = (int64_t)ufirst(ext_list[q]);
+        const int s = ufirst(atom_struct[i]);
+        const StructInfo* si = info + s;
+        const int n = si->n;
+        const int64_t atom0 = si->atom0;
+        const int il = (int)(i - atom0);
+        double L[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) L[r] = si->L[r];
+        const double xi0 = frac[3 * i], xi1 = frac[3 * i + 1], xi2 = frac[3 * i + 2];
+        // plane spacings: r_a = |a_{a+1} x a_{a+2}| / |det|
+        double c[3][3], lsum = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double* u = L + 3 * ((a + 1) % 3);
+            const double* w = L + 3 * ((a + 2) % 3);
+            c[a][0] = u[1] * w[2] - u[2] * w[1];
+            c[a][1] = u[2] * w[0] - u[0] * w[2];
+            c[a][2] = u[0] * w[1] - u[1] * w[0];
+            lsum += sqrt(L[3 * a] * L[3 * a] + L[3 * a + 1] * L[3 * a + 1] + L[3 * a + 2] * L[3 * a + 2]);
+        }
+        const double det = fabs(L[0] * c[0][0] + L[1] * c[0][1] + L[2] * c[0][2]);
+        double rk[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) rk[a] = sqrt(c[a][0] * c[a][0] + c[a][1] * c[a][1] + c[a][2] * c[a][2]) / det;
+        double R = (double)si->Rs;
+        int done = 0;
+        for (int attempt = 0; attempt < KNN_MAX_ATTEMPTS && !done; ++attempt) {
+            R *= 2.0;
+            const double Rb = R * (1.0 + 1e-6) + 1e-3 + 1e-5 * lsum;
+            const double h0 = floor(Rb * rk[0] + 0.5), h1 = floor(Rb * rk[1] + 0.5), h2 = floor(Rb * rk[2] + 0.5);
+            const double W = (2 * h0 + 1) * (2 * h1 + 1) * (2 * h2 + 1);
+            const int fits = ufirst((h0 <= TMAX && h1 <= TMAX && h2 <= TMAX && (double)n * W < 4294967296.0) ? 1 : 0);
+            if (!fits) {
+                done = 2;
+                break;
+            }
+            ImageSet S;
+            S.tab = nullptr;
+            S.n0 = ufirst((int)h0);
+            S.n1 = ufirst((int)h1);
+            S.n2 = ufirst((int)h2);
+            S.I = (uint32_t)((2 * S.n0 + 1) * (2 * S.n1 + 1) * (2 * S.n2 + 1));
+            S.zidx = (S.n0 * (2 * S.n1 + 1) + S.n1) * (2 * S.n2 + 1) + S.n2;
+            const float tau2 = ufirstf((float)(R * R) * (1.0f + 3e-6f));
+            const int cnt = collect(S, tau2, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
+            if (cnt >= k) {
+                emit(S, cnt, k, i, atom0, xi0, xi1, xi2, frac, buf, lane, src, dst, image, length);
+                done = 1;
+            }
+        }
+        if (done != 1) {
+            if (lane == 0) atomicOr(&rep->flags, (uint32_t)MG_FLAG_RANGE);
+            write_invalid(i, k, lane, src, dst, image, length);
+        }
+    }
+}
+
+hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const ImageEntry* table,
+                      const float* frac, const int32_t* atom_struct, int32_t* src, int32_t* dst,
+                      int32_t* image, float* length, int32_t* ext_list, Counters* ctr,
+                      mg_report* report, int grid, hipStream_t s) {
+    (void)B;
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_knn_first, dim3(grid), dim3(256), 0, s, N, k, info, table, frac, atom_struct, src,
+                       dst, image, length, ext_list, ctr, report);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_extended(int B, int64_t N, int k, const StructInfo* info, const float* frac,
+                               const int32_t* atom_struct, int32_t* src, int32_t* dst,
+                               int32_t* image, float* length, const int32_t* ext_list,
+                               Counters* ctr, mg_report* report, int grid, hipStream_t s) {
+    (void)B;
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_knn_extended, dim3(grid), dim3(256), 0, s, k, info, frac, atom_struct, src, dst,
+                       image, length, ext_list, ctr, report);
+    return hipGetLastError();
+}
+
+}  // namespace mg

@@ -1,0 +1,193 @@
+// Internal declarations shared by the HIP translation units of libmatgraph.
+// Not part of the public ABI (include/matgraph.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/matgraph.h"
+
+namespace mg {
+
+constexpr int WAVE = 64;
+constexpr int TBITS = 10;                 // bits per packed image component
+constexpr int TMAX = (1 << (TBITS - 1)) - 1;   // |t_k| <= 511
+constexpr int TBIAS = 1 << (TBITS - 1);
+
+// One lattice translation of a structure's image table: the FP64 product t.L
+// rounded once to FP32, and t packed as three biased 10-bit fields (t0 high).
+struct alignas(16) ImageEntry {
+    float sx, sy, sz;
+    int32_t tpk;
+};
+
+__host__ __device__ inline int32_t pack_t(int t0, int t1, int t2) {
+    return ((t0 + TBIAS) << (2 * TBITS)) | ((t1 + TBIAS) << TBITS) | (t2 + TBIAS);
+}
+__host__ __device__ inline int unpack_t0(int32_t p) { return ((p >> (2 * TBITS)) & ((1 << TBITS) - 1)) - TBIAS; }
+__host__ __device__ inline int unpack_t1(int32_t p) { return ((p >> TBITS) & ((1 << TBITS) - 1)) - TBIAS; }
+__host__ __device__ inline int unpack_t2(int32_t p) { return (p & ((1 << TBITS) - 1)) - TBIAS; }
+
+// Per-structure plan, written by the bounds kernel (FP64).
+struct alignas(16) StructInfo {
+    double L[9];        // lattice rows, FP64 copy of the input
+    int64_t atom0;      // first atom
+    int64_t box;        // images in the box prod(2 nk + 1); 0 when the structure is skipped
+    int64_t img_off;    // first entry in the image table
+    int32_t n;          // atoms
+    int32_t nk[3];      // box half ranges
+    int32_t images;     // entries kept in the table
+    int32_t zero_img;   // table index of t = 0 (-1 if absent)
+    int32_t G;          // sources per work item
+    int32_t groups;     // work items
+    float R;            // radius the table was built for, with rounding margin (Angstrom)
+    float Rs;           // search radius before the margin (Angstrom)
+    uint32_t flags;     // MG_FLAG_* of this structure
+    int32_t pad;
+};
+
+// Scratch counters at the head of every workspace.
+struct alignas(64) Counters {
+    uint32_t ticket[8];        // work-queue tickets of persistent kernels
+    uint32_t knn2_count;       // sources queued for the extended KNN search
+    uint32_t pad[7];
+    int64_t total_box;         // sum of box sizes (image entries needed)
+    int64_t total_items;       // work items of the sweep
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------ device helpers
+
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Number of set bits of `m` in lanes below the calling lane.
+__device__ inline uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+template <typename T>
+__device__ inline T uniform(T v) {
+    return (T)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ inline int64_t uniform64(int64_t v) {
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Inclusive wave scan (64 lanes) with DPP row shifts and row broadcasts.
+__device__ inline int wave_incl_scan_i32(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+// Next item of a work queue for the calling wave: the first active lane (always
+// active, whatever the exec mask) takes one ticket and broadcasts it, so every
+// call advances the queue. Returns a wave-uniform value.
+__device__ __forceinline__ uint32_t wave_ticket(uint32_t* counter) {
+    const uint64_t ex = __builtin_amdgcn_read_exec();
+    const int leader = __builtin_ctzll(ex);
+    uint32_t t = 0;
+    if (lane_id() == leader) t = atomicAdd(counter, 1u);
+    return (uint32_t)__builtin_amdgcn_readlane((int)t, leader);
+}
+
+// Orders this wave's LDS writes before its later LDS reads (lanes exchange data
+// through LDS without a workgroup barrier).
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int64_t wave_incl_scan_i64(int64_t v) {
+    // two 32-bit halves would need carries; use shuffles for 64-bit values
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int64_t u = __shfl_up(v, d, WAVE);
+        if (lane_id() >= d) v += u;
+    }
+    return v;
+}
+
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+__device__ inline double wave_sum_f64(double v) {
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+__device__ inline float wave_sum_f32(float v) {
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// Structure owning atom `a`: largest b with ptr[b] <= a (ptr non-decreasing, B+1 entries).
+__device__ inline int structure_of(const int64_t* __restrict__ ptr, int B, int64_t a) {
+    int lo = 0, hi = B;   // invariant: ptr[lo] <= a < ptr[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (ptr[mid] <= a) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace mg
+
+// ------------------------------------------------------- host-side launchers
+// Each returns hipSuccess or the launch error. All are asynchronous on `stream`.
+namespace mg {
+
+hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
+                         int64_t N, float radius, int knn_k, float knn_lambda, StructInfo* info,
+                         Counters* ctr, mg_report* report, int mode, hipStream_t s);
+hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, Counters* ctr,
+                              mg_report* report, int64_t image_capacity, hipStream_t s);
+hipError_t launch_images(int B, StructInfo* info, ImageEntry* table, int64_t image_capacity,
+                         hipStream_t s);
+hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
+                               const ImageEntry* table, const float* frac, float c2thr,
+                               uint32_t* counts, const int64_t* offsets, int64_t capacity,
+                               int32_t* src, int32_t* dst, int32_t* image, float* length,
+                               Counters* ctr, mg_report* report, int grid, int slots, hipStream_t s);
+hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offsets, int64_t* bsum,
+                              int64_t capacity, mg_report* report, hipStream_t s);
+hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const ImageEntry* table,
+                      const float* frac, const int32_t* atom_struct, int32_t* src, int32_t* dst,
+                      int32_t* image, float* length, int32_t* ext_list, Counters* ctr,
+                      mg_report* report, int grid, hipStream_t s);
+hipError_t launch_knn_extended(int B, int64_t N, int k, const StructInfo* info, const float* frac,
+                               const int32_t* atom_struct, int32_t* src, int32_t* dst,
+                               int32_t* image, float* length, const int32_t* ext_list,
+                               Counters* ctr, mg_report* report, int grid, hipStream_t s);
+hipError_t launch_atom_struct(const int64_t* batch_ptr, int B, int64_t N, int32_t* atom_struct,
+                              hipStream_t s);
+hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const int32_t* atom_struct,
+                               int64_t N, const int32_t* src, const int32_t* dst, const int32_t* image,
+                               int64_t E, const int64_t* num_edges, float* vec, float* length,
+                               hipStream_t s);
+hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const int32_t* atom_struct,
+                               int B, int64_t N, const int32_t* src, const int32_t* dst,
+                               const int32_t* image, int64_t E, const int64_t* num_edges,
+                               const float* grad_vec, const float* grad_length, float* grad_frac,
+                               float* grad_lattice, double* acc, hipStream_t s);
+hipError_t launch_zero_report(mg_report* report, Counters* ctr, int64_t num_edges, hipStream_t s);
+int64_t scan_block_count(int64_t N);
+
+int device_cu_count();
+
+}  // namespace mg

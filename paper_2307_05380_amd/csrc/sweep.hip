@@ -1,0 +1,304 @@
+// Pair x image distance sweep of the cutoff multigraph (Definition def6 with a
+// constant cutoff) and its count / fill compaction.
+//
+// Work item = (structure, group of source atoms). Lanes hold (source,
+// destination) pairs; the image loop is uniform over the wave, so every image
+// (an FP64-derived shift s_t = t.L rounded once to FP32) is read with scalar
+// loads and shared by all lanes. The per-pair part p_ij = wrap(x_j - x_i).L is
+// computed once per item in FP64 and rounded to FP32; the inner step is
+// d = p_ij + s_t, l^2 = d.d and the strict test l < c (as l^2 < c2thr, the
+// smallest float whose correctly rounded square root reaches c).
+//
+// The count pass writes the number of edges of every source; after the scan
+// the fill pass repeats the sweep and writes every hit at
+// offsets[src] + (rank of the hit inside the source), ranked with a wave
+// ballot and mbcnt. Both passes enumerate candidates in the same order, so
+// the edges of a source are contiguous and their order is deterministic.
+// This replaces the ordered stack's concatenate / sort / filter (Sec. 2.2,
+// Algorithm 2) for the cutoff graph: nothing is sorted, the output is grouped
+// by source as Algorithm 2's stable sort by source index would group it.
+#include "mg_internal.h"
+
+namespace mg {
+
+namespace {
+
+struct Pair {
+    float px, py, pz;
+    int w0, w1, w2;
+    bool self;
+};
+
+// p_ij in FP32 from the FP64 wrapped fractional displacement. Inactive lanes
+// get a displacement no image can bring within the cutoff.
+__device__ inline Pair make_pair(const float* __restrict__ frac, const double* L, int64_t atom0,
+                                 int il, int j, bool act) {
+    Pair P;
+    P.self = act && (il == j);
+    if (!act) {
+        P.px = P.py = P.pz = 1e30f;
+        P.w0 = P.w1 = P.w2 = 0;
+        return P;
+    }
+    const int64_t ai = atom0 + il, aj = atom0 + j;
+    double d0 = (double)frac[3 * aj] - (double)frac[3 * ai];
+    double d1 = (double)frac[3 * aj + 1] - (double)frac[3 * ai + 1];
+    double d2 = (double)frac[3 * aj + 2] - (double)frac[3 * ai + 2];
+    const double w0 = rint(d0), w1 = rint(d1), w2 = rint(d2);
+    d0 -= w0;
+    d1 -= w1;
+    d2 -= w2;
+    P.px = (float)(d0 * L[0] + d1 * L[3] + d2 * L[6]);
+    P.py = (float)(d0 * L[1] + d1 * L[4] + d2 * L[7]);
+    P.pz = (float)(d0 * L[2] + d1 * L[5] + d2 * L[8]);
+    P.w0 = (int)w0;
+    P.w1 = (int)w1;
+    P.w2 = (int)w2;
+    return P;
+}
+
+__device__ inline float dist2(const Pair& P, const ImageEntry& e) {
+    const float dx = P.px + e.sx, dy = P.py + e.sy, dz = P.pz + e.sz;
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+__device__ inline void write_edge(int64_t e, int64_t capacity, int64_t src_atom, int64_t dst_atom,
+                                  const Pair& P, int32_t tpk, float l2, int32_t* __restrict__ src,
+                                  int32_t* __restrict__ dst, int32_t* __restrict__ image,
+                                  float* __restrict__ length) {
+    if (e >= capacity) return;
+    src[e] = (int32_t)src_atom;
+    dst[e] = (int32_t)dst_atom;
+    image[3 * e] = unpack_t0(tpk) - P.w0;
+    image[3 * e + 1] = unpack_t1(tpk) - P.w1;
+    image[3 * e + 2] = unpack_t2(tpk) - P.w2;
+    length[e] = sqrtf(l2);
+}
+
+}  // namespace
+
+constexpr int MODE_COUNT = 0, MODE_FILL = 1;
+
+template <int MODE, int SLOTS>
+__global__ __launch_bounds__(256) void k_cutoff_sweep(
+    int B, const StructInfo* __restrict__ info, const int64_t* __restrict__ item_off,
+    const ImageEntry* __restrict__ table, const float* __restrict__ frac, float c2thr,
+    uint32_t* __restrict__ counts, const int64_t* __restrict__ offsets, int64_t capacity,
+    int32_t* __restrict__ src, int32_t* __restrict__ dst, int32_t* __restrict__ image,
+    float* __restrict__ length, Counters* __restrict__ ctr, mg_report* __restrict__ rep) {
+    const int lane = lane_id();
+    const int64_t total = item_off[B];
+    for (;;) {
+        const int64_t q = (int64_t)wave_ticket(&ctr->ticket[MODE]);
+        if (q >= total) break;
+        int lo = 0, hi = B;   // item_off[lo] <= q < item_off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (item_off[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        const StructInfo* si = info + lo;
+        const int n = si->n;
+        const int G = si->G;
+        const int i_first = (int)(q - item_off[lo]) * G;
+        const int nsrc = min(G, n - i_first);
+        const int64_t atom0 = si->atom0;
+        const int I = si->box == 0 ? 0 : si->images;
+        const int zimg = si->zero_img;
+        const ImageEntry* tab = table + si->img_off;
+        double L[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) L[r] = si->L[r];
+
+        if (I == 0 || zimg < 0) {
+            if (MODE == MODE_COUNT && lane < nsrc) counts[atom0 + i_first + lane] = 0u;
+            continue;
+        }
+        if (MODE == MODE_COUNT && lane == 0)
+            atomicAdd((unsigned long long*)&rep->candidates,
+                      (unsigned long long)nsrc * (unsigned long long)n * (unsigned long long)I);
+
+        if (n <= WAVE) {
+            // ---- several sources per wave: lane = a * n + j
+            const int a = lane / n;
+            const int j = lane - a * n;
+            const bool act = a < nsrc;
+            const int il = i_first + a;
+            const Pair P = make_pair(frac, L, atom0, il, j, act);
+            uint32_t cnt = 0;
+            uint32_t run = 0;
+            int64_t base = 0;
+            uint64_t seg = 0;
+            if (MODE == MODE_FILL) {
+                base = act ? offsets[atom0 + il] : 0;
+                seg = (n == WAVE) ? ~0ull : (((1ull << n) - 1ull) << (a * n));
+            }
+            auto step = [&](const ImageEntry& e, bool zero) {
+                const float l2 = dist2(P, e);
+                bool hit = l2 < c2thr;
+                if (zero) hit = hit && !P.self;
+                if (MODE == MODE_COUNT) {
+                    cnt += hit ? 1u : 0u;
+                } else {
+                    const uint64_t m = ballot(hit) & seg;
+                    if (hit)
+                        write_edge(base + run + mbcnt(m), capacity, atom0 + il, atom0 + j, P, e.tpk, l2,
+                                   src, dst, image, length);
+                    run += (uint32_t)__popcll(m);
+                }
+            };
+#pragma unroll 4
+            for (int m = 0; m < zimg; ++m) step(tab[m], false);
+            step(tab[zimg], true);
+#pragma unroll 4
+            for (int m = zimg + 1; m < I; ++m) step(tab[m], false);
+            if (MODE == MODE_COUNT) {
+                const int inc = wave_incl_scan_i32(act ? (int)cnt : 0);
+                const int end = min((lane + 1) * n - 1, WAVE - 1);
+                const int beg = lane * n - 1;
+                const int hiv = __shfl(inc, end, WAVE);
+                const int lov = __shfl(inc, max(beg, 0), WAVE);
+                if (lane < nsrc) counts[atom0 + i_first + lane] = (uint32_t)(hiv - (beg >= 0 ? lov : 0));
+            }
+        } else {
+            // ---- one source per item, SLOTS destinations per lane, chunks of 64*SLOTS
+            const int il = i_first;
+            uint32_t cnt = 0;
+            uint32_t run = 0;
+            const int64_t base = (MODE == MODE_FILL) ? offsets[atom0 + il] : 0;
+            for (int jc = 0; jc < n; jc += WAVE * SLOTS) {
+                Pair P[SLOTS];
+#pragma unroll
+                for (int r = 0; r < SLOTS; ++r) {
+                    const int j = jc + r * WAVE + lane;
+                    P[r] = make_pair(frac, L, atom0, il, j, j < n);
+                }
+                auto step = [&](const ImageEntry& e, bool zero) {
+#pragma unroll
+                    for (int r = 0; r < SLOTS; ++r) {
+                        const float l2 = dist2(P[r], e);
+                        bool hit = l2 < c2thr;
+                        if (zero) hit = hit && !P[r].self;
+                        if (MODE == MODE_COUNT) {
+                            cnt += hit ? 1u : 0u;
+                        } else {
+                            const uint64_t m = ballot(hit);
+                            if (hit)
+                                write_edge(base + run + mbcnt(m), capacity, atom0 + il,
+                                           atom0 + jc + r * WAVE + lane, P[r], e.tpk, l2, src, dst,
+                                           image, length);
+                            run += (uint32_t)__popcll(m);
+                        }
+                    }
+                };
+#pragma unroll 2
+                for (int m = 0; m < zimg; ++m) step(tab[m], false);
+                step(tab[zimg], true);
+#pragma unroll 2
+                for (int m = zimg + 1; m < I; ++m) step(tab[m], false);
+            }
+            if (MODE == MODE_COUNT) {
+                const int tot = wave_incl_scan_i32((int)cnt);
+                if (lane == WAVE - 1) counts[atom0 + il] = (uint32_t)tot;
+            }
+        }
+    }
+}
+
+hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
+                               const ImageEntry* table, const float* frac, float c2thr,
+                               uint32_t* counts, const int64_t* offsets, int64_t capacity,
+                               int32_t* src, int32_t* dst, int32_t* image, float* length,
+                               Counters* ctr, mg_report* report, int grid, int slots, hipStream_t s) {
+    if (B == 0) return hipSuccess;
+#define MG_SWEEP(M, S)                                                                              \
+    hipLaunchKernelGGL((k_cutoff_sweep<M, S>), dim3(grid), dim3(256), 0, s, B, info, item_off, table, \
+                       frac, c2thr, counts, offsets, capacity, src, dst, image, length, ctr, report)
+    if (mode == MODE_COUNT) {
+        if (slots <= 1) MG_SWEEP(MODE_COUNT, 1);
+        else if (slots == 2) MG_SWEEP(MODE_COUNT, 2);
+        else MG_SWEEP(MODE_COUNT, 4);
+    } else {
+        if (slots <= 1) MG_SWEEP(MODE_FILL, 1);
+        else if (slots == 2) MG_SWEEP(MODE_FILL, 2);
+        else MG_SWEEP(MODE_FILL, 4);
+    }
+#undef MG_SWEEP
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ prefix sums
+
+constexpr int SCAN_TILE = 2048;   // 256 threads x 8 counts
+
+__device__ inline int64_t block_sum_256(int64_t v, int64_t* sh) {
+    v = wave_sum_i64(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    const int64_t t = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ counts, int64_t N,
+                                                   int64_t* __restrict__ bsum) {
+    __shared__ int64_t sh[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int64_t idx = base + k * 256 + threadIdx.x;
+        if (idx < N) s += counts[idx];
+    }
+    s = block_sum_256(s, sh);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__ counts, int64_t N,
+                                                    const int64_t* __restrict__ bsum,
+                                                    int64_t* __restrict__ offsets, int64_t capacity,
+                                                    mg_report* __restrict__ rep) {
+    __shared__ int64_t sh[4];
+    __shared__ int64_t swave[4];
+    int64_t p = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) p += bsum[b];
+    p = block_sum_256(p, sh);
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * 8;
+    uint32_t v[8];
+    int64_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k] = (base + k < N) ? counts[base + k] : 0u;
+        tsum += v[k];
+    }
+    const int64_t inc = wave_incl_scan_i64(tsum);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) swave[w] = inc;
+    __syncthreads();
+    int64_t excl = p + inc - tsum;
+    for (int q = 0; q < w; ++q) excl += swave[q];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (base + k < N) offsets[base + k] = excl;
+        excl += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) {
+        offsets[N] = excl;
+        rep->num_edges = excl;
+        if (excl > capacity) atomicOr(&rep->flags, (uint32_t)MG_FLAG_CAPACITY);
+    }
+}
+
+hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offsets, int64_t* bsum,
+                              int64_t capacity, mg_report* report, hipStream_t s) {
+    const int64_t nb = N > 0 ? (N + SCAN_TILE - 1) / SCAN_TILE : 1;
+    if (N > 0) hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, counts, N, bsum);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(256), 0, s, counts, N, bsum, offsets,
+                       capacity, report);
+    return hipGetLastError();
+}
+
+int64_t scan_block_count(int64_t N) { return N > 0 ? (N + SCAN_TILE - 1) / SCAN_TILE : 1; }
+
+}  // namespace mg

@@ -1,0 +1,279 @@
+"""Torch-facing API over libmatgraph (argument marshalling only).
+
+Every computation runs in the HIP library; torch provides device memory and
+the current stream. Tensors must live on a ROCm device:
+
+    lattices  float32 [B, 3, 3]  rows are lattice vectors (Angstrom)
+    frac      float32 [N, 3]     fractional coordinates
+    batch_ptr int64   [B + 1]    structure b owns atoms batch_ptr[b]:batch_ptr[b+1]
+
+Edges come back as int32 src/dst (global atom indices), int32 image [E, 3]
+(the cell of the destination image, Sec. 2.1) and float32 length.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib
+
+__all__ = ["Graph", "Report", "cutoff_graph", "knn_graph", "edge_geometry", "EdgeGeometry",
+           "CutoffBuilder", "KnnBuilder", "GeometryRunner"]
+
+
+@dataclasses.dataclass
+class Report:
+    num_edges: int
+    images_needed: int
+    candidates: int
+    knn_extended: int
+    flags: int
+
+    @staticmethod
+    def from_tensor(t: torch.Tensor) -> "Report":
+        v = t.cpu().view(torch.int64).tolist()
+        return Report(v[0], v[1], v[2], v[3], v[4] & 0xFFFFFFFF)
+
+    def flag_names(self):
+        names = {_lib.MG_FLAG_CAPACITY: "capacity", _lib.MG_FLAG_SINGULAR: "singular",
+                 _lib.MG_FLAG_NONFINITE: "nonfinite", _lib.MG_FLAG_IMAGES: "images",
+                 _lib.MG_FLAG_RANGE: "range", _lib.MG_FLAG_KNN_EXTENDED: "knn_extended"}
+        return [n for b, n in names.items() if self.flags & b]
+
+
+@dataclasses.dataclass
+class Graph:
+    src: torch.Tensor
+    dst: torch.Tensor
+    image: torch.Tensor
+    length: torch.Tensor
+    row_ptr: torch.Tensor | None
+    report: Report
+
+    @property
+    def num_edges(self) -> int:
+        return int(self.src.shape[0])
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_inputs(lattices, frac, batch_ptr):
+    if not (lattices.is_cuda and frac.is_cuda and batch_ptr.is_cuda):
+        raise ValueError("lattices, frac and batch_ptr must be device tensors")
+    if lattices.dtype != torch.float32 or frac.dtype != torch.float32:
+        raise ValueError("lattices and frac must be float32")
+    if batch_ptr.dtype != torch.int64:
+        raise ValueError("batch_ptr must be int64")
+    if lattices.dim() != 3 or lattices.shape[1:] != (3, 3):
+        raise ValueError("lattices must be [B, 3, 3]")
+    if frac.dim() != 2 or frac.shape[1] != 3:
+        raise ValueError("frac must be [N, 3]")
+    B = int(lattices.shape[0])
+    if batch_ptr.shape != (B + 1,):
+        raise ValueError("batch_ptr must be [B + 1]")
+    return lattices.contiguous(), frac.contiguous(), batch_ptr.contiguous(), B, int(frac.shape[0])
+
+
+def _strict_check(rep: Report):
+    bad = rep.flags & (_lib.MG_FLAG_SINGULAR | _lib.MG_FLAG_NONFINITE | _lib.MG_FLAG_RANGE)
+    if bad:
+        raise _lib.MatgraphError(-1, "structures skipped: " + ",".join(rep.flag_names()))
+
+
+class CutoffBuilder:
+    """Preallocated cutoff-graph call: fixed batch shape, edge capacity and
+    image-table capacity. ``run`` only enqueues kernels (no host sync), so it can
+    be replayed or captured into a HIP graph; ``report()`` reads the device
+    report (synchronising)."""
+
+    def __init__(self, B: int, N: int, capacity: int, image_capacity: int, device=None,
+                 row_ptr: bool = True):
+        self.lib = _lib.load()
+        self.device = torch.device(device or "cuda")
+        self.B, self.N = int(B), int(N)
+        self.capacity = int(capacity)
+        self.image_capacity = int(image_capacity)
+        d = self.device
+        self.src = torch.empty(self.capacity, dtype=torch.int32, device=d)
+        self.dst = torch.empty(self.capacity, dtype=torch.int32, device=d)
+        self.image = torch.empty((self.capacity, 3), dtype=torch.int32, device=d)
+        self.length = torch.empty(self.capacity, dtype=torch.float32, device=d)
+        self.row_ptr = torch.empty(self.N + 1, dtype=torch.int64, device=d) if row_ptr else None
+        self.rep = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=d)
+        nbytes = self.lib.mg_cutoff_workspace_bytes(self.B, self.N, self.image_capacity)
+        self.workspace = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=d)
+
+    def run(self, lattices, frac, batch_ptr, cutoff: float, opts: int = 0):
+        _lib.check(self.lib.mg_cutoff_graph(
+            _ptr(lattices), _ptr(frac), _ptr(batch_ptr), self.B, self.N, float(cutoff),
+            self.capacity, _ptr(self.src), _ptr(self.dst), _ptr(self.image), _ptr(self.length),
+            _ptr(self.row_ptr), _ptr(self.rep), _ptr(self.workspace), self.workspace.numel(),
+            int(opts), _stream(self.device)), self.lib)
+
+    def report(self) -> Report:
+        return Report.from_tensor(self.rep)
+
+    def graph(self, rep: Report | None = None) -> Graph:
+        rep = rep or self.report()
+        E = min(rep.num_edges, self.capacity)
+        return Graph(self.src[:E], self.dst[:E], self.image[:E], self.length[:E], self.row_ptr, rep)
+
+
+def cutoff_graph(lattices, frac, batch_ptr, cutoff: float, capacity: int | None = None,
+                 image_capacity: int | None = None, strict: bool = False) -> Graph:
+    """Periodic cutoff multigraph (Definition def6, constant cutoff, strict <).
+
+    Allocates outputs, runs the library and, when the edge or image-table
+    capacity was too small, reruns once with the exact sizes the device
+    reported (this reads the report, i.e. synchronises)."""
+    lattices, frac, batch_ptr, B, N = _check_inputs(lattices, frac, batch_ptr)
+    cap = int(capacity) if capacity is not None else max(4096, 96 * N)
+    icap = int(image_capacity) if image_capacity is not None else 96 * B + 4096
+    for _ in range(3):
+        b = CutoffBuilder(B, N, cap, icap, frac.device)
+        b.run(lattices, frac, batch_ptr, cutoff)
+        rep = b.report()
+        retry = False
+        if rep.flags & _lib.MG_FLAG_IMAGES:
+            icap = int(rep.images_needed)
+            retry = True
+        if rep.flags & _lib.MG_FLAG_CAPACITY:
+            cap = int(rep.num_edges)
+            retry = True
+        if not retry:
+            break
+    if strict:
+        _strict_check(rep)
+    return b.graph(rep)
+
+
+class KnnBuilder:
+    """Preallocated KNN-graph call (output size N*k is fixed)."""
+
+    def __init__(self, B: int, N: int, k: int, image_capacity: int, device=None):
+        self.lib = _lib.load()
+        self.device = torch.device(device or "cuda")
+        self.B, self.N, self.k = int(B), int(N), int(k)
+        self.image_capacity = int(image_capacity)
+        d = self.device
+        M = self.N * self.k
+        self.src = torch.empty(M, dtype=torch.int32, device=d)
+        self.dst = torch.empty(M, dtype=torch.int32, device=d)
+        self.image = torch.empty((M, 3), dtype=torch.int32, device=d)
+        self.length = torch.empty(M, dtype=torch.float32, device=d)
+        self.rep = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=d)
+        nbytes = self.lib.mg_knn_workspace_bytes(self.B, self.N, self.k, self.image_capacity)
+        if nbytes == 0:
+            raise ValueError("invalid KNN sizes (k must be in 1..64)")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=d)
+
+    def run(self, lattices, frac, batch_ptr, opts: int = 0):
+        _lib.check(self.lib.mg_knn_graph(
+            _ptr(lattices), _ptr(frac), _ptr(batch_ptr), self.B, self.N, self.k, _ptr(self.src),
+            _ptr(self.dst), _ptr(self.image), _ptr(self.length), _ptr(self.rep),
+            _ptr(self.workspace), self.workspace.numel(), int(opts), _stream(self.device)), self.lib)
+
+    def report(self) -> Report:
+        return Report.from_tensor(self.rep)
+
+    def graph(self, rep: Report | None = None) -> Graph:
+        return Graph(self.src, self.dst, self.image, self.length, None, rep or self.report())
+
+
+def knn_graph(lattices, frac, batch_ptr, k: int, image_capacity: int | None = None,
+              strict: bool = False) -> Graph:
+    """Periodic KNN multigraph: exactly k edges per source in (length, dst, t) order."""
+    lattices, frac, batch_ptr, B, N = _check_inputs(lattices, frac, batch_ptr)
+    icap = int(image_capacity) if image_capacity is not None else 64 * B + 4096
+    for _ in range(3):
+        b = KnnBuilder(B, N, k, icap, frac.device)
+        b.run(lattices, frac, batch_ptr)
+        rep = b.report()
+        if rep.flags & _lib.MG_FLAG_IMAGES:
+            icap = int(rep.images_needed)
+            continue
+        break
+    if strict:
+        _strict_check(rep)
+    return b.graph(rep)
+
+
+class GeometryRunner:
+    """Preallocated edge-geometry forward / backward for a fixed batch shape."""
+
+    def __init__(self, B: int, N: int, device=None):
+        self.lib = _lib.load()
+        self.device = torch.device(device or "cuda")
+        self.B, self.N = int(B), int(N)
+        nbytes = self.lib.mg_geometry_workspace_bytes(self.B, self.N)
+        self.workspace = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+
+    def forward(self, lattices, frac, batch_ptr, src, dst, image, vec=None, length=None,
+                num_edges=None):
+        E = int(src.shape[0])
+        _lib.check(self.lib.mg_edge_geometry(
+            _ptr(lattices), _ptr(frac), _ptr(batch_ptr), self.B, self.N, _ptr(src), _ptr(dst),
+            _ptr(image), E, _ptr(num_edges), _ptr(vec), _ptr(length), _ptr(self.workspace),
+            self.workspace.numel(), _stream(self.device)), self.lib)
+        return vec, length
+
+    def backward(self, lattices, frac, batch_ptr, src, dst, image, grad_vec=None,
+                 grad_length=None, grad_frac=None, grad_lattice=None, num_edges=None):
+        E = int(src.shape[0])
+        _lib.check(self.lib.mg_edge_geometry_backward(
+            _ptr(lattices), _ptr(frac), _ptr(batch_ptr), self.B, self.N, _ptr(src), _ptr(dst),
+            _ptr(image), E, _ptr(num_edges), _ptr(grad_vec), _ptr(grad_length), _ptr(grad_frac),
+            _ptr(grad_lattice), _ptr(self.workspace), self.workspace.numel(),
+            _stream(self.device)), self.lib)
+        return grad_frac, grad_lattice
+
+
+def _edge_inputs(src, dst, image):
+    for t, nm in ((src, "src"), (dst, "dst"), (image, "image")):
+        if not t.is_cuda or t.dtype != torch.int32:
+            raise ValueError(f"{nm} must be an int32 device tensor")
+    if image.dim() != 2 or image.shape[1] != 3 or image.shape[0] != src.shape[0] or dst.shape != src.shape:
+        raise ValueError("src [E], dst [E], image [E, 3] expected")
+    return src.contiguous(), dst.contiguous(), image.contiguous()
+
+
+class EdgeGeometry(torch.autograd.Function):
+    """(vec [E,3], length [E]) of fixed edges, differentiable w.r.t. lattices and frac."""
+
+    @staticmethod
+    def forward(ctx, lattices, frac, batch_ptr, src, dst, image):
+        lattices, frac, batch_ptr, B, N = _check_inputs(lattices, frac, batch_ptr)
+        src, dst, image = _edge_inputs(src, dst, image)
+        E = int(src.shape[0])
+        run = GeometryRunner(B, N, frac.device)
+        vec = torch.empty((E, 3), dtype=torch.float32, device=frac.device)
+        length = torch.empty(E, dtype=torch.float32, device=frac.device)
+        run.forward(lattices, frac, batch_ptr, src, dst, image, vec, length)
+        ctx.save_for_backward(lattices, frac, batch_ptr, src, dst, image)
+        ctx.run = run
+        return vec, length
+
+    @staticmethod
+    def backward(ctx, grad_vec, grad_length):
+        lattices, frac, batch_ptr, src, dst, image = ctx.saved_tensors
+        need_L, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        gf = torch.empty_like(frac) if need_x else None
+        gL = torch.empty_like(lattices) if need_L else None
+        if need_x or need_L:
+            gv = grad_vec.contiguous().float() if grad_vec is not None else None
+            gl = grad_length.contiguous().float() if grad_length is not None else None
+            ctx.run.backward(lattices, frac, batch_ptr, src, dst, image, gv, gl, gf, gL)
+        return gL, gf, None, None, None, None
+
+
+def edge_geometry(lattices, frac, batch_ptr, src, dst, image):
+    """Differentiable (vec, length) of the given edges (see ``EdgeGeometry``)."""
+    return EdgeGeometry.apply(lattices, frac, batch_ptr, src, dst, image)

@@ -1,0 +1,196 @@
+"""Cutoff multigraph on the GPU against the FP64 oracle (Definition def6)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import compare
+import gpu_util as gu
+from paper_2307_05380_amd import graph, inputs
+from paper_2307_05380_amd import _lib
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 4])
+def test_parity_full(cfg):
+    b = inputs.make_config(cfg)
+    print(f"config {cfg}: B={b.B} N={b.N} cutoff={b.cutoff}", flush=True)
+    g = gu.cutoff(b)
+    assert g.report.flags == 0, g.report.flag_names()
+    st = compare.cutoff_check(b, *gu.np_graph(g), processes=8)
+    print(st)
+    assert st["edges"] == g.num_edges
+
+
+def _config3_sample(b, n_random=160, n_heavy=32, seed=0):
+    n = b.counts()
+    L = b.lattices.astype(np.float64)
+    vol = np.abs(np.linalg.det(L))
+    cost = n.astype(np.float64) ** 2 * (b.cutoff ** 3) / vol
+    heavy = np.argsort(-cost)[:n_heavy]
+    rnd = np.random.default_rng(seed).choice(b.B, n_random, replace=False)
+    thin = np.argsort(vol / np.prod(np.linalg.norm(L, axis=2), axis=1))[:16]
+    return sorted(set(heavy.tolist()) | set(rnd.tolist()) | set(thin.tolist()))
+
+
+def test_parity_config3_sampled():
+    """Full 4096-structure batch in one call; structures checked: the most
+    expensive, the thinnest cells and a random sample."""
+    b = inputs.make_config(3)
+    g = gu.cutoff(b)
+    assert g.report.flags == 0, g.report.flag_names()
+    sample = _config3_sample(b)
+    st = compare.cutoff_check(b, *gu.np_graph(g), structures=sample, processes=8)
+    print(st, g.report)
+
+
+def test_symmetry_bitwise_config3():
+    """(i, j, t) is an edge iff (j, i, -t) is, with bit-identical FP32 length."""
+    b = inputs.make_config(3)
+    g = gu.cutoff(b)
+    s, d, t, ln = gu.np_graph(g)
+    fwd = np.stack([s, d, t[:, 0], t[:, 1], t[:, 2]], 1)
+    rev = np.stack([d, s, -t[:, 0], -t[:, 1], -t[:, 2]], 1)
+    fo = np.lexsort(fwd.T[::-1])
+    ro = np.lexsort(rev.T[::-1])
+    assert np.array_equal(fwd[fo], rev[ro])
+    assert np.array_equal(ln[fo].view(np.uint32), ln[ro].view(np.uint32))
+
+
+def test_row_ptr_and_grouping():
+    b = inputs.make_config(2)
+    g = gu.cutoff(b)
+    rp = g.row_ptr.cpu().numpy()
+    s = g.src.cpu().numpy()
+    assert rp[0] == 0 and rp[-1] == g.num_edges and (np.diff(rp) >= 0).all()
+    assert np.array_equal(np.repeat(np.arange(b.N), np.diff(rp)), s)
+
+
+def test_closed_forms():
+    g = json.load(open(os.path.join(GOLDEN, "cubic_shells.json")))
+    for name in ("sc", "bcc", "fcc"):
+        x = np.array(g[name]["frac"], np.float32)
+        for c, want in zip(g[name]["cutoffs"], g[name]["edges_per_atom"]):
+            bb = gu.single(np.eye(3), x, cutoff=c)
+            gg = gu.cutoff(bb)
+            counts = np.bincount(gg.src.cpu().numpy(), minlength=len(x))
+            assert (counts == want).all(), (name, c, counts)
+    for name in ("fcc_primitive", "bcc_primitive"):
+        L = np.array(g[name]["lattice"], np.float32)
+        for c, want in zip(g[name]["cutoffs"], g[name]["edges_per_atom"]):
+            gg = gu.cutoff(gu.single(L, np.zeros((1, 3)), cutoff=c))
+            assert gg.num_edges == want, (name, c, gg.num_edges)
+    # strict cutoff: sc a = 1, c = 1 has no edge (exact in FP32)
+    assert gu.cutoff(gu.single(np.eye(3), np.zeros((1, 3)), cutoff=1.0)).num_edges == 0
+    # sums of three squares: shell m has r3(m) images at exactly sqrt(m)
+    r3 = g["r3"]["values"]
+    gg = gu.cutoff(gu.single(np.eye(3), np.zeros((1, 3)), cutoff=math.sqrt(len(r3) + 0.5)))
+    sq = np.rint(gg.length.cpu().numpy().astype(np.float64) ** 2).astype(int)
+    assert [int((sq == m).sum()) for m in range(1, len(r3) + 1)] == r3
+
+
+def test_figure1():
+    g = json.load(open(os.path.join(GOLDEN, "paper_figure1.json")))
+    bb = gu.single(np.array(g["lattice"]), np.array(g["frac"]), cutoff=g["cutoff"])
+    gg = gu.cutoff(bb)
+    s, d, t, ln = gu.np_graph(gg)
+    got = {(int(a), int(c)) + tuple(int(q) for q in tt) for a, c, tt in zip(s, d, t)}
+    want = {(0, 1) + tuple(x) for x in g["edges"]["0->1"]} | {(1, 0) + tuple(x) for x in g["edges"]["1->0"]}
+    assert got == want
+    assert np.allclose(ln, g["length"], atol=1e-6)
+
+
+def test_ragged_and_edge_cases():
+    """Atom counts 0..200 (one source per item beyond 64 atoms, several
+    destination chunks beyond 128), coordinates outside [0, 1)."""
+    rng = np.random.default_rng(11)
+    parts = []
+    for n in (1, 2, 3, 7, 31, 63, 64, 65, 127, 128, 129, 200):
+        bb = inputs.random_batch(rng, 1, n, n, 4.0, 9.0, cutoff=5.0)
+        parts.append(bb)
+    b = gu.concat(parts, 5.0, 8)
+    b.frac[::7] += np.float32(1.0)
+    b.frac[3::11] -= np.float32(2.0)
+    # an empty structure in the middle
+    ptr = np.insert(b.batch_ptr, 4, b.batch_ptr[4])
+    lat = np.insert(b.lattices, 4, np.eye(3, dtype=np.float32) * 3, axis=0)
+    b = inputs.Batch(lat, b.frac, ptr, 5.0, 8, "ragged")
+    g = gu.cutoff(b)
+    assert g.report.flags == 0
+    compare.cutoff_check(b, *gu.np_graph(g))
+
+
+def test_empty_batch():
+    b = inputs.Batch(np.zeros((0, 3, 3), np.float32), np.zeros((0, 3), np.float32),
+                     np.zeros(1, np.int64), 5.0, 4, "empty")
+    g = gu.cutoff(b)
+    assert g.num_edges == 0 and g.report.flags == 0
+
+
+def test_flags_singular_nonfinite():
+    rng = np.random.default_rng(5)
+    good = inputs.random_batch(rng, 3, 3, 6, cutoff=5.0)
+    lat = good.lattices.copy()
+    frac = good.frac.copy()
+    lat[1] = 0.0                              # singular
+    a0 = good.batch_ptr[2]
+    frac[a0, 1] = np.nan                      # non-finite coordinate
+    b = inputs.Batch(lat, frac, good.batch_ptr, 5.0, 4, "flags")
+    g = gu.cutoff(b)
+    assert g.report.flags & _lib.MG_FLAG_SINGULAR and g.report.flags & _lib.MG_FLAG_NONFINITE
+    s = g.src.cpu().numpy()
+    assert ((s >= good.batch_ptr[1]) & (s < good.batch_ptr[3])).sum() == 0
+    compare.cutoff_check(b, *gu.np_graph(g), structures=[0])
+
+
+def test_capacity_overflow():
+    """Past `capacity` nothing is written; the report holds the exact edge count
+    and the edges that fit are the first edges of the full graph."""
+    b = inputs.make_config(1)
+    L, X, P = gu.dev(b)
+    full = gu.cutoff(b)
+    E = full.num_edges
+    bld = graph.CutoffBuilder(b.B, b.N, 100, 4096, "cuda")
+    big = {nm: torch.full((200,) + tuple(getattr(bld, nm).shape[1:]), -7, dtype=getattr(bld, nm).dtype,
+                          device="cuda") for nm in ("src", "dst", "image", "length")}
+    for nm, t in big.items():
+        setattr(bld, nm, t[:100])
+    bld.run(L, X, P, b.cutoff)
+    rep = bld.report()
+    assert rep.flags & _lib.MG_FLAG_CAPACITY and rep.num_edges == E
+    for nm, t in big.items():
+        assert (t[100:] == -7).all(), nm
+    assert np.array_equal(bld.src.cpu().numpy(), full.src.cpu().numpy()[:100])
+    assert np.array_equal(bld.image.cpu().numpy(), full.image.cpu().numpy()[:100])
+
+
+def test_image_capacity_overflow_and_retry():
+    b = inputs.make_config(2)
+    L, X, P = gu.dev(b)
+    bld = graph.CutoffBuilder(b.B, b.N, 4_000_000, 64, "cuda")
+    bld.run(L, X, P, b.cutoff)
+    rep = bld.report()
+    assert rep.flags & _lib.MG_FLAG_IMAGES and rep.images_needed > 64
+    g = gu.cutoff(b, image_capacity=64)       # the binding retries with the reported size
+    assert g.report.flags == 0
+    assert g.num_edges == gu.cutoff(b).num_edges
+
+
+def test_deterministic_replay():
+    b = inputs.make_config(2)
+    L, X, P = gu.dev(b)
+    bld = graph.CutoffBuilder(b.B, b.N, 2_000_000, 100_000, "cuda")
+    outs = []
+    for _ in range(3):
+        bld.run(L, X, P, b.cutoff)
+        torch.cuda.synchronize()
+        E = bld.report().num_edges
+        outs.append([t[:E].clone() for t in (bld.src, bld.dst, bld.image, bld.length)])
+    for o in outs[1:]:
+        for a, c in zip(outs[0], o):
+            assert torch.equal(a, c)

@@ -1,0 +1,102 @@
+"""Edge geometry forward / backward on the GPU against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import gpu_util as gu
+import oracle
+from paper_2307_05380_amd import graph, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _edges(b):
+    g = gu.cutoff(b)
+    return g, gu.np_graph(g)
+
+
+def test_forward_parity_config4():
+    b = inputs.make_config(4)
+    g, (s, d, t, ln) = _edges(b)
+    L, X, P = gu.dev(b)
+    vec, length = graph.edge_geometry(L, X, P, g.src, g.dst, g.image)
+    v64, l64 = oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, s, d, t)
+    assert np.abs(vec.detach().cpu().numpy() - v64).max() <= 2e-5
+    assert np.abs(length.detach().cpu().numpy() - l64).max() <= 2e-5
+    # the graph's own lengths agree with the geometry op
+    assert np.abs(length.detach().cpu().numpy() - ln).max() <= 2e-5
+
+
+def _rel_err(a, ref):
+    return np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def test_backward_parity_config4_loss():
+    """Loss = sum_e w_e exp(-(l_e - 3)^2), w_e ~ N(0,1) in canonical edge order;
+    gradients to frac [N,3] and lattice [B,3,3] against the oracle's analytic
+    gradient at 1e-4 relative, per structure and tensor."""
+    b = inputs.make_config(4)
+    g, (s, d, t, ln) = _edges(b)
+    order = np.lexsort((t[:, 2], t[:, 1], t[:, 0], d, s))
+    w = np.empty(len(s), np.float32)
+    w[order] = inputs.loss_weights(len(s))
+    L, X, P = gu.dev(b)
+    L.requires_grad_(True)
+    X.requires_grad_(True)
+    vec, length = graph.edge_geometry(L, X, P, g.src, g.dst, g.image)
+    wt = torch.from_numpy(w).cuda()
+    loss = (wt * torch.exp(-(length - 3.0) ** 2)).sum()
+    loss.backward()
+    gl64 = oracle.gaussian_loss_grad_len64(oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, s, d, t)[1], w)
+    gf64, gL64 = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, None, gl64)
+    gf = X.grad.cpu().numpy()
+    gL = L.grad.cpu().numpy()
+    worst_f = worst_L = 0.0
+    for q in range(b.B):
+        a0, a1 = b.batch_ptr[q], b.batch_ptr[q + 1]
+        if np.abs(gf64[a0:a1]).max() > 0:
+            worst_f = max(worst_f, _rel_err(gf[a0:a1], gf64[a0:a1]))
+        if np.abs(gL64[q]).max() > 0:
+            worst_L = max(worst_L, _rel_err(gL[q], gL64[q]))
+    print("worst relative errors", worst_f, worst_L)
+    assert worst_f <= 1e-4 and worst_L <= 1e-4
+
+
+def test_backward_vs_finite_differences():
+    rng = np.random.default_rng(4)
+    b = inputs.random_batch(rng, 3, 2, 6, 3.0, 6.0, cutoff=4.5)
+    g, (s, d, t, ln) = _edges(b)
+    E = len(s)
+    gv = rng.normal(size=(E, 3)).astype(np.float32)
+    glen = rng.normal(size=E).astype(np.float32)
+    L, X, P = gu.dev(b)
+    run = graph.GeometryRunner(b.B, b.N)
+    gf = torch.empty_like(X)
+    gL = torch.empty_like(L)
+    run.backward(L, X, P, g.src, g.dst, g.image, torch.from_numpy(gv).cuda(), torch.from_numpy(glen).cuda(), gf, gL)
+    ff, fL = oracle.fd_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, gv, glen, h=1e-6)
+    assert _rel_err(gf.cpu().numpy(), ff) <= 1e-4
+    assert _rel_err(gL.cpu().numpy(), fL) <= 1e-4
+    # sum of coordinate gradients of a structure vanishes
+    for q in range(b.B):
+        a0, a1 = b.batch_ptr[q], b.batch_ptr[q + 1]
+        assert np.abs(gf.cpu().numpy()[a0:a1].sum(0)).max() <= 1e-4 * np.abs(ff).max()
+
+
+def test_backward_random_edge_order():
+    """Edges in arbitrary order (no grouping by source) and only grad_vec."""
+    rng = np.random.default_rng(8)
+    b = inputs.random_batch(rng, 5, 3, 40, 3.0, 8.0, cutoff=5.0)
+    g, (s, d, t, ln) = _edges(b)
+    perm = rng.permutation(len(s))
+    s, d, t = s[perm], d[perm], t[perm]
+    gv = rng.normal(size=(len(s), 3)).astype(np.float32)
+    L, X, P = gu.dev(b)
+    run = graph.GeometryRunner(b.B, b.N)
+    gf = torch.empty_like(X)
+    gL = torch.empty_like(L)
+    ti = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.int32))).cuda()
+    run.backward(L, X, P, ti(s), ti(d), ti(t), torch.from_numpy(gv).cuda(), None, gf, gL)
+    rf, rL = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, gv, None)
+    assert _rel_err(gf.cpu().numpy(), rf) <= 1e-4
+    assert _rel_err(gL.cpu().numpy(), rL) <= 1e-4
