@@ -1,7 +1,6 @@
 """KNN multigraph on the GPU against the FP64 oracle (Sec. 1; Algorithms 1-2)."""
 import itertools
 import math
-import os
 
 import numpy as np
 import pytest
@@ -22,9 +21,6 @@ def test_parity_full(cfg):
     print(st, g.report)
 
 
-@pytest.mark.skipif(os.environ.get("MG_GPU_CONFIG3_KNN") != "1",
-                    reason="an earlier KNN implementation hung on this case; it runs only when "
-                           "MG_GPU_CONFIG3_KNN=1 until the rewritten kernel has passed it")
 def test_parity_config3_sampled():
     b = inputs.make_config(3)
     g = gu.knn(b)
