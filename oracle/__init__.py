@@ -20,13 +20,13 @@ Parity status of every function is listed in ``oracle/graph64.py`` and
 ``oracle/geometry64.py``; all are pinned by CPU tests (closed forms,
 invariants, brute force, finite differences).
 """
-from .graph64 import (Graph64, KnnResult64, cutoff_graph64, cutoff_structure64, image_ranges64,
-                      knn_graph64, knn_structure64)
+from .graph64 import (Graph64, KnnResult64, cutoff_graph64, cutoff_sources64, cutoff_structure64,
+                      image_ranges64, knn_graph64, knn_structure64)
 from .geometry64 import (edge_geometry64, edge_geometry_vjp64, fd_vjp64, gaussian_loss64,
                          gaussian_loss_grad_len64)
 
 __all__ = [
-    "Graph64", "KnnResult64", "cutoff_graph64", "cutoff_structure64", "image_ranges64",
+    "Graph64", "KnnResult64", "cutoff_graph64", "cutoff_sources64", "cutoff_structure64", "image_ranges64",
     "knn_graph64", "knn_structure64", "edge_geometry64", "edge_geometry_vjp64", "fd_vjp64",
     "gaussian_loss64", "gaussian_loss_grad_len64",
 ]

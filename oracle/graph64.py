@@ -122,47 +122,54 @@ def cutoff_structure64(L, x, cutoff: float, band: float = 0.0):
     Returns local (src, dst, image [E,3], length) arrays; with band = 0 this is
     exactly Definition def6 with a constant cutoff.
     """
+    return cutoff_sources64(L, x, cutoff, range(np.asarray(x).shape[0]), band)
+
+
+def cutoff_sources64(L, x, cutoff: float, sources, band: float = 0.0):
+    """Edges of the listed sources of one structure with length < cutoff + band
+    (same definition as ``cutoff_structure64``, restricted to some sources, for
+    structures too large to enumerate whole). Sorted by (src, dst, t)."""
     L = np.asarray(L, np.float64)
     x = np.asarray(x, np.float64)
     R = float(cutoff) + float(band)
-    srcs, dsts, imgs, lens = [], [], [], []
-    for i in range(x.shape[0]):
-        j, t, length = _candidates_within(L, x, i, R)
+    out = [[], [], [], []]
+    for i in sources:
+        j, t, length = _candidates_within(L, x, int(i), R)
         m = length < R
-        srcs.append(np.full(int(m.sum()), i, np.int64))
-        dsts.append(j[m])
-        imgs.append(t[m])
-        lens.append(length[m])
-    if not srcs:
-        return (np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3), np.int64),
-                np.zeros(0, np.float64))
-    src = np.concatenate(srcs)
-    dst = np.concatenate(dsts)
-    img = np.concatenate(imgs).reshape(-1, 3)
-    length = np.concatenate(lens)
+        out[0].append(np.full(int(m.sum()), int(i), np.int64))
+        out[1].append(j[m])
+        out[2].append(t[m])
+        out[3].append(length[m])
+    if not out[0]:
+        return (np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3), np.int64), np.zeros(0))
+    src, dst = np.concatenate(out[0]), np.concatenate(out[1])
+    img, length = np.concatenate(out[2]).reshape(-1, 3), np.concatenate(out[3])
     order = np.lexsort((img[:, 2], img[:, 1], img[:, 0], dst, src))
     return src[order], dst[order], img[order], length[order]
 
 
-def knn_structure64(L, x, k: int, band: float = 0.0):
+def knn_structure64(L, x, k: int, band: float = 0.0, sources=None):
     """k nearest (j, t) of every source of one structure (Sec. 1, Definition def6 remark).
 
     Returns (src, dst, image, length, dk, near, inside) with local indices;
     each source's k edges are in key order (length, dst, t0, t1, t2).
+    ``sources`` restricts the computation to some sources (rows in that order).
     """
     L = np.asarray(L, np.float64)
     x = np.asarray(x, np.float64)
     n = x.shape[0]
     vol = abs(float(np.linalg.det(L)))
     R0 = (3.0 * (k + 1) * vol / (4.0 * math.pi * max(n, 1))) ** (1.0 / 3.0)
-    src = np.zeros(n * k, np.int64)
-    dst = np.zeros(n * k, np.int64)
-    img = np.zeros((n * k, 3), np.int64)
-    length = np.zeros(n * k, np.float64)
-    dk = np.zeros(n, np.float64)
-    inside = np.zeros(n, np.int64)
+    srcs = list(range(n)) if sources is None else [int(i) for i in sources]
+    ns = len(srcs)
+    src = np.zeros(ns * k, np.int64)
+    dst = np.zeros(ns * k, np.int64)
+    img = np.zeros((ns * k, 3), np.int64)
+    length = np.zeros(ns * k, np.float64)
+    dk = np.zeros(ns, np.float64)
+    inside = np.zeros(ns, np.int64)
     near = {}
-    for i in range(n):
+    for r, i in enumerate(srcs):
         R = R0
         while True:
             j, t, ln = _candidates_within(L, x, i, R)
@@ -175,12 +182,12 @@ def knn_structure64(L, x, k: int, band: float = 0.0):
             else:
                 R = 2.0 * R           # extend the search area (Algorithm 1)
         sel = order[:k]
-        src[i * k:(i + 1) * k] = i
-        dst[i * k:(i + 1) * k] = j[sel]
-        img[i * k:(i + 1) * k] = t[sel]
-        length[i * k:(i + 1) * k] = ln[sel]
-        dk[i] = d
-        inside[i] = int((ln[sel] < d - band).sum())
+        src[r * k:(r + 1) * k] = i
+        dst[r * k:(r + 1) * k] = j[sel]
+        img[r * k:(r + 1) * k] = t[sel]
+        length[r * k:(r + 1) * k] = ln[sel]
+        dk[r] = d
+        inside[r] = int((ln[sel] < d - band).sum())
         if band > 0.0:
             m = np.abs(ln - d) <= band
             near[i] = [(int(a), int(b[0]), int(b[1]), int(b[2]), float(c))

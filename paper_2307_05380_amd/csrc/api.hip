@@ -2,6 +2,7 @@
 // workspace carving, launch sequencing, tuning state and phase profiling.
 // No entry point allocates device memory; every kernel is enqueued on the
 // caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -102,17 +103,42 @@ struct Carver {
     }
 };
 
+void carve_cl(Carver& c, int B, int64_t N, mg::Counters* ctr, mg::ClWs& w) {
+    w.cap = mg::cl_bin_capacity(B, N);
+    w.cl_off = c.take<int64_t>((size_t)B + 1);
+    w.bin_count = c.take<uint32_t>((size_t)w.cap);
+    w.bin_fill = c.take<uint32_t>((size_t)w.cap);
+    w.bin_start = c.take<int64_t>((size_t)w.cap + 1);
+    w.bsum = c.take<int64_t>((size_t)((w.cap + 2047) / 2048) + 1);
+    w.atom_bin = c.take<int32_t>((size_t)N);
+    w.atom_shift = c.take<int32_t>((size_t)N);
+    w.slot_atom = c.take<int32_t>((size_t)N);
+    w.slot_pos = c.take<float4>((size_t)N);
+    w.atom_struct = c.take<int32_t>((size_t)N);
+    w.ctr = ctr;
+}
+
 struct CutoffWs {
     mg::Counters* ctr;
     mg::StructInfo* info;
     int64_t* item_off;
+    int64_t* box_off;
     uint32_t* counts;
     int64_t* offsets;
     int64_t* bsum;
+    int64_t* partials;
+    mg::ClWs cl;
     mg::ImageEntry* table;
     int64_t table_cap;
     size_t fixed;
 };
+
+// Persistent sweep grid: workgroups per CU times the CU count, bounded so the
+// per-wave partial array (4 waves per 256-thread workgroup) fits.
+int sweep_grid(int wgs_per_cu) {
+    const int g = mg::device_cu_count() * (wgs_per_cu > 0 ? wgs_per_cu : 8);
+    return std::min(std::max(g, 1), mg::MAX_GRID_WAVES / 4);
+}
 
 CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
     Carver c{static_cast<char*>(ws)};
@@ -120,9 +146,12 @@ CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
     w.ctr = c.take<mg::Counters>(1);
     w.info = c.take<mg::StructInfo>((size_t)B);
     w.item_off = c.take<int64_t>((size_t)B + 1);
+    w.box_off = c.take<int64_t>((size_t)B + 1);
     w.counts = c.take<uint32_t>((size_t)N);
     w.offsets = c.take<int64_t>((size_t)N + 1);
     w.bsum = c.take<int64_t>((size_t)mg::scan_block_count(N) + 1);
+    w.partials = c.take<int64_t>((size_t)mg::MAX_GRID_WAVES);
+    carve_cl(c, B, N, w.ctr, w.cl);
     w.table = c.take<mg::ImageEntry>(0);
     w.fixed = c.used;
     w.table_cap = bytes > w.fixed ? (int64_t)((bytes - w.fixed) / sizeof(mg::ImageEntry)) : 0;
@@ -133,8 +162,10 @@ struct KnnWs {
     mg::Counters* ctr;
     mg::StructInfo* info;
     int64_t* item_off;
-    int32_t* atom_struct;
+    int64_t* box_off;
     int32_t* ext_list;
+    int64_t* partials;
+    mg::ClWs cl;
     mg::ImageEntry* table;
     int64_t table_cap;
     size_t fixed;
@@ -146,8 +177,10 @@ KnnWs carve_knn(void* ws, size_t bytes, int B, int64_t N) {
     w.ctr = c.take<mg::Counters>(1);
     w.info = c.take<mg::StructInfo>((size_t)B);
     w.item_off = c.take<int64_t>((size_t)B + 1);
-    w.atom_struct = c.take<int32_t>((size_t)N);
+    w.box_off = c.take<int64_t>((size_t)B + 1);
     w.ext_list = c.take<int32_t>((size_t)N);
+    w.partials = c.take<int64_t>((size_t)mg::MAX_GRID_WAVES);
+    carve_cl(c, B, N, w.ctr, w.cl);
     w.table = c.take<mg::ImageEntry>(0);
     w.fixed = c.used;
     w.table_cap = bytes > w.fixed ? (int64_t)((bytes - w.fixed) / sizeof(mg::ImageEntry)) : 0;
@@ -247,37 +280,57 @@ mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_
     const mg_tuning tu = tuning();
     const float c2 = cutoff_threshold(cutoff);
     int64_t* offs = row_ptr ? row_ptr : w.offsets;
-    const int grid = mg::device_cu_count() * (tu.cutoff_wgs_per_cu > 0 ? tu.cutoff_wgs_per_cu : 8);
+    const int grid = sweep_grid(tu.cutoff_wgs_per_cu);
+    const bool sum = B > 0 && N > 0;
     hipError_t e;
     if ((e = mg::launch_zero_report(report, w.ctr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
+    const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
     if ((e = phase("cutoff.bounds", s, [&] {
              return mg::launch_bounds(lattices, batch_ptr, frac, B, N, cutoff, 0, 0.f, w.info, w.ctr,
-                                      report, 0, s);
+                                      report, 0, opts, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("cutoff.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.item_off, w.ctr, report, w.table_cap, s);
+             return mg::launch_struct_scan(B, w.info, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.table_cap, s);
          })) != hipSuccess)
         return hip_fail(e, "plan");
-    if ((e = phase("cutoff.images", s, [&] { return mg::launch_images(B, w.info, w.table, w.table_cap, s); })) !=
+    if ((e = phase("cutoff.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.table, w.table_cap, s); })) !=
         hipSuccess)
         return hip_fail(e, "images");
+    if (cl && (e = phase("cutoff.cells", s, [&] { return mg::launch_cl_build(B, N, frac, batch_ptr, w.info, w.cl, s); })) !=
+                  hipSuccess)
+        return hip_fail(e, "cell lists");
     if ((e = phase("cutoff.count", s, [&] {
-             return mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.table, frac, c2, w.counts, offs,
-                                            capacity, src, dst, image, length, w.ctr, report, grid,
-                                            tu.cutoff_slots, s);
+             hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.table, frac, c2, w.counts, offs,
+                                                    capacity, src, dst, image, length, w.ctr, report, w.partials,
+                                                    grid, tu.cutoff_slots, s);
+             if (r != hipSuccess || !sum) return r;
+             return mg::launch_sum_partials(w.partials, grid * 4, report, s);
          })) != hipSuccess)
         return hip_fail(e, "count");
+    if (cl && (e = phase("cutoff.cells.count", s, [&] {
+                   hipError_t r = mg::launch_cl_cutoff_sweep(0, B, w.info, w.cl, frac, c2, w.counts, offs,
+                                                             capacity, src, dst, image, length, w.ctr, report,
+                                                             w.partials, grid, s);
+                   if (r != hipSuccess || !sum) return r;
+                   return mg::launch_sum_partials(w.partials, grid * 4, report, s);
+               })) != hipSuccess)
+        return hip_fail(e, "cell-list count");
     if ((e = phase("cutoff.scan", s, [&] {
              return mg::launch_scan_counts(w.counts, N, offs, w.bsum, capacity, report, s);
          })) != hipSuccess)
         return hip_fail(e, "scan");
     if ((e = phase("cutoff.fill", s, [&] {
              return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.table, frac, c2, w.counts, offs,
-                                            capacity, src, dst, image, length, w.ctr, report, grid,
-                                            tu.cutoff_slots, s);
+                                            capacity, src, dst, image, length, w.ctr, report, w.partials,
+                                            grid, tu.cutoff_slots, s);
          })) != hipSuccess)
         return hip_fail(e, "fill");
+    if (cl && (e = phase("cutoff.cells.fill", s, [&] {
+                   return mg::launch_cl_cutoff_sweep(1, B, w.info, w.cl, frac, c2, w.counts, offs, capacity, src,
+                                                     dst, image, length, w.ctr, report, w.partials, grid, s);
+               })) != hipSuccess)
+        return hip_fail(e, "cell-list fill");
     return MG_OK;
 }
 
@@ -304,31 +357,45 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const mg_tuning tu = tuning();
     const float lambda = (tu.knn_lambda_x4 > 0 ? tu.knn_lambda_x4 : 6) / 4.0f;
-    const int grid = mg::device_cu_count() * (tu.knn_wgs_per_cu > 0 ? tu.knn_wgs_per_cu : 8);
+    const int grid = sweep_grid(tu.knn_wgs_per_cu);
+    const bool sum = B > 0 && N > 0;
     hipError_t e;
     if ((e = mg::launch_zero_report(report, w.ctr, N * (int64_t)k, s)) != hipSuccess) return hip_fail(e, "zero");
+    const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
     if ((e = phase("knn.bounds", s, [&] {
              return mg::launch_bounds(lattices, batch_ptr, frac, B, N, 0.f, k, lambda, w.info, w.ctr,
-                                      report, 1, s);
+                                      report, 1, opts, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("knn.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.item_off, w.ctr, report, w.table_cap, s);
+             return mg::launch_struct_scan(B, w.info, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.table_cap, s);
          })) != hipSuccess)
         return hip_fail(e, "plan");
-    if ((e = phase("knn.images", s, [&] { return mg::launch_images(B, w.info, w.table, w.table_cap, s); })) !=
+    if ((e = phase("knn.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.table, w.table_cap, s); })) !=
         hipSuccess)
         return hip_fail(e, "images");
-    if ((e = phase("knn.atoms", s, [&] { return mg::launch_atom_struct(batch_ptr, B, N, w.atom_struct, s); })) !=
+    if ((e = phase("knn.atoms", s, [&] { return mg::launch_atom_struct(batch_ptr, B, N, w.cl.atom_struct, s); })) !=
         hipSuccess)
         return hip_fail(e, "atom map");
+    if (cl && (e = phase("knn.cells", s, [&] { return mg::launch_cl_build(B, N, frac, batch_ptr, w.info, w.cl, s); })) !=
+                  hipSuccess)
+        return hip_fail(e, "cell lists");
     if ((e = phase("knn.select", s, [&] {
-             return mg::launch_knn(B, N, k, w.info, w.table, frac, w.atom_struct, src, dst, image, length,
-                                   w.ext_list, w.ctr, report, grid, s);
+             hipError_t r = mg::launch_knn(B, N, k, w.info, w.item_off, w.table, frac, src, dst, image, length,
+                                           w.ext_list, w.ctr, report, w.partials, grid, s);
+             if (r != hipSuccess || !sum) return r;
+             return mg::launch_sum_partials(w.partials, grid * 4, report, s);
          })) != hipSuccess)
         return hip_fail(e, "knn");
+    if (cl && (e = phase("knn.cells.select", s, [&] {
+                   hipError_t r = mg::launch_cl_knn(B, k, w.info, w.cl, frac, src, dst, image, length, w.ext_list,
+                                                    w.ctr, report, w.partials, grid, s);
+                   if (r != hipSuccess || !sum) return r;
+                   return mg::launch_sum_partials(w.partials, grid * 4, report, s);
+               })) != hipSuccess)
+        return hip_fail(e, "cell-list knn");
     if ((e = phase("knn.extended", s, [&] {
-             return mg::launch_knn_extended(B, N, k, w.info, frac, w.atom_struct, src, dst, image, length,
+             return mg::launch_knn_extended(B, N, k, w.info, frac, w.cl.atom_struct, src, dst, image, length,
                                             w.ext_list, w.ctr, report, mg::device_cu_count() * 2, s);
          })) != hipSuccess)
         return hip_fail(e, "knn extended");

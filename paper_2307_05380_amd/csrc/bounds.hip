@@ -40,7 +40,7 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
                                                const float* __restrict__ frac, int B, float radius,
                                                int knn_k, float knn_lambda,
                                                StructInfo* __restrict__ info,
-                                               mg_report* __restrict__ rep, int mode) {
+                                               mg_report* __restrict__ rep, int mode, int opts) {
     const int b = blockIdx.x;
     if (b >= B) return;
     const int lane = threadIdx.x;
@@ -91,6 +91,37 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     }
     // conservative radius for pruning: covers FP32 rounding of the sweep
     const double Rb = R * (1.0 + 1e-6) + 1e-3 + 1e-5 * lsum;
+    const bool valid = n > 0 && !(flags & (MG_FLAG_SINGULAR | MG_FLAG_NONFINITE));
+    // Cell lists: m_k bins of thickness h_k / m_k >= Rb along every direction
+    // (h_k = |det| / |a_{k+1} x a_{k+2}| is the spacing of the lattice planes),
+    // so every neighbour within Rb lies in the 27 bins around the source's bin;
+    // m_k >= 3 keeps those 27 bins distinct. Bins are capped at 2n + 64.
+    int cm[3] = {0, 0, 0};
+    double wcl = 0.0;
+    bool use_cl = false;
+    if (valid && !(opts & MG_OPT_CELL_LIST_OFF) && (n >= CL_MIN_ATOMS || (opts & MG_OPT_CELL_LIST_FORCE))) {
+        double h[3];
+        bool ok = true;
+        for (int k = 0; k < 3; ++k) {
+            h[k] = fabs(det) / sqrt(c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2]);
+            const double mk = floor(h[k] / Rb);
+            ok &= mk >= 3.0;
+            cm[k] = ok ? (int)fmin(mk, 1024.0) : 0;
+        }
+        if (ok) {
+            // shrink the largest direction until the bins fit 2n + 64 (27 always fits)
+            const double cap = 2.0 * n + 64.0;
+            for (int it = 0; it < 4096; ++it) {
+                const double tot = (double)cm[0] * cm[1] * cm[2];
+                if (tot <= cap) break;
+                const int a = (cm[0] >= cm[1] && cm[0] >= cm[2]) ? 0 : (cm[1] >= cm[2] ? 1 : 2);
+                const int shrunk = max(3, (int)floor(cm[a] * cap / tot));
+                cm[a] = shrunk < cm[a] ? shrunk : cm[a] - 1;
+            }
+            wcl = fmin(fmin(h[0] / cm[0], h[1] / cm[1]), h[2] / cm[2]);
+            use_cl = true;
+        }
+    }
     int64_t box = 1;
     for (int k = 0; k < 3; ++k) {
         double r = sqrt(c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2]) / fabs(det);
@@ -101,6 +132,10 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
         }
         si.nk[k] = (int)h;
         box *= 2 * (int64_t)si.nk[k] + 1;
+    }
+    if (use_cl) {
+        flags &= ~(uint32_t)MG_FLAG_RANGE;   // the image box is not used
+        box = 0;
     }
     if (n == 0 || (flags & (MG_FLAG_SINGULAR | MG_FLAG_NONFINITE | MG_FLAG_RANGE))) box = 0;
 
@@ -122,19 +157,27 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     }
     // items stay planned for skipped structures (box == 0): the sweeps then
     // write empty results for their sources
-    si.pad = 0;
+    si.mode = use_cl ? 1 : 0;
+    si.m[0] = cm[0];
+    si.m[1] = cm[1];
+    si.m[2] = cm[2];
+    si.nbins = use_cl ? cm[0] * cm[1] * cm[2] : 0;
+    si.bin_off = 0;
+    si.cl_items = use_cl ? n : 0;
+    si.wcl = (float)(wcl * (1.0 - 1e-6) - 1e-3);
+    if (use_cl) si.groups = 0;
     info[b] = si;
     if (flags) atomicOr(&rep->flags, flags);
 }
 
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
                          int64_t N, float radius, int knn_k, float knn_lambda, StructInfo* info,
-                         Counters* ctr, mg_report* report, int mode, hipStream_t s) {
+                         Counters* ctr, mg_report* report, int mode, int opts, hipStream_t s) {
     (void)N;
     (void)ctr;
     if (B == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bounds, dim3(B), dim3(64), 0, s, lattices, batch_ptr, frac, B, radius,
-                       knn_k, knn_lambda, info, report, mode);
+                       knn_k, knn_lambda, info, report, mode, opts);
     return hipGetLastError();
 }
 
@@ -145,70 +188,80 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
 // box does not fit the table capacity are skipped and flagged.
 __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restrict__ info,
                                                       int64_t* __restrict__ item_off,
+                                                      int64_t* __restrict__ cl_off,
+                                                      int64_t* __restrict__ box_off,
                                                       Counters* __restrict__ ctr,
                                                       mg_report* __restrict__ rep,
                                                       int64_t capacity) {
-    __shared__ int64_t s_box[16], s_item[16];
-    __shared__ int64_t s_base_box, s_base_item;
+    __shared__ int64_t s_part[4][16];
+    __shared__ int64_t s_base[4];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    if (t == 0) {
-        s_base_box = 0;
-        s_base_item = 0;
-    }
+    if (t < 4) s_base[t] = 0;
     __syncthreads();
     bool overflow = false;
     for (int base = 0; base < B; base += 1024) {
         const int b = base + t;
-        int64_t box = 0, items = 0;
+        // scanned quantities: image box, image items, cell-list items, bins
+        int64_t v[4] = {0, 0, 0, 0};
         if (b < B) {
-            box = info[b].box;
-            items = info[b].groups;
+            v[0] = info[b].box;
+            v[1] = info[b].groups;
+            v[2] = info[b].cl_items;
+            v[3] = info[b].nbins;
         }
-        int64_t ib = wave_incl_scan_i64(box);
-        int64_t ii = wave_incl_scan_i64(items);
-        if (lane == 63) {
-            s_box[w] = ib;
-            s_item[w] = ii;
+        int64_t inc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            inc[q] = wave_incl_scan_i64(v[q]);
+            if (lane == 63) s_part[q][w] = inc[q];
         }
         __syncthreads();
-        int64_t pb = s_base_box, pi = s_base_item;
-        for (int q = 0; q < w; ++q) {
-            pb += s_box[q];
-            pi += s_item[q];
+        int64_t pre[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pre[q] = s_base[q];
+            for (int r = 0; r < w; ++r) pre[q] += s_part[q][r];
         }
         if (b < B) {
-            const int64_t off = pb + ib - box;
-            const bool fits = off + box <= capacity;
+            const int64_t off = pre[0] + inc[0] - v[0];
             info[b].img_off = off;
-            if (!fits && box > 0) {
+            box_off[b] = off;
+            if (off + v[0] > capacity && v[0] > 0) {
                 overflow = true;
                 info[b].box = 0;           // skipped: no images; its items write empty results
                 info[b].flags |= MG_FLAG_IMAGES;
             }
-            item_off[b] = pi + ii - items;
+            item_off[b] = pre[1] + inc[1] - v[1];
+            if (cl_off) cl_off[b] = pre[2] + inc[2] - v[2];
+            info[b].bin_off = pre[3] + inc[3] - v[3];
         }
         __syncthreads();
         if (t == 1023) {
-            s_base_box = pb + ib;
-            s_base_item = pi + ii;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_base[q] = pre[q] + inc[q];
         }
         __syncthreads();
     }
     if (overflow) atomicOr(&rep->flags, (uint32_t)MG_FLAG_IMAGES);
     if (t == 0) {
-        item_off[B] = s_base_item;
-        ctr->total_box = s_base_box;
-        ctr->total_items = s_base_item;
-        rep->images_needed = s_base_box;
+        item_off[B] = s_base[1];
+        if (cl_off) cl_off[B] = s_base[2];
+        box_off[B] = s_base[0];
+        ctr->total_box = s_base[0];
+        ctr->total_items = s_base[1];
+        ctr->total_cl_items = s_base[2];
+        ctr->total_bins = s_base[3];
+        rep->images_needed = s_base[0];
     }
 }
 
 // Skipped structures keep their planned item ranges, so item_off stays a plain
 // scan of the planned items.
-hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, Counters* ctr,
-                              mg_report* report, int64_t image_capacity, hipStream_t s) {
-    hipLaunchKernelGGL(k_struct_scan, dim3(1), dim3(1024), 0, s, B, info, item_off, ctr, report,
-                       image_capacity);
+hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, int64_t* cl_off,
+                              int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_struct_scan, dim3(1), dim3(1024), 0, s, B, info, item_off, cl_off, box_off, ctr,
+                       report, image_capacity);
     return hipGetLastError();
 }
 
@@ -268,14 +321,100 @@ __device__ double cell_min_dist2(const double G[3][3], int t0, int t1, int t2) {
     return best;
 }
 
-// One workgroup (256 threads) per structure: enumerate the box in
-// lexicographic (t0, t1, t2) order, keep the cells within R, compact them in
-// order into the table and record where t = 0 landed.
-__global__ __launch_bounds__(256) void k_images(int B, StructInfo* __restrict__ info,
-                                                ImageEntry* __restrict__ table,
-                                                int64_t capacity) {
+// Every box image of the batch, one thread each: the FP64 shift t.L and a keep
+// flag, written into the structure's box-sized slot of the table (tpk = -1 for
+// images dropped). Cheap bounds decide most images: the slab bound
+// (|t_k| - 1/2) h_k and the sphere bound |t.L| - (half cell diagonal) reject,
+// a cell centre inside the ball accepts; the exact distance decides the rest.
+__global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __restrict__ info,
+                                                     const int64_t* __restrict__ box_off,
+                                                     const Counters* __restrict__ ctr,
+                                                     ImageEntry* __restrict__ table, int64_t capacity) {
+    const int64_t total = min(ctr->total_box, capacity);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+        int lo = 0, hi = B;   // box_off[lo] <= idx < box_off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (box_off[mid] <= idx) lo = mid;
+            else hi = mid;
+        }
+        const StructInfo* si = info + lo;
+        if (si->box == 0) continue;       // skipped structure (its slot is never read)
+        const int64_t loc = idx - box_off[lo];
+        const int n0 = si->nk[0], n1 = si->nk[1], n2 = si->nk[2];
+        const int w1 = 2 * n1 + 1, w2 = 2 * n2 + 1;
+        const int t2 = (int)(loc % w2) - n2;
+        const int64_t r = loc / w2;
+        const int t1 = (int)(r % w1) - n1;
+        const int t0 = (int)(r / w1) - n0;
+        double L[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) L[q] = si->L[q];
+        const double R = (double)si->R;
+        const double cx = t0 * L[0] + t1 * L[3] + t2 * L[6];
+        const double cy = t0 * L[1] + t1 * L[4] + t2 * L[7];
+        const double cz = t0 * L[2] + t1 * L[5] + t2 * L[8];
+        bool keep;
+        const double c2 = cx * cx + cy * cy + cz * cz;
+        if ((t0 | t1 | t2) == 0 || c2 <= R * R) {
+            keep = true;
+        } else {
+            // slab bound
+            double cof[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double* u = L + 3 * ((a + 1) % 3);
+                const double* w = L + 3 * ((a + 2) % 3);
+                cof[a][0] = u[1] * w[2] - u[2] * w[1];
+                cof[a][1] = u[2] * w[0] - u[0] * w[2];
+                cof[a][2] = u[0] * w[1] - u[1] * w[0];
+            }
+            const double det = fabs(L[0] * cof[0][0] + L[1] * cof[0][1] + L[2] * cof[0][2]);
+            const int tt[3] = {t0, t1, t2};
+            double slab = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double h = det / sqrt(cof[a][0] * cof[a][0] + cof[a][1] * cof[a][1] + cof[a][2] * cof[a][2]);
+                slab = fmax(slab, (fabs((double)tt[a]) - 0.5) * h);
+            }
+            // sphere bound: half the longest cell diagonal
+            double rh2 = 0.0;
+#pragma unroll
+            for (int cnr = 0; cnr < 4; ++cnr) {
+                const double s1 = (cnr & 1) ? 0.5 : -0.5, s2 = (cnr & 2) ? 0.5 : -0.5;
+                const double dx = 0.5 * L[0] + s1 * L[3] + s2 * L[6];
+                const double dy = 0.5 * L[1] + s1 * L[4] + s2 * L[7];
+                const double dz = 0.5 * L[2] + s1 * L[5] + s2 * L[8];
+                rh2 = fmax(rh2, dx * dx + dy * dy + dz * dz);
+            }
+            if (slab >= R || sqrt(c2) - sqrt(rh2) >= R) {
+                keep = false;
+            } else {
+                double G[3][3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        G[a][b] = L[3 * a] * L[3 * b] + L[3 * a + 1] * L[3 * b + 1] + L[3 * a + 2] * L[3 * b + 2];
+                keep = cell_min_dist2(G, t0, t1, t2) < R * R;
+            }
+        }
+        ImageEntry e;
+        e.sx = (float)cx;
+        e.sy = (float)cy;
+        e.sz = (float)cz;
+        e.tpk = keep ? pack_t(t0, t1, t2) : -1;
+        table[idx] = e;
+    }
+}
+
+// One workgroup per structure: stable in-place compaction of the kept images
+// (lexicographic order is kept) and the table index of t = 0.
+__global__ __launch_bounds__(256) void k_image_compact(StructInfo* __restrict__ info,
+                                                       ImageEntry* __restrict__ table,
+                                                       int64_t capacity) {
     __shared__ uint32_t s_cnt[4];
-    __shared__ double sL[9];
     __shared__ int s_total;
     const int b = blockIdx.x;
     const int t = threadIdx.x, w = t >> 6;
@@ -288,28 +427,17 @@ __global__ __launch_bounds__(256) void k_images(int B, StructInfo* __restrict__ 
         }
         return;
     }
-    if (t < 9) sL[t] = info[b].L[t];
     if (t == 0) s_total = 0;
-    const int n0 = info[b].nk[0], n1 = info[b].nk[1], n2 = info[b].nk[2];
-    const int w1 = 2 * n1 + 1, w2 = 2 * n2 + 1;
-    const double R = (double)info[b].R;
-    const double R2 = R * R;
     __syncthreads();
-    double G[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            G[i][j] = sL[3 * i] * sL[3 * j] + sL[3 * i + 1] * sL[3 * j + 1] + sL[3 * i + 2] * sL[3 * j + 2];
-    ImageEntry* out = table + off;
+    ImageEntry* slot = table + off;
+    const int32_t zero_pk = pack_t(0, 0, 0);
     for (int64_t base = 0; base < box; base += 256) {
         const int64_t idx = base + t;
+        ImageEntry e;
         bool keep = false;
-        int t0 = 0, t1 = 0, t2 = 0;
         if (idx < box) {
-            t2 = (int)(idx % w2) - n2;
-            const int64_t r = idx / w2;
-            t1 = (int)(r % w1) - n1;
-            t0 = (int)(r / w1) - n0;
-            keep = (t0 == 0 && t1 == 0 && t2 == 0) || cell_min_dist2(G, t0, t1, t2) < R2;
+            e = slot[idx];
+            keep = e.tpk >= 0;
         }
         const uint64_t m = ballot(keep);
         if ((t & 63) == 0) s_cnt[w] = (uint32_t)__popcll(m);
@@ -318,13 +446,8 @@ __global__ __launch_bounds__(256) void k_images(int B, StructInfo* __restrict__ 
         for (int q = 0; q < w; ++q) pos += (int)s_cnt[q];
         pos += (int)mbcnt(m);
         if (keep) {
-            ImageEntry e;
-            e.sx = (float)(t0 * sL[0] + t1 * sL[3] + t2 * sL[6]);
-            e.sy = (float)(t0 * sL[1] + t1 * sL[4] + t2 * sL[7]);
-            e.sz = (float)(t0 * sL[2] + t1 * sL[5] + t2 * sL[8]);
-            e.tpk = pack_t(t0, t1, t2);
-            out[pos] = e;
-            if (t0 == 0 && t1 == 0 && t2 == 0) info[b].zero_img = pos;
+            slot[pos] = e;
+            if (e.tpk == zero_pk) info[b].zero_img = pos;
         }
         __syncthreads();
         if (t == 0) s_total += (int)(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
@@ -333,10 +456,12 @@ __global__ __launch_bounds__(256) void k_images(int B, StructInfo* __restrict__ 
     if (t == 0) info[b].images = s_total;
 }
 
-hipError_t launch_images(int B, StructInfo* info, ImageEntry* table, int64_t image_capacity,
-                         hipStream_t s) {
+hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr,
+                         ImageEntry* table, int64_t image_capacity, hipStream_t s) {
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_images, dim3(B), dim3(256), 0, s, B, info, table, image_capacity);
+    const int grid = device_cu_count() * 8;
+    hipLaunchKernelGGL(k_image_flags, dim3(grid), dim3(256), 0, s, B, info, box_off, ctr, table, image_capacity);
+    hipLaunchKernelGGL(k_image_compact, dim3(B), dim3(256), 0, s, info, table, image_capacity);
     return hipGetLastError();
 }
 

@@ -23,8 +23,8 @@
 // Every wave-level decision (loop bounds, stack size, threshold, the sort
 // branch) is taken on values made explicitly uniform with readfirstlane, every
 // helper that shuffles across lanes is force-inlined (no device calls), work is
-// pulled with wave_ticket (the first active lane takes the ticket, so every
-// iteration advances the queue) and the extended search is capped at
+// handed out cyclically over the grid's waves (loops bounded by the item
+// count) and the extended search is capped at
 // KNN_MAX_ATTEMPTS radius doublings: every wave reaches its exit.
 #include "mg_internal.h"
 
@@ -153,12 +153,42 @@ __device__ __forceinline__ void image_t(const ImageSet& S, uint32_t img, int& t0
     }
 }
 
+// The ordered stack of one wave: cnt keys in buf, threshold tau2 on l^2.
+struct Stack {
+    int cnt;
+    float tau2;
+};
+
+// Push this lane's candidate (pass, l2, ordinal lo) onto the stack; when the
+// stack would overflow, keep the k smallest keys and lower the threshold first.
+__device__ __forceinline__ void stack_push(Stack& st, bool pass, float l2, uint32_t lo, int k, uint64_t* buf,
+                                           int lane) {
+    uint64_t m = ballot(pass);
+    int c = ufirst(__popcll(m));
+    if (c == 0) return;
+    if (st.cnt + c > KNN_CAP) {
+        wave_lds_sync();
+        const uint64_t v0 = sorted_rank<KNN_CAP / WAVE>(buf, st.cnt, lane);
+        wave_lds_sync();
+        if (lane < k) buf[lane] = v0;
+        const uint64_t kth = readlane_u64(v0, k - 1);
+        st.tau2 = ufirstf(fminf(st.tau2, thr_from_len(key_len(kth))));
+        st.cnt = k;
+        pass = pass && l2 < st.tau2;
+        m = ballot(pass);
+        c = ufirst(__popcll(m));
+        wave_lds_sync();
+    }
+    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(sqrtf(l2)) << 32) | (uint64_t)lo;
+    st.cnt = ufirst(st.cnt + c);
+}
+
 // Stream every candidate (j, t) of source il through the ordered stack with the
 // initial threshold tau2. Returns the uniform number of keys left in buf.
 __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int n, int il, int64_t atom0,
                                        const double* L, double xi0, double xi1, double xi2,
                                        const float* __restrict__ frac, float4* P, uint64_t* buf, int lane) {
-    int cnt = 0;
+    Stack st{0, tau2};
     const uint32_t I = S.I;
     const float invI = 1.0f / (float)I;
     for (int jc0 = 0; jc0 < n; jc0 += KNN_JC) {
@@ -205,33 +235,13 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
                 }
                 const float dx = pp.x + sx, dy = pp.y + sy, dz = pp.z + sz;
                 l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                pass = l2 < tau2 && !(__float_as_int(pp.w) != 0 && (int)img == S.zidx);
+                pass = l2 < st.tau2 && !(__float_as_int(pp.w) != 0 && (int)img == S.zidx);
             }
-            uint64_t m = ballot(pass);
-            int c = ufirst(__popcll(m));
-            if (c == 0) continue;
-            if (cnt + c > KNN_CAP) {
-                // the stack is full: keep the k smallest keys, lower the threshold
-                wave_lds_sync();
-                const uint64_t v0 = sorted_rank<KNN_CAP / WAVE>(buf, cnt, lane);
-                wave_lds_sync();
-                if (lane < k) buf[lane] = v0;
-                const uint64_t kth = readlane_u64(v0, k - 1);
-                tau2 = ufirstf(fminf(tau2, thr_from_len(key_len(kth))));
-                cnt = k;
-                pass = pass && l2 < tau2;
-                m = ballot(pass);
-                c = ufirst(__popcll(m));
-                wave_lds_sync();
-            }
-            if (pass)
-                buf[cnt + (int)mbcnt(m)] =
-                    ((uint64_t)__float_as_uint(sqrtf(l2)) << 32) | (uint64_t)((uint32_t)(jc0 + jl) * I + img);
-            cnt = ufirst(cnt + c);
+            stack_push(st, pass, l2, (uint32_t)(jc0 + jl) * I + img, k, buf, lane);
         }
     }
     wave_lds_sync();
-    return cnt;
+    return st.cnt;
 }
 
 // Sort the stack and write the k edges of source i (requires cnt >= k).
@@ -262,29 +272,37 @@ __device__ __forceinline__ void emit(const ImageSet& S, int cnt, int k, int64_t 
 
 }  // namespace
 
-// First pass: every source, with its structure's image table (radius R0).
-__global__ __launch_bounds__(256) void k_knn_first(int64_t N, int k, const StructInfo* __restrict__ info,
+// First pass: the sources of image-sweep structures, each with its
+// structure's image table (radius R0). Items: item_off scans the sources of
+// those structures (skipped structures keep their items and get invalid rows).
+__global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInfo* __restrict__ info,
+                                                   const int64_t* __restrict__ item_off,
                                                    const ImageEntry* __restrict__ table,
                                                    const float* __restrict__ frac,
-                                                   const int32_t* __restrict__ atom_struct,
                                                    int32_t* __restrict__ src, int32_t* __restrict__ dst,
                                                    int32_t* __restrict__ image, float* __restrict__ length,
                                                    int32_t* __restrict__ ext_list, Counters* __restrict__ ctr,
-                                                   mg_report* __restrict__ rep) {
+                                                   mg_report* __restrict__ rep, int64_t* __restrict__ partials) {
     __shared__ KnnShared sh;
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
     float4* P = sh.p[wv];
     uint64_t* buf = sh.buf[wv];
     const uint32_t bad = MG_FLAG_SINGULAR | MG_FLAG_NONFINITE | MG_FLAG_RANGE | MG_FLAG_IMAGES;
-    for (;;) {
-        const int64_t i = (int64_t)wave_ticket(&ctr->ticket[2]);
-        if (i >= N) break;
-        const int s = ufirst(atom_struct[i]);
-        const StructInfo* si = info + s;
+    const int64_t total = item_off[B];
+    int64_t wave_cand = 0;
+    for (int64_t q = grid_wave(); q < total; q += grid_waves()) {
+        int lo = 0, hi = B;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (item_off[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        const StructInfo* si = info + lo;
         const int n = si->n;
         const int64_t atom0 = si->atom0;
-        const int il = (int)(i - atom0);
+        const int il = (int)(q - item_off[lo]);
+        const int64_t i = atom0 + il;
         const bool ok = si->box != 0 && si->images > 0 && si->zero_img >= 0 && (si->flags & bad) == 0;
         if (!ok) {
             write_invalid(i, k, lane, src, dst, image, length);
@@ -304,6 +322,7 @@ __global__ __launch_bounds__(256) void k_knn_first(int64_t N, int k, const Struc
             write_invalid(i, k, lane, src, dst, image, length);
             continue;
         }
+        wave_cand += (int64_t)n * S.I;
         const double R = (double)si->Rs;
         const float tau2 = (float)(R * R) * (1.0f + 3e-6f);
         const int cnt = collect(S, tau2, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
@@ -316,6 +335,117 @@ __global__ __launch_bounds__(256) void k_knn_first(int64_t N, int k, const Struc
             atomicOr(&rep->flags, (uint32_t)MG_FLAG_KNN_EXTENDED);
         }
     }
+    if (lane == 0) partials[grid_wave()] = wave_cand;
+}
+
+// Cell-list pass: the sources of cell-list structures, candidates from the 27
+// bins around the source's bin (see celllist.hip for the layout). Key ordinal:
+// local dst * 32768 + (t0+16, t1+16, t2+16) in 5 bits each, which is the
+// (dst, t) order. The stencil covers every candidate within wcl, so a stack of
+// >= k keys under the threshold wcl^2 is exact; otherwise (or if an image
+// component falls outside [-16, 15]) the source goes to the extended pass.
+__global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* __restrict__ info, ClWs w,
+                                                const float* __restrict__ frac,
+                                                int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                                                int32_t* __restrict__ image, float* __restrict__ length,
+                                                int32_t* __restrict__ ext_list, Counters* __restrict__ ctr,
+                                                mg_report* __restrict__ rep, int64_t* __restrict__ partials) {
+    __shared__ KnnShared sh;
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    uint64_t* buf = sh.buf[wv];
+    const int64_t total = w.cl_off[B];
+    int64_t wave_cand = 0;
+    for (int64_t q = grid_wave(); q < total; q += grid_waves()) {
+        int lo = 0, hi = B;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (w.cl_off[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        const StructInfo* si = info + lo;
+        const int64_t atom0 = si->atom0;
+        const int64_t i = atom0 + (q - w.cl_off[lo]);
+        const int m[3] = {si->m[0], si->m[1], si->m[2]};
+        double L[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) L[r] = si->L[r];
+        const int lb = ufirst(w.atom_bin[i]);
+        const int b2 = lb % m[2], b1 = (lb / m[2]) % m[1], b0 = lb / (m[2] * m[1]);
+        const int32_t shi = ufirst(w.atom_shift[i]);
+        const int si0 = unpack_t0(shi), si1 = unpack_t1(shi), si2 = unpack_t2(shi);
+        const double x0 = frac[3 * i], x1 = frac[3 * i + 1], x2 = frac[3 * i + 2];
+        const double xw0 = x0 - floor(x0), xw1 = x1 - floor(x1), xw2 = x2 - floor(x2);
+        const int64_t* bst = w.bin_start + si->bin_off;
+        const float wc = si->wcl;
+        Stack st{0, wc * wc};
+        int overflow = si->n >= 131072 ? 1 : 0;   // local dst index must fit 17 bits
+        int64_t ncand = 0;
+        for (int d = 0; d < 27; ++d) {
+            int nb0 = b0 + d / 9 - 1, nb1 = b1 + (d / 3) % 3 - 1, nb2 = b2 + d % 3 - 1;
+            const int u0 = nb0 < 0 ? -1 : (nb0 >= m[0] ? 1 : 0);
+            const int u1 = nb1 < 0 ? -1 : (nb1 >= m[1] ? 1 : 0);
+            const int u2 = nb2 < 0 ? -1 : (nb2 >= m[2] ? 1 : 0);
+            nb0 -= u0 * m[0];
+            nb1 -= u1 * m[1];
+            nb2 -= u2 * m[2];
+            const int nb = (nb0 * m[1] + nb1) * m[2] + nb2;
+            const double f0 = (double)nb0 / m[0] + u0 - xw0;
+            const double f1 = (double)nb1 / m[1] + u1 - xw1;
+            const double f2 = (double)nb2 / m[2] + u2 - xw2;
+            const float qx = (float)(f0 * L[0] + f1 * L[3] + f2 * L[6]);
+            const float qy = (float)(f0 * L[1] + f1 * L[4] + f2 * L[7]);
+            const float qz = (float)(f0 * L[2] + f1 * L[5] + f2 * L[8]);
+            const int64_t p0 = bst[nb], p1 = bst[nb + 1];
+            ncand += p1 - p0;
+            for (int64_t pb = p0; pb < p1; pb += WAVE) {
+                const int64_t p = pb + lane;
+                bool pass = false;
+                float l2 = 0.0f;
+                uint32_t ord = 0;
+                if (p < p1) {
+                    const float4 e = w.slot_pos[p];
+                    const int32_t j = __float_as_int(e.w);
+                    const float dx = e.x + qx, dy = e.y + qy, dz = e.z + qz;
+                    l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    pass = l2 < st.tau2 && (int64_t)j != i;
+                    if (pass) {
+                        const int32_t shj = w.atom_shift[j];
+                        const int t0 = u0 - unpack_t0(shj) + si0, t1 = u1 - unpack_t1(shj) + si1,
+                                  t2 = u2 - unpack_t2(shj) + si2;
+                        const bool fits = t0 >= -16 && t0 <= 15 && t1 >= -16 && t1 <= 15 && t2 >= -16 && t2 <= 15;
+                        overflow |= fits ? 0 : 1;
+                        ord = (uint32_t)(j - atom0) * 32768u + (uint32_t)(((t0 + 16) * 32 + (t1 + 16)) * 32 + (t2 + 16));
+                        pass = fits;
+                    }
+                }
+                stack_push(st, pass, l2, ord, k, buf, lane);
+            }
+        }
+        wave_lds_sync();
+        wave_cand += ncand;
+        const int any_overflow = ufirst(ballot(overflow != 0) != 0 ? 1 : 0);
+        if (st.cnt >= k && !any_overflow) {
+            const uint64_t key = sorted_head(buf, st.cnt, lane);
+            if (lane < k) {
+                const uint32_t qv = (uint32_t)key;
+                const uint32_t jl = qv >> 15, tc = qv & 32767u;
+                const int64_t e = i * k + lane;
+                src[e] = (int32_t)i;
+                dst[e] = (int32_t)(atom0 + jl);
+                image[3 * e] = (int)(tc >> 10) - 16;
+                image[3 * e + 1] = (int)((tc >> 5) & 31u) - 16;
+                image[3 * e + 2] = (int)(tc & 31u) - 16;
+                length[e] = key_len(key);
+            }
+        } else if (lane == 0) {
+            const uint32_t pos = atomicAdd(&ctr->knn2_count, 1u);
+            ext_list[pos] = (int32_t)i;
+            atomicAdd((unsigned long long*)&rep->knn_extended, 1ull);
+            atomicOr(&rep->flags, (uint32_t)MG_FLAG_KNN_EXTENDED);
+        }
+    }
+    if (lane == 0) partials[grid_wave()] = wave_cand;
 }
 
 // Extended pass: the queued sources, full image boxes of radius 2 R0, 4 R0, ...
@@ -332,9 +462,7 @@ __global__ __launch_bounds__(256) void k_knn_extended(int k, const StructInfo* _
     float4* P = sh.p[wv];
     uint64_t* buf = sh.buf[wv];
     const uint32_t total = (uint32_t)ufirst((int)ctr->knn2_count);
-    for (;;) {
-        const uint32_t q = wave_ticket(&ctr->ticket[3]);
-        if (q >= total) break;
+    for (int64_t q = grid_wave(); q < (int64_t)total; q += grid_waves()) {
         const int64_t i = (int64_t)ufirst(ext_list[q]);
         const int s = ufirst(atom_struct[i]);
         const StructInfo* si = info + s;
@@ -393,14 +521,23 @@ __global__ __launch_bounds__(256) void k_knn_extended(int k, const StructInfo* _
     }
 }
 
-hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const ImageEntry* table,
-                      const float* frac, const int32_t* atom_struct, int32_t* src, int32_t* dst,
+hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const int64_t* item_off,
+                      const ImageEntry* table, const float* frac, int32_t* src, int32_t* dst,
                       int32_t* image, float* length, int32_t* ext_list, Counters* ctr,
-                      mg_report* report, int grid, hipStream_t s) {
-    (void)B;
-    if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_knn_first, dim3(grid), dim3(256), 0, s, N, k, info, table, frac, atom_struct, src,
-                       dst, image, length, ext_list, ctr, report);
+                      mg_report* report, int64_t* partials, int grid, hipStream_t s) {
+    if (N == 0 || B == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_knn_first, dim3(grid), dim3(256), 0, s, B, k, info, item_off, table, frac, src, dst,
+                       image, length, ext_list, ctr, report, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_cl_knn(int B, int k, const StructInfo* info, const ClWs& w, const float* frac,
+                         int32_t* src, int32_t* dst, int32_t* image, float* length,
+                         int32_t* ext_list, Counters* ctr, mg_report* report, int64_t* partials,
+                         int grid, hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_knn_cl, dim3(grid), dim3(256), 0, s, B, k, info, w, frac, src, dst, image, length,
+                       ext_list, ctr, report, partials);
     return hipGetLastError();
 }
 

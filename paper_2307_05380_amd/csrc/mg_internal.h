@@ -43,17 +43,29 @@ struct alignas(16) StructInfo {
     float R;            // radius the table was built for, with rounding margin (Angstrom)
     float Rs;           // search radius before the margin (Angstrom)
     uint32_t flags;     // MG_FLAG_* of this structure
-    int32_t pad;
+    int32_t mode;       // 0: pair x image sweep, 1: cell lists
+    int32_t m[3];       // cell lists: bins per lattice direction
+    int32_t nbins;      // cell lists: m0 * m1 * m2
+    int64_t bin_off;    // cell lists: first bin in the global bin arrays
+    int32_t cl_items;   // cell lists: work items (one per source)
+    float wcl;          // cell lists: radius covered by the 27-bin stencil (Angstrom)
 };
+
+constexpr int CL_MIN_ATOMS = 512;   // structures smaller than this use the image sweep
 
 // Scratch counters at the head of every workspace.
 struct alignas(64) Counters {
-    uint32_t ticket[8];        // work-queue tickets of persistent kernels
+    uint32_t spare[8];
     uint32_t knn2_count;       // sources queued for the extended KNN search
     uint32_t pad[7];
     int64_t total_box;         // sum of box sizes (image entries needed)
-    int64_t total_items;       // work items of the sweep
+    int64_t total_items;       // work items of the image sweep
+    int64_t total_cl_items;    // work items of the cell-list sweep
+    int64_t total_bins;        // cell-list bins of the batch
 };
+
+// Capacity of the cell-list bin arrays: bins are capped at 2n + 64 per structure.
+inline int64_t cl_bin_capacity(int B, int64_t N) { return 2 * N + 64 * (int64_t)B + 1; }
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -89,16 +101,14 @@ __device__ inline int wave_incl_scan_i32(int v) {
     return v;
 }
 
-// Next item of a work queue for the calling wave: the first active lane (always
-// active, whatever the exec mask) takes one ticket and broadcasts it, so every
-// call advances the queue. Returns a wave-uniform value.
-__device__ __forceinline__ uint32_t wave_ticket(uint32_t* counter) {
-    const uint64_t ex = __builtin_amdgcn_read_exec();
-    const int leader = __builtin_ctzll(ex);
-    uint32_t t = 0;
-    if (lane_id() == leader) t = atomicAdd(counter, 1u);
-    return (uint32_t)__builtin_amdgcn_readlane((int)t, leader);
+// Persistent kernels hand out work items cyclically: wave w of the grid takes
+// items w, w + W, w + 2W, ... (W waves in the grid). Consecutive items (the
+// sources of one structure) land on different waves, which balances uneven
+// structures without a shared counter; every loop is bounded by the item count.
+__device__ __forceinline__ int64_t grid_wave() {
+    return (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
 }
+__device__ __forceinline__ int64_t grid_waves() { return (int64_t)gridDim.x * (blockDim.x / WAVE); }
 
 // Orders this wave's LDS writes before its later LDS reads (lanes exchange data
 // through LDS without a workgroup barrier).
@@ -154,22 +164,51 @@ namespace mg {
 
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
                          int64_t N, float radius, int knn_k, float knn_lambda, StructInfo* info,
-                         Counters* ctr, mg_report* report, int mode, hipStream_t s);
-hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, Counters* ctr,
-                              mg_report* report, int64_t image_capacity, hipStream_t s);
-hipError_t launch_images(int B, StructInfo* info, ImageEntry* table, int64_t image_capacity,
-                         hipStream_t s);
+                         Counters* ctr, mg_report* report, int mode, int opts, hipStream_t s);
+hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, int64_t* cl_off,
+                              int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
+                              hipStream_t s);
+struct ClWs {
+    int64_t* cl_off;        // [B+1] scan of cell-list items
+    uint32_t* bin_count;    // [cap] atoms per bin
+    uint32_t* bin_fill;     // [cap] scatter cursors
+    int64_t* bin_start;     // [cap+1] first slot of every bin
+    int64_t* bsum;          // scan partials
+    int32_t* atom_bin;      // [N] bin of every atom (local to its structure)
+    int32_t* atom_shift;    // [N] packed floor(x) of every atom
+    int32_t* slot_atom;     // [N] atoms in bin order
+    float4* slot_pos;       // [N] position relative to the bin origin (xyz) and atom (w)
+    int32_t* atom_struct;   // [N] structure of every atom
+    Counters* ctr;          // workspace counters (bin totals)
+    int64_t cap;            // bin capacity
+};
+hipError_t launch_cl_build(int B, int64_t N, const float* frac, const int64_t* batch_ptr,
+                           const StructInfo* info, const ClWs& w, hipStream_t s);
+hipError_t launch_cl_cutoff_sweep(int mode, int B, const StructInfo* info, const ClWs& w,
+                                  const float* frac, float c2thr, uint32_t* counts,
+                                  const int64_t* offsets, int64_t capacity, int32_t* src,
+                                  int32_t* dst, int32_t* image, float* length, Counters* ctr,
+                                  mg_report* report, int64_t* partials, int grid, hipStream_t s);
+hipError_t launch_cl_knn(int B, int k, const StructInfo* info, const ClWs& w, const float* frac,
+                         int32_t* src, int32_t* dst, int32_t* image, float* length,
+                         int32_t* ext_list, Counters* ctr, mg_report* report, int64_t* partials,
+                         int grid, hipStream_t s);
+hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr,
+                         ImageEntry* table, int64_t image_capacity, hipStream_t s);
 hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
                                const ImageEntry* table, const float* frac, float c2thr,
                                uint32_t* counts, const int64_t* offsets, int64_t capacity,
                                int32_t* src, int32_t* dst, int32_t* image, float* length,
-                               Counters* ctr, mg_report* report, int grid, int slots, hipStream_t s);
+                               Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
+                               hipStream_t s);
+// Exclusive scan of counts[0..N) into offsets[0..N]; with a report, also
+// records the total as num_edges and flags a capacity overflow.
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offsets, int64_t* bsum,
                               int64_t capacity, mg_report* report, hipStream_t s);
-hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const ImageEntry* table,
-                      const float* frac, const int32_t* atom_struct, int32_t* src, int32_t* dst,
+hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const int64_t* item_off,
+                      const ImageEntry* table, const float* frac, int32_t* src, int32_t* dst,
                       int32_t* image, float* length, int32_t* ext_list, Counters* ctr,
-                      mg_report* report, int grid, hipStream_t s);
+                      mg_report* report, int64_t* partials, int grid, hipStream_t s);
 hipError_t launch_knn_extended(int B, int64_t N, int k, const StructInfo* info, const float* frac,
                                const int32_t* atom_struct, int32_t* src, int32_t* dst,
                                int32_t* image, float* length, const int32_t* ext_list,
@@ -185,6 +224,11 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
                                const int32_t* image, int64_t E, const int64_t* num_edges,
                                const float* grad_vec, const float* grad_length, float* grad_frac,
                                float* grad_lattice, double* acc, hipStream_t s);
+// Per-wave partial counts (candidates evaluated) are written to a workspace
+// array and summed by one block afterwards: no shared-counter atomics in the
+// sweeps. The array holds MAX_GRID_WAVES entries.
+constexpr int MAX_GRID_WAVES = 256 * 64 * 4;
+hipError_t launch_sum_partials(const int64_t* partials, int n, mg_report* report, hipStream_t s);
 hipError_t launch_zero_report(mg_report* report, Counters* ctr, int64_t num_edges, hipStream_t s);
 int64_t scan_block_count(int64_t N);
 

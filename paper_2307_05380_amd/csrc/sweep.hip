@@ -85,12 +85,12 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
     const ImageEntry* __restrict__ table, const float* __restrict__ frac, float c2thr,
     uint32_t* __restrict__ counts, const int64_t* __restrict__ offsets, int64_t capacity,
     int32_t* __restrict__ src, int32_t* __restrict__ dst, int32_t* __restrict__ image,
-    float* __restrict__ length, Counters* __restrict__ ctr, mg_report* __restrict__ rep) {
+    float* __restrict__ length, Counters* __restrict__ ctr, mg_report* __restrict__ rep,
+    int64_t* __restrict__ partials) {
     const int lane = lane_id();
     const int64_t total = item_off[B];
-    for (;;) {
-        const int64_t q = (int64_t)wave_ticket(&ctr->ticket[MODE]);
-        if (q >= total) break;
+    int64_t ncand = 0;
+    for (int64_t q = grid_wave(); q < total; q += grid_waves()) {
         int lo = 0, hi = B;   // item_off[lo] <= q < item_off[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -114,9 +114,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
             if (MODE == MODE_COUNT && lane < nsrc) counts[atom0 + i_first + lane] = 0u;
             continue;
         }
-        if (MODE == MODE_COUNT && lane == 0)
-            atomicAdd((unsigned long long*)&rep->candidates,
-                      (unsigned long long)nsrc * (unsigned long long)n * (unsigned long long)I);
+        ncand += (int64_t)nsrc * n * I;
 
         if (n <= WAVE) {
             // ---- several sources per wave: lane = a * n + j
@@ -203,17 +201,19 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
             }
         }
     }
+    if (MODE == MODE_COUNT && lane == 0) partials[grid_wave()] = ncand;
 }
 
 hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
                                const ImageEntry* table, const float* frac, float c2thr,
                                uint32_t* counts, const int64_t* offsets, int64_t capacity,
                                int32_t* src, int32_t* dst, int32_t* image, float* length,
-                               Counters* ctr, mg_report* report, int grid, int slots, hipStream_t s) {
+                               Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
+                               hipStream_t s) {
     if (B == 0) return hipSuccess;
 #define MG_SWEEP(M, S)                                                                              \
     hipLaunchKernelGGL((k_cutoff_sweep<M, S>), dim3(grid), dim3(256), 0, s, B, info, item_off, table, \
-                       frac, c2thr, counts, offsets, capacity, src, dst, image, length, ctr, report)
+                       frac, c2thr, counts, offsets, capacity, src, dst, image, length, ctr, report, partials)
     if (mode == MODE_COUNT) {
         if (slots <= 1) MG_SWEEP(MODE_COUNT, 1);
         else if (slots == 2) MG_SWEEP(MODE_COUNT, 2);
@@ -285,8 +285,10 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) {
         offsets[N] = excl;
-        rep->num_edges = excl;
-        if (excl > capacity) atomicOr(&rep->flags, (uint32_t)MG_FLAG_CAPACITY);
+        if (rep) {
+            rep->num_edges = excl;
+            if (excl > capacity) atomicOr(&rep->flags, (uint32_t)MG_FLAG_CAPACITY);
+        }
     }
 }
 
@@ -300,5 +302,25 @@ hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offset
 }
 
 int64_t scan_block_count(int64_t N) { return N > 0 ? (N + SCAN_TILE - 1) / SCAN_TILE : 1; }
+
+}  // namespace mg
+
+namespace mg {
+
+__global__ __launch_bounds__(256) void k_sum_partials(const int64_t* __restrict__ p, int n,
+                                                      mg_report* __restrict__ rep) {
+    __shared__ int64_t sh[4];
+    int64_t v = 0;
+    for (int q = threadIdx.x; q < n; q += 256) v += p[q];
+    v = wave_sum_i64(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) rep->candidates += sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+hipError_t launch_sum_partials(const int64_t* partials, int n, mg_report* report, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, n, report);
+    return hipGetLastError();
+}
 
 }  // namespace mg

@@ -20,7 +20,7 @@ import torch
 from . import _lib
 
 __all__ = ["Graph", "Report", "cutoff_graph", "knn_graph", "edge_geometry", "EdgeGeometry",
-           "CutoffBuilder", "KnnBuilder", "GeometryRunner"]
+           "CutoffBuilder", "KnnBuilder", "GeometryRunner", "auto_opts"]
 
 
 @dataclasses.dataclass
@@ -82,6 +82,19 @@ def _check_inputs(lattices, frac, batch_ptr):
     return lattices.contiguous(), frac.contiguous(), batch_ptr.contiguous(), B, int(frac.shape[0])
 
 
+CL_MIN_ATOMS = 512   # structures smaller than this never use cell lists (see the C library)
+
+
+def auto_opts(batch_ptr, opts: int | None = None) -> int:
+    """MG_OPT_CELL_LIST_OFF when no structure is large enough for cell lists
+    (saves the cell-list launches), else the caller's opts (default 0)."""
+    if opts is not None:
+        return int(opts)
+    counts = batch_ptr[1:] - batch_ptr[:-1]
+    nmax = int(counts.max()) if counts.numel() else 0
+    return _lib.MG_OPT_CELL_LIST_OFF if nmax < CL_MIN_ATOMS else 0
+
+
 def _strict_check(rep: Report):
     bad = rep.flags & (_lib.MG_FLAG_SINGULAR | _lib.MG_FLAG_NONFINITE | _lib.MG_FLAG_RANGE)
     if bad:
@@ -128,18 +141,20 @@ class CutoffBuilder:
 
 
 def cutoff_graph(lattices, frac, batch_ptr, cutoff: float, capacity: int | None = None,
-                 image_capacity: int | None = None, strict: bool = False) -> Graph:
+                 image_capacity: int | None = None, strict: bool = False,
+                 opts: int | None = None) -> Graph:
     """Periodic cutoff multigraph (Definition def6, constant cutoff, strict <).
 
     Allocates outputs, runs the library and, when the edge or image-table
     capacity was too small, reruns once with the exact sizes the device
     reported (this reads the report, i.e. synchronises)."""
     lattices, frac, batch_ptr, B, N = _check_inputs(lattices, frac, batch_ptr)
+    opts = auto_opts(batch_ptr, opts)
     cap = int(capacity) if capacity is not None else max(4096, 96 * N)
     icap = int(image_capacity) if image_capacity is not None else 96 * B + 4096
     for _ in range(3):
         b = CutoffBuilder(B, N, cap, icap, frac.device)
-        b.run(lattices, frac, batch_ptr, cutoff)
+        b.run(lattices, frac, batch_ptr, cutoff, opts)
         rep = b.report()
         retry = False
         if rep.flags & _lib.MG_FLAG_IMAGES:
@@ -189,13 +204,14 @@ class KnnBuilder:
 
 
 def knn_graph(lattices, frac, batch_ptr, k: int, image_capacity: int | None = None,
-              strict: bool = False) -> Graph:
+              strict: bool = False, opts: int | None = None) -> Graph:
     """Periodic KNN multigraph: exactly k edges per source in (length, dst, t) order."""
     lattices, frac, batch_ptr, B, N = _check_inputs(lattices, frac, batch_ptr)
+    opts = auto_opts(batch_ptr, opts)
     icap = int(image_capacity) if image_capacity is not None else 64 * B + 4096
     for _ in range(3):
         b = KnnBuilder(B, N, k, icap, frac.device)
-        b.run(lattices, frac, batch_ptr)
+        b.run(lattices, frac, batch_ptr, opts)
         rep = b.report()
         if rep.flags & _lib.MG_FLAG_IMAGES:
             icap = int(rep.images_needed)

@@ -109,3 +109,55 @@ def knn_check(batch, k, g_src, g_dst, g_img, g_len, sources=None, band=BAND, len
         near_total += len(ok.near.get(int(a), []))
     return {"sources": int(len(atoms)), "near": int(near_total),
             "max_len_err": float(np.abs(l64 - g_len[atoms]).max(initial=0.0))}
+
+
+def cutoff_sources_check(batch, s, sources, g_src, g_dst, g_img, g_len, band=BAND, len_tol=LEN_TOL):
+    """cutoff_check restricted to some sources (local indices) of structure s."""
+    a0 = int(batch.batch_ptr[s])
+    L, x = batch.structure(s)
+    os_, od, oi, ol = oracle.cutoff_sources64(L, x, batch.cutoff, sources, band=band)
+    glob = a0 + np.asarray(sources, np.int64)
+    sel = np.isin(g_src, glob)
+    G = _rows(g_src[sel], g_dst[sel], g_img[sel])
+    GL = np.asarray(g_len)[sel].astype(np.float64)
+    O = _rows(os_ + a0, od + a0, oi)
+    gv, ov = _void(G), _void(O)
+    assert np.unique(gv).shape[0] == gv.shape[0], "duplicate GPU edges"
+    c = batch.cutoff
+    must = ol < c - band
+    in_o = np.isin(gv, ov)
+    assert in_o.all(), f"{int((~in_o).sum())} GPU edges are not edges of the oracle (first: {G[~in_o][:3]})"
+    found = np.isin(ov[must], gv)
+    assert found.all(), f"{int((~found).sum())} oracle edges missing on GPU (first: {O[must][~found][:3]})"
+    order_o = np.argsort(ov)
+    pos = order_o[np.searchsorted(ov[order_o], gv)]
+    err = np.abs(GL - ol[pos])
+    assert err.max(initial=0.0) <= len_tol, f"length error {err.max():.3g}"
+    return {"edges": int(G.shape[0]), "near": int((np.abs(ol - c) <= band).sum()),
+            "max_len_err": float(err.max(initial=0.0))}
+
+
+def knn_sources_check(batch, s, k, sources, g_src, g_dst, g_img, g_len, band=BAND, len_tol=LEN_TOL):
+    """knn_check restricted to some sources (local indices) of structure s."""
+    a0 = int(batch.batch_ptr[s])
+    L, x = batch.structure(s)
+    src, dst, img, ln, dk, near, inside = oracle.knn_structure64(L, x, k, band=band, sources=sources)
+    g_dst = np.asarray(g_dst).reshape(-1, k)
+    g_img = np.asarray(g_img).reshape(-1, k, 3)
+    g_len = np.asarray(g_len).reshape(-1, k).astype(np.float64)
+    for r, il in enumerate(sources):
+        a = a0 + int(il)
+        assert (g_dst[a] >= 0).all(), f"source {a}: invalid edges"
+        gset = {(int(d),) + tuple(int(q) for q in t) for d, t in zip(g_dst[a], g_img[a])}
+        assert len(gset) == k and (a, 0, 0, 0) not in gset
+        want = {(int(d) + a0,) + tuple(int(q) for q in t)
+                for d, t, l in zip(dst[r * k:(r + 1) * k], img[r * k:(r + 1) * k], ln[r * k:(r + 1) * k])
+                if l < dk[r] - band}
+        assert not (want - gset), f"source {a}: missing {sorted(want - gset)[:3]}"
+        gs = np.full(k, a)
+        _, l64 = oracle.edge_geometry64(batch.lattices, batch.frac, batch.batch_ptr, gs, g_dst[a], g_img[a])
+        assert (l64 <= dk[r] + band).all(), f"source {a}: beyond the k-th distance"
+        assert np.abs(l64 - g_len[a]).max() <= len_tol
+        keys = list(zip(g_len[a], g_dst[a], g_img[a][:, 0], g_img[a][:, 1], g_img[a][:, 2]))
+        assert keys == sorted(keys), f"source {a}: not in (length, dst, t) order"
+    return {"sources": len(sources)}

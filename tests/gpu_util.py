@@ -17,7 +17,7 @@ def np_graph(g):
             g.image.cpu().numpy().astype(np.int64), g.length.cpu().numpy())
 
 
-def cutoff(batch, cutoff=None, **kw):
+def cutoff(batch, cutoff=None, **kw):  # kw: capacity, image_capacity, strict, opts
     L, X, P = dev(batch)
     g = graph.cutoff_graph(L, X, P, batch.cutoff if cutoff is None else cutoff, **kw)
     torch.cuda.synchronize()

@@ -1,0 +1,86 @@
+"""Cell lists for large structures on the GPU (supercells of the 64-supercell
+update workload, forced cell lists on large cells, wrapped coordinates),
+checked against the FP64 oracle on sampled sources."""
+import numpy as np
+import pytest
+
+import compare
+import gpu_util as gu
+from paper_2307_05380_amd import _lib, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample(n, count, seed):
+    rng = np.random.default_rng(seed)
+    return sorted(rng.choice(n, min(count, n), replace=False).tolist())
+
+
+@pytest.fixture(scope="module")
+def supercells():
+    # two supercells (8x8x8 and 9x9x9 tilings of an 8-atom cell), 4096 and 5832 atoms
+    return inputs.make_config5(B=2, m_lo=8, m_hi=9)
+
+
+def test_supercell_cutoff_cell_lists(supercells):
+    b = supercells
+    g = gu.cutoff(b)
+    assert g.report.flags == 0, g.report.flag_names()
+    s, d, t, ln = gu.np_graph(g)
+    for q in range(b.B):
+        n = int(b.batch_ptr[q + 1] - b.batch_ptr[q])
+        st = compare.cutoff_sources_check(b, q, _sample(n, 48, q), s, d, t, ln)
+        print(q, st)
+    rp = g.row_ptr.cpu().numpy()
+    assert np.array_equal(np.repeat(np.arange(b.N), np.diff(rp)), s)
+
+
+def test_supercell_knn_cell_lists(supercells):
+    b = supercells
+    g = gu.knn(b, k=32)
+    assert g.report.flags & ~_lib.MG_FLAG_KNN_EXTENDED == 0, g.report.flag_names()
+    s, d, t, ln = gu.np_graph(g)
+    for q in range(b.B):
+        n = int(b.batch_ptr[q + 1] - b.batch_ptr[q])
+        compare.knn_sources_check(b, q, 32, _sample(n, 48, 10 + q), s, d, t, ln)
+    print(g.report)
+
+
+def _large_cells(seed, B=6):
+    rng = np.random.default_rng(seed)
+    return inputs.random_batch(rng, B, 40, 220, 15.0, 26.0, 60.0, 120.0, cutoff=5.0, k=12)
+
+
+def test_forced_cell_lists_match_image_sweep():
+    """The same batch through cell lists (forced) and through the image sweep
+    gives the same edges; both agree with the oracle."""
+    b = _large_cells(3)
+    gc = gu.cutoff(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    gi = gu.cutoff(b, opts=_lib.MG_OPT_CELL_LIST_OFF)
+    compare.cutoff_check(b, *gu.np_graph(gc))
+    compare.cutoff_check(b, *gu.np_graph(gi))
+    assert gc.num_edges == gi.num_edges
+    kc = gu.knn(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    compare.knn_check(b, b.k, *gu.np_graph(kc))
+
+
+def test_cell_lists_wrapped_coordinates():
+    b = _large_cells(4)
+    rng = np.random.default_rng(0)
+    shift = rng.integers(-2, 3, size=b.frac.shape).astype(np.float32)
+    b.frac[:] = b.frac + shift
+    g = gu.cutoff(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    compare.cutoff_check(b, *gu.np_graph(g))
+    k = gu.knn(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    compare.knn_check(b, b.k, *gu.np_graph(k))
+
+
+def test_cell_list_knn_extended():
+    """Clustered atoms: the k-th neighbour lies beyond the stencil, the source
+    falls back to the extended search."""
+    rng = np.random.default_rng(7)
+    L = 30.0 * np.eye(3, dtype=np.float32)
+    x = np.concatenate([0.5 + 0.004 * rng.standard_normal((6, 3)), rng.random((200, 3))]).astype(np.float32)
+    b = gu.single(L, x, cutoff=5.0, k=12)
+    g = gu.knn(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    compare.knn_check(b, 12, *gu.np_graph(g))
