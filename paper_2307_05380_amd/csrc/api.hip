@@ -189,7 +189,7 @@ KnnWs carve_knn(void* ws, size_t bytes, int B, int64_t N) {
 
 struct GeomWs {
     int32_t* atom_struct;
-    double* acc;
+    mg::GeomBwdWs bwd;
     size_t fixed;
 };
 
@@ -197,7 +197,10 @@ GeomWs carve_geom(void* ws, int B, int64_t N) {
     Carver c{static_cast<char*>(ws)};
     GeomWs w;
     w.atom_struct = c.take<int32_t>((size_t)N);
-    w.acc = c.take<double>((size_t)B * 9);
+    w.bwd.acc = c.take<double>((size_t)B * 9);
+    w.bwd.start = c.take<int64_t>((size_t)B + 1);
+    w.bwd.item_off = c.take<int64_t>((size_t)B + 1);
+    w.bwd.flag = c.take<int32_t>(1);
     w.fixed = mg::align_up(c.used, 256);
     return w;
 }
@@ -455,8 +458,8 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac, co
         hipSuccess)
         return hip_fail(e, "atom map");
     if ((e = phase("geometry.bwd", s, [&] {
-             return mg::launch_geometry_bwd(lattices, frac, w.atom_struct, B, N, src, dst, image, E, num_edges,
-                                            grad_vec, grad_length, grad_frac, grad_lattice, w.acc, s);
+             return mg::launch_geometry_bwd(lattices, frac, w.atom_struct, batch_ptr, B, N, src, dst, image, E,
+                                            num_edges, grad_vec, grad_length, grad_frac, grad_lattice, w.bwd, s);
          })) != hipSuccess)
         return hip_fail(e, "geometry backward");
     return MG_OK;

@@ -59,73 +59,364 @@ __global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ p, int64_t
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = 0.0f;
 }
 
+__global__ __launch_bounds__(64) void k_zero_i32(int32_t* __restrict__ p, int n) {
+    for (int q = threadIdx.x; q < n; q += 64) p[q] = 0;
+}
+
 __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = 0.0;
 }
 
-// Backward pass. Each workgroup takes a contiguous range of edges and walks it
-// 256 edges at a time (64 per wave).
-// - Destination side: coordinate gradients go to an LDS window of GB_WIN atoms
-//   (FP32 LDS atomics) that follows the edges; when a step touches atoms
-//   outside the window, the touched part is flushed to global memory with FP32
-//   atomics and the window moves. A step spanning more atoms than the window
-//   uses global atomics directly.
-// - Source side and lattice: edges grouped by source give every wave long runs
-//   of one source and one structure, so each lane keeps running sums in
-//   registers for the wave's current source (3 FP32) and structure (9 FP64)
-//   and the wave reduces and flushes them (global atomics) only when the run
-//   ends; a step that mixes sources (or structures) flushes and falls back to
-//   per-lane atomics for that step.
-constexpr int GB_WIN = 2048;
+// Backward pass.
+//
+// Global atomics on MI355X are resolved far from the compute units and cost
+// far more than LDS traffic, so the backward pass is organised so that almost
+// no per-edge value reaches global memory through an atomic:
+// - a plan pass checks that the edges are grouped by structure (both
+//   endpoints in the structure, structures in ascending order: what the
+//   graph builders emit) and records every structure's edge range;
+// - one workgroup per item (a structure, or a chunk of BW_CHUNK edges of a
+//   large one) accumulates the coordinate gradients of the structure's atoms
+//   in LDS and the lattice gradient in registers, then writes them with plain
+//   stores when the item covers the whole structure (atomics only for split
+//   structures). A wave whose 64 edges share the source (edges grouped by
+//   source) keeps the source's sum in registers until the run ends.
+// - Structures with more than BW_WIN atoms, and edges in any other order, take
+//   a general kernel: runs of equal dst / src / structure are merged inside the
+//   wave by a segmented scan, and the run's last lane adds the total with a
+//   global atomic.
+// Both kernels are launched; each leaves the items of the other at once.
+constexpr int BW_CHUNK = 16384;   // edges per item
+constexpr int BW_WIN = 2048;      // atoms of a structure held in LDS
 
-__global__ __launch_bounds__(256) void k_geom_bwd(const float* __restrict__ lattices,
-                                                  const float* __restrict__ frac,
-                                                  const int32_t* __restrict__ atom_struct, int64_t N,
-                                                  const int32_t* __restrict__ src,
-                                                  const int32_t* __restrict__ dst,
-                                                  const int32_t* __restrict__ image, int64_t E,
-                                                  const int64_t* __restrict__ num_edges,
-                                                  const float* __restrict__ gvec,
-                                                  const float* __restrict__ glen,
-                                                  float* __restrict__ grad_frac,
-                                                  double* __restrict__ acc) {
-    __shared__ float win[GB_WIN * 3];
-    __shared__ int s_lo[4], s_hi[4];
+// Lane index of the start of this lane's run (runs of equal key over lanes);
+// `heads` has bit l set where lane l starts a run (bit 0 always set).
+__device__ __forceinline__ int run_start(uint64_t heads, int lane) {
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    return 63 - __builtin_clzll(heads & upto);
+}
+
+__device__ __forceinline__ uint64_t run_heads(int32_t key, int lane) {
+    const int32_t prev = __shfl_up(key, 1, WAVE);
+    return ballot(lane == 0 || prev != key);
+}
+
+__device__ __forceinline__ bool run_tail(uint64_t heads, int lane) {
+    return lane == 63 || ((heads >> (lane + 1)) & 1ull);
+}
+
+// Inclusive scan of v restricted to this lane's run [rs, lane].
+template <typename T>
+__device__ __forceinline__ T seg_scan(T v, int rs, int lane) {
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const T y = __shfl_up(v, d, WAVE);
+        if (lane - d >= rs) v += y;
+    }
+    return v;
+}
+
+// Structure of edge e, or -1 if an endpoint is out of range or the endpoints
+// lie in different structures.
+__device__ __forceinline__ int32_t edge_struct(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                               const int32_t* __restrict__ atom_struct, int64_t N, int64_t e) {
+    const int32_t i = src[e], j = dst[e];
+    if (i < 0 || j < 0 || i >= N || j >= N) return -1;
+    const int32_t si = atom_struct[i];
+    return si == atom_struct[j] ? si : -1;
+}
+
+// Plan: edge ranges start[s] .. start[s+1] of every structure, and flag = 1 if
+// the edges are not grouped by structure in ascending order.
+__global__ __launch_bounds__(256) void k_bwd_plan(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                                  const int32_t* __restrict__ atom_struct, int64_t N, int B,
+                                                  int64_t E, const int64_t* __restrict__ num_edges,
+                                                  int64_t* __restrict__ start, int32_t* __restrict__ flag) {
     const int64_t Ee = edge_count(E, num_edges);
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (Ee == 0) {
+        for (int64_t q = t0; q <= B; q += stride) start[q] = 0;
+        return;
+    }
+    // whole waves step together so that lane - 1 holds edge e - 1
+    const int64_t span = (Ee + WAVE - 1) / WAVE * WAVE;
+    for (int64_t e = t0; e < span; e += stride) {
+        const int32_t k = e < Ee ? edge_struct(src, dst, atom_struct, N, e) : B;
+        int32_t kp = __shfl_up(k, 1, WAVE);
+        if (lane == 0) kp = e == 0 ? -1 : edge_struct(src, dst, atom_struct, N, e - 1);
+        if (e >= Ee) continue;
+        if (k < 0 || (e > 0 && kp < 0) || k < kp) {
+            atomicOr(flag, 1);
+            continue;
+        }
+        for (int32_t q = kp + 1; q <= k; ++q) start[q] = e;
+        if (e == Ee - 1)
+            for (int32_t q = k + 1; q <= B; ++q) start[q] = Ee;
+    }
+}
+
+// Items: item_off[s] = number of items of structures < s (one item per
+// BW_CHUNK edges, at least one per structure); item_off[B] = total.
+__global__ __launch_bounds__(1024) void k_bwd_items(const int64_t* __restrict__ start, int B,
+                                                    int64_t* __restrict__ item_off) {
+    __shared__ int64_t sh[1024];
+    const int t = threadIdx.x;
+    const int per = (B + 1023) / 1024;
+    const int s0 = min(B, t * per), s1 = min(B, s0 + per);
+    int64_t sum = 0;
+    for (int q = s0; q < s1; ++q) {
+        const int64_t n = start[q + 1] - start[q];
+        sum += n > BW_CHUNK ? (n + BW_CHUNK - 1) / BW_CHUNK : 1;
+    }
+    sh[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t y = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += y;
+        __syncthreads();
+    }
+    int64_t run = sh[t] - sum;
+    for (int q = s0; q < s1; ++q) {
+        item_off[q] = run;
+        const int64_t n = start[q + 1] - start[q];
+        run += n > BW_CHUNK ? (n + BW_CHUNK - 1) / BW_CHUNK : 1;
+    }
+    if (t == 1023) item_off[B] = sh[1023];
+}
+
+// Item `item` of the grouped order: its structure, edge range and whether it
+// covers the whole structure. False if there is no such item.
+struct BwdItem {
+    int32_t st;
+    int64_t c0, c1, atom0;
+    int n;
+    bool whole;
+};
+
+__device__ __forceinline__ bool bwd_item(int64_t item, int B, const int64_t* __restrict__ start,
+                                         const int64_t* __restrict__ item_off,
+                                         const int64_t* __restrict__ batch_ptr, BwdItem& it) {
+    if (item >= item_off[B]) return false;
+    int lo = 0, hi = B;   // largest s with item_off[s] <= item
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_off[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    it.st = lo;
+    const int64_t k = item - item_off[lo];
+    it.c0 = start[lo] + k * BW_CHUNK;
+    it.c1 = min(start[lo + 1], it.c0 + BW_CHUNK);
+    it.whole = item_off[lo + 1] - item_off[lo] == 1;
+    it.atom0 = batch_ptr[lo];
+    it.n = (int)(batch_ptr[lo + 1] - it.atom0);
+    return true;
+}
+
+// Block reduction of the per-lane lattice sums; thread q < 9 gets entry q.
+__device__ __forceinline__ double block_lattice(const double (&la)[9], double (&red)[4][9], int tid) {
+    const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const double t = wave_sum_f64(la[q]);
+        if (lane == 0) red[wv][q] = t;
+    }
+    __syncthreads();
+    return tid < 9 ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
+}
+
+// Grouped order, structures of at most BW_WIN atoms: LDS accumulation.
+__global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ lattices,
+                                                      const float* __restrict__ frac,
+                                                      const int64_t* __restrict__ batch_ptr, int B,
+                                                      const int32_t* __restrict__ src,
+                                                      const int32_t* __restrict__ dst,
+                                                      const int32_t* __restrict__ image,
+                                                      const float* __restrict__ gvec,
+                                                      const float* __restrict__ glen,
+                                                      const int64_t* __restrict__ start,
+                                                      const int64_t* __restrict__ item_off,
+                                                      const int32_t* __restrict__ flag,
+                                                      float* __restrict__ grad_frac,
+                                                      double* __restrict__ acc) {
+    __shared__ float win[BW_WIN * 3];
+    __shared__ double red[4][9];
+    if (*flag != 0) return;
+    BwdItem it;
+    if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it) || it.n > BW_WIN) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t per = ((Ee + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
-    const int64_t e0 = (int64_t)blockIdx.x * per;
-    const int64_t e1 = min(Ee, e0 + per);
-    for (int q = tid; q < GB_WIN * 3; q += 256) win[q] = 0.0f;
-    int64_t wb = -1;              // window base atom (block-uniform), -1: no window
-    int tlo = GB_WIN, thi = -1;   // touched local range of the window
-    int32_t src_cur = -1;         // wave's current source run (uniform), -1: none
+    const bool gf = grad_frac != nullptr;
+    if (gf) {
+        for (int q = tid; q < 3 * it.n; q += 256) win[q] = 0.0f;
+        __syncthreads();
+    }
+    const float* Lp = lattices + 9 * (int64_t)it.st;
+    float Lf[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Lf[q] = Lp[q];
+    const float* fr = frac + 3 * it.atom0;
+    const int32_t a0 = (int32_t)it.atom0;
+    // this wave's contiguous quarter of the item
+    const int64_t qlen = ((it.c1 - it.c0 + 3) / 4 + WAVE - 1) / WAVE * WAVE;
+    const int64_t w0 = it.c0 + wv * qlen, w1 = min(it.c1, w0 + qlen);
+    int src_cur = -1;   // wave's current source run (local index), -1: none
     float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f;
-    int32_t st_cur = -1;          // wave's current structure run (uniform), -1: none
     double la[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) la[q] = 0.0;
-    __syncthreads();
-    auto flush_window = [&]() {
-        __syncthreads();   // every LDS atomic of the previous steps is done
-        if (wb >= 0 && thi >= tlo) {
-            for (int q = tlo * 3 + tid; q < (thi + 1) * 3; q += 256) {
-                const float v = win[q];
-                if (v != 0.0f) unsafeAtomicAdd(&grad_frac[wb * 3 + q], v);
-                win[q] = 0.0f;
+    for (int64_t base = w0; base < w1; base += WAVE) {
+        const bool act = base + lane < w1;
+        const int32_t* sw = src + base;
+        const int32_t* dw = dst + base;
+        const int32_t* iw = image + 3 * base;
+        int li = 0, lj = 0;
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+        double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+        if (act) {
+            li = sw[lane] - a0;
+            lj = dw[lane] - a0;
+            f0 = (double)fr[3 * lj] - (double)fr[3 * li] + (double)iw[3 * lane];
+            f1 = (double)fr[3 * lj + 1] - (double)fr[3 * li + 1] + (double)iw[3 * lane + 1];
+            f2 = (double)fr[3 * lj + 2] - (double)fr[3 * li + 2] + (double)iw[3 * lane + 2];
+            if (gvec) {
+                const float* gw = gvec + 3 * base;
+                g0 = gw[3 * lane];
+                g1 = gw[3 * lane + 1];
+                g2 = gw[3 * lane + 2];
+            }
+            if (glen) {
+                // v in FP64 (large image offsets), the length term in FP32
+                const double v0 = f0 * (double)Lf[0] + f1 * (double)Lf[3] + f2 * (double)Lf[6];
+                const double v1 = f0 * (double)Lf[1] + f1 * (double)Lf[4] + f2 * (double)Lf[7];
+                const double v2 = f0 * (double)Lf[2] + f1 * (double)Lf[5] + f2 * (double)Lf[8];
+                const float l2 = (float)(v0 * v0 + v1 * v1 + v2 * v2);
+                const float c = l2 > 0.0f ? glen[base + lane] / sqrtf(l2) : 0.0f;
+                g0 += c * (float)v0;
+                g1 += c * (float)v1;
+                g2 += c * (float)v2;
+            }
+            // g L^T: component k is g . (row k of L)
+            x0 = g0 * Lf[0] + g1 * Lf[1] + g2 * Lf[2];
+            x1 = g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
+            x2 = g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
+        }
+        if (gf) {
+            if (act) {
+                atomicAdd(&win[3 * lj], x0);
+                atomicAdd(&win[3 * lj + 1], x1);
+                atomicAdd(&win[3 * lj + 2], x2);
+            }
+            const int iu = __builtin_amdgcn_readfirstlane(li);   // lane 0 is active
+            const bool uni = ballot(act && li != iu) == 0;
+            if (!(uni && iu == src_cur)) {
+                if (src_cur >= 0) {
+                    const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
+                    if (lane == 0) {
+                        atomicAdd(&win[3 * src_cur], r0);
+                        atomicAdd(&win[3 * src_cur + 1], r1);
+                        atomicAdd(&win[3 * src_cur + 2], r2);
+                    }
+                }
+                sa0 = sa1 = sa2 = 0.f;
+                src_cur = uni ? iu : -1;
+            }
+            if (src_cur >= 0) {
+                sa0 -= x0;
+                sa1 -= x1;
+                sa2 -= x2;
+            } else if (act) {
+                atomicAdd(&win[3 * li], -x0);
+                atomicAdd(&win[3 * li + 1], -x1);
+                atomicAdd(&win[3 * li + 2], -x2);
             }
         }
-        __syncthreads();
+        if (acc) {
+            const double h0 = g0, h1 = g1, h2 = g2;
+            la[0] += f0 * h0; la[1] += f0 * h1; la[2] += f0 * h2;
+            la[3] += f1 * h0; la[4] += f1 * h1; la[5] += f1 * h2;
+            la[6] += f2 * h0; la[7] += f2 * h1; la[8] += f2 * h2;
+        }
+    }
+    if (gf && src_cur >= 0) {
+        const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
+        if (lane == 0) {
+            atomicAdd(&win[3 * src_cur], r0);
+            atomicAdd(&win[3 * src_cur + 1], r1);
+            atomicAdd(&win[3 * src_cur + 2], r2);
+        }
+    }
+    const double lt = block_lattice(la, red, tid);   // also orders the LDS atomics before the reads below
+    if (acc && tid < 9) {
+        if (it.whole) acc[9 * (int64_t)it.st + tid] = lt;
+        else unsafeAtomicAdd(&acc[9 * (int64_t)it.st + tid], lt);
+    }
+    if (gf) {
+        float* out = grad_frac + 3 * it.atom0;
+        for (int q = tid; q < 3 * it.n; q += 256) {
+            const float v = win[q];
+            if (it.whole) out[q] = v;
+            else if (v != 0.0f) unsafeAtomicAdd(&out[q], v);
+        }
+    }
+}
+
+// General kernel: grouped order with structures of more than BW_WIN atoms
+// (one workgroup per item), or any other order (one workgroup per BW_CHUNK
+// edges). Per-edge math in FP64; merged runs go to global atomics.
+__global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ lattices,
+                                                      const float* __restrict__ frac,
+                                                      const int32_t* __restrict__ atom_struct,
+                                                      const int64_t* __restrict__ batch_ptr, int B, int64_t N,
+                                                      const int32_t* __restrict__ src,
+                                                      const int32_t* __restrict__ dst,
+                                                      const int32_t* __restrict__ image, int64_t E,
+                                                      const int64_t* __restrict__ num_edges,
+                                                      const float* __restrict__ gvec,
+                                                      const float* __restrict__ glen,
+                                                      const int64_t* __restrict__ start,
+                                                      const int64_t* __restrict__ item_off,
+                                                      const int32_t* __restrict__ flag,
+                                                      float* __restrict__ grad_frac,
+                                                      double* __restrict__ acc) {
+    __shared__ double red[4][9];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const bool grouped = *flag == 0;
+    int64_t c0, c1;
+    BwdItem it;
+    it.st = -1;
+    it.whole = false;
+    if (grouped) {
+        if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it) || it.n <= BW_WIN) return;
+        c0 = it.c0;
+        c1 = it.c1;
+    } else {
+        const int64_t Ee = edge_count(E, num_edges);
+        c0 = (int64_t)blockIdx.x * BW_CHUNK;
+        if (c0 >= Ee) return;
+        c1 = min(Ee, c0 + BW_CHUNK);
+    }
+    const int64_t qlen = ((c1 - c0 + 3) / 4 + WAVE - 1) / WAVE * WAVE;
+    const int64_t w0 = c0 + wv * qlen, w1 = min(c1, w0 + qlen);
+    int32_t src_cur = -1;   // wave's current source run (uniform), -1: none
+    float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f;
+    int32_t st_cur = it.st; // wave's current structure run, -1: none
+    double la[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) la[q] = 0.0;
+    auto add_atom = [&](int32_t a, float y0, float y1, float y2) {
+        unsafeAtomicAdd(&grad_frac[3 * (int64_t)a], y0);
+        unsafeAtomicAdd(&grad_frac[3 * (int64_t)a + 1], y1);
+        unsafeAtomicAdd(&grad_frac[3 * (int64_t)a + 2], y2);
     };
     auto flush_src = [&]() {
         if (src_cur >= 0) {
             const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
-            if (lane == 0) {
-                unsafeAtomicAdd(&grad_frac[3 * (int64_t)src_cur], r0);
-                unsafeAtomicAdd(&grad_frac[3 * (int64_t)src_cur + 1], r1);
-                unsafeAtomicAdd(&grad_frac[3 * (int64_t)src_cur + 2], r2);
-            }
+            if (lane == 0) add_atom(src_cur, r0, r1, r2);
         }
         sa0 = sa1 = sa2 = 0.f;
     };
@@ -140,19 +431,20 @@ __global__ __launch_bounds__(256) void k_geom_bwd(const float* __restrict__ latt
 #pragma unroll
         for (int q = 0; q < 9; ++q) la[q] = 0.0;
     };
-    for (int64_t base = e0; base < e1; base += 256) {
-        const int64_t e = base + tid;
-        int32_t i = 0, j = 0, s = 0;
-        bool act = e < e1;
+    for (int64_t base = w0; base < w1; base += WAVE) {
+        const int64_t e = base + lane;
+        int32_t i = -1, j = -1, s = -1;
+        bool act = e < w1;
         double f0 = 0, f1 = 0, f2 = 0, g0 = 0, g1 = 0, g2 = 0;
         float x0 = 0.f, x1 = 0.f, x2 = 0.f;
         if (act) {
             i = src[e];
             j = dst[e];
             act = i >= 0 && j >= 0 && i < N && j < N;
+            if (!act) i = j = -1;
         }
         if (act) {
-            s = atom_struct[i];
+            s = grouped ? it.st : atom_struct[i];
             const float* L = lattices + 9 * (int64_t)s;
             f0 = (double)frac[3 * (int64_t)j] - (double)frac[3 * (int64_t)i] + (double)image[3 * e];
             f1 = (double)frac[3 * (int64_t)j + 1] - (double)frac[3 * (int64_t)i + 1] + (double)image[3 * e + 1];
@@ -172,52 +464,17 @@ __global__ __launch_bounds__(256) void k_geom_bwd(const float* __restrict__ latt
                 g1 += c * v1;
                 g2 += c * v2;
             }
-            // g L^T: component k is g . (row k of L)
             x0 = (float)(g0 * (double)L[0] + g1 * (double)L[1] + g2 * (double)L[2]);
             x1 = (float)(g0 * (double)L[3] + g1 * (double)L[4] + g2 * (double)L[5]);
             x2 = (float)(g0 * (double)L[6] + g1 * (double)L[7] + g2 * (double)L[8]);
         }
         if (grad_frac) {
-            // ---- destination side: LDS window (block-uniform decisions)
-            int lo = act ? j : INT32_MAX, hi = act ? j : -1;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                lo = min(lo, __shfl_xor(lo, d, WAVE));
-                hi = max(hi, __shfl_xor(hi, d, WAVE));
+            {   // destination side: merge runs of equal dst; the run's last lane adds
+                const uint64_t heads = run_heads(j, lane);
+                const int rs = run_start(heads, lane);
+                const float y0 = seg_scan(x0, rs, lane), y1 = seg_scan(x1, rs, lane), y2 = seg_scan(x2, rs, lane);
+                if (j >= 0 && run_tail(heads, lane)) add_atom(j, y0, y1, y2);
             }
-            if (lane == 0) {
-                s_lo[wv] = lo;
-                s_hi[wv] = hi;
-            }
-            __syncthreads();
-            lo = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
-            hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
-            __syncthreads();
-            if (hi >= 0) {
-                if (hi - lo + 1 > GB_WIN) {
-                    if (act) {
-                        unsafeAtomicAdd(&grad_frac[3 * (int64_t)j], x0);
-                        unsafeAtomicAdd(&grad_frac[3 * (int64_t)j + 1], x1);
-                        unsafeAtomicAdd(&grad_frac[3 * (int64_t)j + 2], x2);
-                    }
-                } else {
-                    if (wb < 0 || lo < wb || hi >= wb + GB_WIN) {
-                        flush_window();
-                        wb = lo;
-                        tlo = GB_WIN;
-                        thi = -1;
-                    }
-                    tlo = min(tlo, (int)(lo - wb));
-                    thi = max(thi, (int)(hi - wb));
-                    if (act) {
-                        const int lj = 3 * (int)(j - wb);
-                        unsafeAtomicAdd(&win[lj], x0);
-                        unsafeAtomicAdd(&win[lj + 1], x1);
-                        unsafeAtomicAdd(&win[lj + 2], x2);
-                    }
-                }
-            }
-            // ---- source side: per-lane running sums over the wave's source run
             const uint64_t am = ballot(act);
             const int fl = am ? __builtin_ctzll(am) : 0;
             const int32_t iu = am ? __builtin_amdgcn_readlane(i, fl) : -1;
@@ -230,40 +487,53 @@ __global__ __launch_bounds__(256) void k_geom_bwd(const float* __restrict__ latt
                 sa0 -= x0;
                 sa1 -= x1;
                 sa2 -= x2;
-            } else if (act) {
-                unsafeAtomicAdd(&grad_frac[3 * (int64_t)i], -x0);
-                unsafeAtomicAdd(&grad_frac[3 * (int64_t)i + 1], -x1);
-                unsafeAtomicAdd(&grad_frac[3 * (int64_t)i + 2], -x2);
+            } else if (am) {
+                const uint64_t heads = run_heads(i, lane);
+                const int rs = run_start(heads, lane);
+                const float y0 = seg_scan(x0, rs, lane), y1 = seg_scan(x1, rs, lane), y2 = seg_scan(x2, rs, lane);
+                if (i >= 0 && run_tail(heads, lane)) add_atom(i, -y0, -y1, -y2);
             }
         }
         if (acc) {
-            const double F[3] = {f0, f1, f2}, Gv[3] = {g0, g1, g2};
-            const uint64_t am = ballot(act);
-            const int fl = am ? __builtin_ctzll(am) : 0;
-            const int32_t su = am ? __builtin_amdgcn_readlane(s, fl) : -1;
-            const bool uni = su >= 0 && ballot(act && s != su) == 0;
-            if (!(uni && su == st_cur)) {
-                flush_lat();
-                st_cur = uni ? su : -1;
+            if (!grouped) {
+                const uint64_t am = ballot(act);
+                const int fl = am ? __builtin_ctzll(am) : 0;
+                const int32_t su = am ? __builtin_amdgcn_readlane(s, fl) : -1;
+                const bool uni = su >= 0 && ballot(act && s != su) == 0;
+                if (!(uni && su == st_cur)) {
+                    flush_lat();
+                    st_cur = uni ? su : -1;
+                }
+                if (st_cur < 0 && am) {
+                    const uint64_t heads = run_heads(s, lane);
+                    const int rs = run_start(heads, lane);
+                    const bool tail = s >= 0 && run_tail(heads, lane);
+#pragma unroll 1
+                    for (int q = 0; q < 9; ++q) {
+                        const int a = q / 3, b = q - 3 * (q / 3);
+                        const double Fa = a == 0 ? f0 : (a == 1 ? f1 : f2);
+                        const double Gb = b == 0 ? g0 : (b == 1 ? g1 : g2);
+                        const double y = seg_scan(Fa * Gb, rs, lane);
+                        if (tail) unsafeAtomicAdd(&acc[9 * (int64_t)s + q], y);
+                    }
+                    continue;
+                }
             }
-            if (st_cur >= 0) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) la[3 * a + b] += F[a] * Gv[b];
-            } else if (act) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) unsafeAtomicAdd(&acc[9 * (int64_t)s + 3 * a + b], F[a] * Gv[b]);
-            }
+            la[0] += f0 * g0; la[1] += f0 * g1; la[2] += f0 * g2;
+            la[3] += f1 * g0; la[4] += f1 * g1; la[5] += f1 * g2;
+            la[6] += f2 * g0; la[7] += f2 * g1; la[8] += f2 * g2;
         }
     }
-    if (grad_frac) {
-        flush_src();
-        flush_window();
+    if (grad_frac) flush_src();
+    if (!grouped) {
+        if (acc) flush_lat();
+        return;
     }
-    if (acc) flush_lat();
+    const double lt = block_lattice(la, red, tid);
+    if (acc && tid < 9) {
+        if (it.whole) acc[9 * (int64_t)it.st + tid] = lt;
+        else unsafeAtomicAdd(&acc[9 * (int64_t)it.st + tid], lt);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_finalize_lattice(const double* __restrict__ acc, int64_t n,
@@ -291,25 +561,33 @@ hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const i
 }
 
 hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const int32_t* atom_struct,
-                               int B, int64_t N, const int32_t* src, const int32_t* dst,
-                               const int32_t* image, int64_t E, const int64_t* num_edges,
-                               const float* grad_vec, const float* grad_length, float* grad_frac,
-                               float* grad_lattice, double* acc, hipStream_t s) {
+                               const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
+                               const int32_t* dst, const int32_t* image, int64_t E,
+                               const int64_t* num_edges, const float* grad_vec, const float* grad_length,
+                               float* grad_frac, float* grad_lattice, const GeomBwdWs& w, hipStream_t s) {
     const int cu = device_cu_count();
     if (grad_frac && N > 0)
         hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(3 * N, 256, cu * 4)), dim3(256), 0, s, grad_frac, 3 * N);
     if (grad_lattice && B > 0)
-        hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(9 * (int64_t)B, 256, cu * 4)), dim3(256), 0, s, acc,
+        hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(9 * (int64_t)B, 256, cu * 4)), dim3(256), 0, s, w.acc,
                            9 * (int64_t)B);
-    if (E > 0 && (grad_frac || grad_lattice) && (grad_vec || grad_length)) {
-        const int grid = grid_for(E, 256 * 8, cu * 8);
-        hipLaunchKernelGGL(k_geom_bwd, dim3(grid), dim3(256), 0, s, lattices, frac, atom_struct, N, src,
-                           dst, image, E, num_edges, grad_vec, grad_length, grad_frac,
-                           grad_lattice ? acc : nullptr);
+    if (E > 0 && B > 0 && (grad_frac || grad_lattice) && (grad_vec || grad_length)) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, w.flag, 1);
+        hipLaunchKernelGGL(k_bwd_plan, dim3(grid_for(E, 256, cu * 16)), dim3(256), 0, s, src, dst, atom_struct, N,
+                           B, E, num_edges, w.start, w.flag);
+        hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, B, w.item_off);
+        // enough workgroups for either order: sum_s max(1, ceil(E_s / chunk)) <= B + ceil(E / chunk)
+        const int64_t grid = (int64_t)B + (E + BW_CHUNK - 1) / BW_CHUNK;
+        double* acc = grad_lattice ? w.acc : nullptr;
+        hipLaunchKernelGGL(k_geom_bwd_lds, dim3((unsigned)grid), dim3(256), 0, s, lattices, frac, batch_ptr, B,
+                           src, dst, image, grad_vec, grad_length, w.start, w.item_off, w.flag, grad_frac, acc);
+        hipLaunchKernelGGL(k_geom_bwd_any, dim3((unsigned)grid), dim3(256), 0, s, lattices, frac, atom_struct,
+                           batch_ptr, B, N, src, dst, image, E, num_edges, grad_vec, grad_length, w.start,
+                           w.item_off, w.flag, grad_frac, acc);
     }
     if (grad_lattice && B > 0)
         hipLaunchKernelGGL(k_finalize_lattice, dim3(grid_for(9 * (int64_t)B, 256, 1 << 30)), dim3(256), 0, s,
-                           acc, 9 * (int64_t)B, grad_lattice);
+                           w.acc, 9 * (int64_t)B, grad_lattice);
     return hipGetLastError();
 }
 

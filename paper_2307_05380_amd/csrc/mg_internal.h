@@ -219,11 +219,19 @@ hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const i
                                int64_t N, const int32_t* src, const int32_t* dst, const int32_t* image,
                                int64_t E, const int64_t* num_edges, float* vec, float* length,
                                hipStream_t s);
+// Workspace of the geometry backward pass: lattice accumulators (9 B), edge
+// range of every structure (B + 1), items per structure (B + 1), order flag.
+struct GeomBwdWs {
+    double* acc;
+    int64_t* start;
+    int64_t* item_off;
+    int32_t* flag;
+};
 hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const int32_t* atom_struct,
-                               int B, int64_t N, const int32_t* src, const int32_t* dst,
-                               const int32_t* image, int64_t E, const int64_t* num_edges,
-                               const float* grad_vec, const float* grad_length, float* grad_frac,
-                               float* grad_lattice, double* acc, hipStream_t s);
+                               const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
+                               const int32_t* dst, const int32_t* image, int64_t E,
+                               const int64_t* num_edges, const float* grad_vec, const float* grad_length,
+                               float* grad_frac, float* grad_lattice, const GeomBwdWs& w, hipStream_t s);
 // Per-wave partial counts (candidates evaluated) are written to a workspace
 // array and summed by one block afterwards: no shared-counter atomics in the
 // sweeps. The array holds MAX_GRID_WAVES entries.

@@ -100,3 +100,77 @@ def test_backward_random_edge_order():
     rf, rL = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, gv, None)
     assert _rel_err(gf.cpu().numpy(), rf) <= 1e-4
     assert _rel_err(gL.cpu().numpy(), rL) <= 1e-4
+
+
+def _per_structure_check(b, gf, gL, rf, rL, tol=1e-4):
+    worst_f = worst_L = 0.0
+    for q in range(b.B):
+        a0, a1 = b.batch_ptr[q], b.batch_ptr[q + 1]
+        if np.abs(rf[a0:a1]).max() > 0:
+            worst_f = max(worst_f, _rel_err(gf[a0:a1], rf[a0:a1]))
+        if np.abs(rL[q]).max() > 0:
+            worst_L = max(worst_L, _rel_err(gL[q], rL[q]))
+    print("worst relative errors", worst_f, worst_L)
+    assert worst_f <= tol and worst_L <= tol
+
+
+@pytest.mark.parametrize("m", [6, 8])
+def test_backward_supercells(m):
+    """Structures large enough that one structure's edges are split over
+    several workgroups (m = 6: 1728 atoms, ~10^5 edges) or exceed the LDS
+    atom window (m = 8: 4096 atoms), next to a small structure."""
+    big = inputs.make_config5(B=1, m_lo=m, m_hi=m)
+    small = inputs.random_batch(np.random.default_rng(30 + m), 2, 4, 30, 3.0, 7.0, cutoff=5.0)
+    b = gu.concat([small, big], cutoff=5.0, k=16)
+    g, (s, d, t, ln) = _edges(b)
+    rng = np.random.default_rng(40 + m)
+    gv = rng.normal(size=(len(s), 3)).astype(np.float32)
+    glen = rng.normal(size=len(s)).astype(np.float32)
+    L, X, P = gu.dev(b)
+    run = graph.GeometryRunner(b.B, b.N)
+    gf = torch.empty_like(X)
+    gL = torch.empty_like(L)
+    run.backward(L, X, P, g.src, g.dst, g.image, torch.from_numpy(gv).cuda(), torch.from_numpy(glen).cuda(), gf, gL)
+    rf, rL = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, gv, glen)
+    _per_structure_check(b, gf.cpu().numpy(), gL.cpu().numpy(), rf, rL)
+
+
+def test_backward_knn_edges():
+    """KNN edges (k per source, source-major) with both upstream gradients."""
+    b = inputs.make_config(4)
+    g = gu.knn(b)
+    s, d, t, ln = gu.np_graph(g)
+    rng = np.random.default_rng(12)
+    gv = rng.normal(size=(len(s), 3)).astype(np.float32)
+    glen = rng.normal(size=len(s)).astype(np.float32)
+    L, X, P = gu.dev(b)
+    run = graph.GeometryRunner(b.B, b.N)
+    gf = torch.empty_like(X)
+    gL = torch.empty_like(L)
+    run.backward(L, X, P, g.src, g.dst, g.image, torch.from_numpy(gv).cuda(), torch.from_numpy(glen).cuda(), gf, gL)
+    rf, rL = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, gv, glen)
+    _per_structure_check(b, gf.cpu().numpy(), gL.cpu().numpy(), rf, rL)
+
+
+def test_backward_empty_structures_and_no_edges():
+    """Structures without edges (isolated atoms far apart) get zero gradients;
+    an empty edge list gives all-zero outputs."""
+    b = gu.concat([gu.single(np.eye(3) * 20.0, [[0.1, 0.1, 0.1]]),
+                   inputs.random_batch(np.random.default_rng(5), 2, 3, 10, 3.0, 6.0, cutoff=4.0),
+                   gu.single(np.eye(3) * 30.0, [[0.5, 0.5, 0.5], [0.0, 0.0, 0.0]])], cutoff=4.0, k=4)
+    g, (s, d, t, ln) = _edges(b)
+    rng = np.random.default_rng(13)
+    gv = rng.normal(size=(len(s), 3)).astype(np.float32)
+    L, X, P = gu.dev(b)
+    run = graph.GeometryRunner(b.B, b.N)
+    gf = torch.full_like(X, 7.0)
+    gL = torch.full_like(L, 7.0)
+    run.backward(L, X, P, g.src, g.dst, g.image, torch.from_numpy(gv).cuda(), None, gf, gL)
+    rf, rL = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, gv, None)
+    gfn, gLn = gf.cpu().numpy(), gL.cpu().numpy()
+    assert np.all(gfn[0] == 0) and np.all(gLn[0] == 0) and np.all(gfn[-2:] == 0) and np.all(gLn[-1] == 0)
+    _per_structure_check(b, gfn, gLn, rf, rL)
+    z = torch.zeros(0, dtype=torch.int32, device="cuda")
+    run.backward(L, X, P, z, z, torch.zeros((0, 3), dtype=torch.int32, device="cuda"),
+                 torch.zeros((0, 3), device="cuda"), None, gf, gL)
+    assert float(gf.abs().max()) == 0.0 and float(gL.abs().max()) == 0.0
