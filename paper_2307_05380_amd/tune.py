@@ -9,7 +9,9 @@ Tunables (``mg_tuning`` in include/matgraph.h):
                      the first KNN search radius is sized for.
 
 Every candidate is timed with device events over repeated calls and must give
-bit-identical edges to the first candidate; the fastest is kept. Results are
+the same graph as the first candidate: the KNN edges bit for bit, the cutoff
+edges as a set (the order of a source's edges may depend on the tile shape) with
+identical per-source counts; the fastest is kept. Results are
 cached as JSON keyed by GPU architecture and workload signature
 (``MG_TUNE_CACHE`` or ``~/.cache/matgraph/tune.json``).
 """
@@ -55,12 +57,33 @@ def _time(fn, reps: int) -> float:
     return a.elapsed_time(b) / reps
 
 
-def _snapshot(builder, count):
-    return [t[:count].clone() for t in (builder.src, builder.dst, builder.image, builder.length)]
+def _mix(x: torch.Tensor) -> torch.Tensor:
+    """64-bit mixing of int64 values (wrapping arithmetic)."""
+    x = x * -7046029254386353131
+    x = x ^ (x >> 29)
+    return x * -4658895280553007687
+
+
+def _cutoff_signature(b, count):
+    """Per-source edge counts plus an order-independent checksum of the edges."""
+    E = int(count)
+    h = _mix(b.src[:E].long() * 1000003 + b.dst[:E].long())
+    for c in range(3):
+        h = _mix(h + b.image[:E, c].long() + 7 * (c + 1))
+    h = _mix(h + b.length[:E].view(torch.int32).long())
+    return [b.row_ptr.clone(), h.sum().view(1)]
+
+
+def _knn_signature(b):
+    return [t.clone() for t in (b.src, b.dst, b.image, b.length)]
 
 
 def _same(a, b):
     return all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+def _clean(rep) -> bool:
+    return (rep.flags & ~_lib.MG_FLAG_KNN_EXTENDED) == 0
 
 
 def tune(lattices, frac, batch_ptr, cutoff: float, k: int, reps: int = 5, space_cutoff=None,
@@ -69,36 +92,42 @@ def tune(lattices, frac, batch_ptr, cutoff: float, k: int, reps: int = 5, space_
     B, N = int(lattices.shape[0]), int(frac.shape[0])
     dev = frac.device
     base = _lib.get_tuning()
-    g = graph.cutoff_graph(lattices, frac, batch_ptr, cutoff)
+    space_cutoff = space_cutoff or CUTOFF_SPACE
+    space_knn = space_knn or KNN_SPACE
+    opts = graph.auto_opts(batch_ptr, None)
+    g = graph.cutoff_graph(lattices, frac, batch_ptr, cutoff, opts=opts)
     E, icap = g.num_edges, g.report.images_needed
-    kg = graph.knn_graph(lattices, frac, batch_ptr, k)
-    kcap = kg.report.images_needed
+    del g
+    # the first KNN radius (hence the image tables) depends on knn_lambda_x4
+    kcap = 1
+    for lam in sorted(set(space_knn.get("knn_lambda_x4", [base["knn_lambda_x4"]]))):
+        _lib.set_tuning(knn_lambda_x4=lam)
+        kcap = max(kcap, graph.knn_graph(lattices, frac, batch_ptr, k, opts=opts).report.images_needed)
+    _lib.set_tuning(**base)
     cb = graph.CutoffBuilder(B, N, max(E, 1), max(icap, 1), dev)
     kb = graph.KnnBuilder(B, N, k, max(kcap, 1), dev)
     results = {"cutoff": [], "knn": []}
     ref = None
-    space_cutoff = space_cutoff or CUTOFF_SPACE
     for vals in itertools.product(*space_cutoff.values()):
         cfg = dict(zip(space_cutoff.keys(), vals))
         _lib.set_tuning(**cfg)
-        ms = _time(lambda: cb.run(lattices, frac, batch_ptr, cutoff), reps)
-        snap = _snapshot(cb, E)
+        ms = _time(lambda: cb.run(lattices, frac, batch_ptr, cutoff, opts), reps)
+        snap = _cutoff_signature(cb, E)
         if ref is None:
             ref = snap
-        ok = _same(ref, snap)
+        ok = _same(ref, snap) and _clean(cb.report())
         results["cutoff"].append((ms, cfg, ok))
         if verbose:
             print("cutoff", cfg, f"{ms:.4f} ms", "ok" if ok else "MISMATCH", flush=True)
     ref = None
-    space_knn = space_knn or KNN_SPACE
     for vals in itertools.product(*space_knn.values()):
         cfg = dict(zip(space_knn.keys(), vals))
         _lib.set_tuning(**cfg)
-        ms = _time(lambda: kb.run(lattices, frac, batch_ptr), reps)
-        snap = _snapshot(kb, N * k)
+        ms = _time(lambda: kb.run(lattices, frac, batch_ptr, opts), reps)
+        snap = _knn_signature(kb)
         if ref is None:
             ref = snap
-        ok = _same(ref, snap)
+        ok = _same(ref, snap) and _clean(kb.report())
         results["knn"].append((ms, cfg, ok))
         if verbose:
             print("knn", cfg, f"{ms:.4f} ms", "ok" if ok else "MISMATCH", flush=True)
