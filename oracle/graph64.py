@@ -1,10 +1,11 @@
 """FP64 brute-force cutoff and KNN multigraphs (oracle; test infrastructure only).
 
-What is computed (paper Sec. 2.1, Definition def6, with a constant cutoff c):
+What is computed (paper Sec. 2.1, Definition def6):
 
-    Gamma_1 = {(i, j, t) in Gamma_0 x Gamma_0 x Z^3 : || (x_j - x_i + t) L || < c}
+    Gamma_1 = {(i, j, t) in Gamma_0 x Gamma_0 x Z^3 : || (x_j - x_i + t) L || < c_i}
 
-minus the self-image (i, i, 0). Because a periodic crystal is a multigraph
+with c_i the cutoff of the source atom (one constant c for every atom in the
+common case), minus the self-image (i, i, 0). Because a periodic crystal is a multigraph
 (Sec. 1), a pair (i, j) may carry several edges, and an atom has edges to its
 own images (i, i, t != 0).
 
@@ -116,24 +117,27 @@ def _candidates_within(L: np.ndarray, x: np.ndarray, i: int, R: float):
     return jj.astype(np.int64), T[tt], length[jj, tt]
 
 
-def cutoff_structure64(L, x, cutoff: float, band: float = 0.0):
-    """Edges of one structure with length < cutoff + band, sorted by (src, dst, t).
+def cutoff_structure64(L, x, cutoff, band: float = 0.0):
+    """Edges of one structure with length < c_src + band, sorted by (src, dst, t).
 
-    Returns local (src, dst, image [E,3], length) arrays; with band = 0 this is
-    exactly Definition def6 with a constant cutoff.
+    ``cutoff`` is one distance for every atom, or an array of per-atom cutoffs
+    c_i (the cutoff of an edge is its source's, Definition def6). Returns local
+    (src, dst, image [E,3], length) arrays; with band = 0 this is exactly
+    Definition def6.
     """
     return cutoff_sources64(L, x, cutoff, range(np.asarray(x).shape[0]), band)
 
 
-def cutoff_sources64(L, x, cutoff: float, sources, band: float = 0.0):
-    """Edges of the listed sources of one structure with length < cutoff + band
+def cutoff_sources64(L, x, cutoff, sources, band: float = 0.0):
+    """Edges of the listed sources of one structure with length < c_src + band
     (same definition as ``cutoff_structure64``, restricted to some sources, for
     structures too large to enumerate whole). Sorted by (src, dst, t)."""
     L = np.asarray(L, np.float64)
     x = np.asarray(x, np.float64)
-    R = float(cutoff) + float(band)
+    radii = np.broadcast_to(np.asarray(cutoff, np.float64), (x.shape[0],))
     out = [[], [], [], []]
     for i in sources:
+        R = float(radii[int(i)]) + float(band)
         j, t, length = _candidates_within(L, x, int(i), R)
         m = length < R
         out[0].append(np.full(int(m.sum()), int(i), np.int64))
@@ -231,14 +235,16 @@ def _single_thread_blas():
         os.environ[var] = "1"
 
 
-def cutoff_graph64(lattices, frac, batch_ptr, cutoff: float, band: float = 0.0,
+def cutoff_graph64(lattices, frac, batch_ptr, cutoff, band: float = 0.0,
                    structures=None, processes: int | None = None) -> Graph64:
     """Cutoff multigraph of a batch (global atom indices), structure-major, each
-    structure's edges sorted by (src, dst, t). ``structures`` restricts the
-    computation to a subset of structure indices (in the given order)."""
+    structure's edges sorted by (src, dst, t). ``cutoff`` is a scalar or an
+    array [N] of per-atom cutoffs. ``structures`` restricts the computation to a
+    subset of structure indices (in the given order)."""
     lattices = np.asarray(lattices, np.float64)
     frac = np.asarray(frac, np.float64)
-    jobs = [(lattices[s], frac[a:e], cutoff, band, a)
+    radii = np.broadcast_to(np.asarray(cutoff, np.float64), (frac.shape[0],))
+    jobs = [(lattices[s], frac[a:e], radii[a:e], band, a)
             for s, a, e in _structure_slices(batch_ptr, structures)]
     parts = _run(_cutoff_task, jobs, processes)
     if not parts:

@@ -314,7 +314,89 @@ def pin_gradients(O, seed=7):
         assert abs(np.trace(M) - float((ln * gl)[s_of == s].sum())) <= 1e-9 * np.abs(M).max()
 
 
+# ------------------------------------------------------------ per-atom cutoffs
+
+
+def pin_radii_closed_form(O):
+    """CsCl arrangement (cubic a = 1, A at 0, B at the body centre): A-B at
+    sqrt(3)/2, A-A and B-B at 1. With c_A = 0.95 and c_B = 1.05 every A has the
+    8 B around it and every B the 8 A plus its 6 B images: the graph is not
+    symmetric, and an edge's cutoff is its source's."""
+    x = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]])
+    src, dst, img, ln = O.cutoff_structure64(np.eye(3), x, np.array([0.95, 1.05]))
+    counts = np.bincount(src, minlength=2)
+    assert counts.tolist() == [8, 14], counts
+    assert (dst[src == 0] == 1).all()
+    assert np.allclose(ln[src == 0], math.sqrt(3.0) / 2.0)
+    assert (np.sort(ln[src == 1])[8:] > 0.999).all()
+    src, _, _, _ = O.cutoff_structure64(np.eye(3), x, np.array([0.8, 0.9]))
+    assert np.bincount(src, minlength=2).tolist() == [0, 8]
+
+
+def pin_radii_restriction(O, seed=8):
+    """Per-atom cutoffs: the out-edges of source i are exactly the constant-cutoff
+    graph at c = c_i restricted to i; equal radii give the constant graph."""
+    rng = np.random.default_rng(seed)
+    L, x = _random_structure(rng, 5)
+    radii = rng.uniform(2.0, 6.0, size=5)
+    s, d, t, ln = O.cutoff_structure64(L, x, radii)
+    got = _edges_set(s, d, t)
+    want = set()
+    for i in range(5):
+        cs, cd, ct, cl = O.cutoff_structure64(L, x, float(radii[i]))
+        m = cs == i
+        want |= _edges_set(cs[m], cd[m], ct[m])
+    assert got == want
+    s1, d1, t1, l1 = O.cutoff_structure64(L, x, np.full(5, 4.5))
+    s2, d2, t2, l2 = O.cutoff_structure64(L, x, 4.5)
+    assert _edges_set(s1, d1, t1) == _edges_set(s2, d2, t2)
+
+
+# --------------------------------------------------------------------- triplets
+
+
+def pin_triplets_closed_form(O):
+    """Tetragonal cell a = b = 1, c = 1.5, one atom, cutoff 1.45: the 8 edges are
+    +-x, +-y and the 4 in-plane diagonals (+-1, +-1, 0). 56 ordered pairs; their
+    angles follow from those 8 vectors written out here."""
+    L = np.diag([1.0, 1.0, 1.5])
+    src, dst, img, ln = O.cutoff_structure64(L, np.zeros((1, 3)), 1.45)
+    assert len(src) == 8
+    ptr = np.array([0, 8])
+    e1, e2 = O.triplets64(ptr)
+    assert len(e1) == 56 and (e1 != e2).all()
+    assert len(set(zip(e1.tolist(), e2.tolist()))) == 56
+    vec, _ = O.edge_geometry64(L[None], np.zeros((1, 3)), np.array([0, 1]), src, dst, img)
+    cos = O.triplet_cos64(vec, e1, e2)
+    known = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                      [1, 1, 0], [1, -1, 0], [-1, 1, 0], [-1, -1, 0]], np.float64)
+    want = []
+    for p, q in itertools.permutations(range(8), 2):
+        u, w = known[p], known[q]
+        want.append(float(u @ w) / math.sqrt(float(u @ u) * float(w @ w)))
+    assert np.allclose(np.sort(cos), np.sort(want), atol=1e-12)
+    assert np.isclose(np.sort(cos)[0], -1.0) and np.isclose(np.sort(cos)[-1], 1.0 / math.sqrt(2.0))
+
+
+def pin_triplets_brute_force(O, seed=9):
+    """Random degrees (including 0 and 1): the pairs are exactly the ordered
+    pairs of distinct edges of each source, sum_i d_i (d_i - 1) of them, in
+    (source, first, second) order."""
+    rng = np.random.default_rng(seed)
+    deg = rng.integers(0, 7, size=12)
+    deg[3] = 0
+    deg[5] = 1
+    ptr = np.concatenate([[0], np.cumsum(deg)])
+    e1, e2 = O.triplets64(ptr)
+    want = []
+    for i in range(12):
+        want += list(itertools.permutations(range(ptr[i], ptr[i + 1]), 2))
+    assert list(zip(e1.tolist(), e2.tolist())) == sorted(want)
+    assert len(e1) == int((deg * (deg - 1)).sum())
+
+
 ALL_PINS = [pin_cubic_shells, pin_sc_sum_of_three_squares, pin_strict_cutoff, pin_row_convention,
             pin_figure1, pin_knn_tie_break, pin_knn_single_atom_and_cluster, pin_symmetry,
             pin_supercell, pin_unimodular, pin_translation, pin_enormous_range, pin_knn_vs_cutoff,
-            pin_gradients]
+            pin_gradients, pin_radii_closed_form, pin_radii_restriction, pin_triplets_closed_form,
+            pin_triplets_brute_force]

@@ -25,6 +25,8 @@ MUTATIONS = [
     ("graph64", "d = x - x[i]", "d = x[i] - x", "displacement sign x_i - x_j"),
     ("graph64", "keep[i, self_t[0]] = False", "pass", "self-image (i, i, 0) kept"),
     ("graph64", "m = length < R", "m = length <= R", "non-strict cutoff"),
+    ("graph64", "R = float(radii[int(i)]) + float(band)", "R = float(radii.max()) + float(band)",
+     "largest per-atom cutoff used for every source"),
     ("graph64", "lo = np.ceil(-R * r - d - _BOX_SLACK)", "lo = np.ceil(-R * r + d - _BOX_SLACK)",
      "sign error in the lower image bound"),
     ("graph64", "hi = np.floor(R * r - d + _BOX_SLACK)", "hi = np.floor(R * r - d + _BOX_SLACK - 1)",
@@ -34,6 +36,10 @@ MUTATIONS = [
     ("graph64", "order = np.lexsort((t[:, 2], t[:, 1], t[:, 0], j, ln))",
      "order = np.lexsort((t[:, 2], t[:, 1], t[:, 0], ln, j))", "KNN ordered by dst before length"),
     ("graph64", "sel = order[:k]", "sel = order[1:k + 1]", "KNN off-by-one selection"),
+    ("triplets64", "keep = a != b", "keep = a >= 0", "triplets include the pair (g, g)"),
+    ("triplets64", "b = np.tile(idx, d)", "b = np.repeat(idx, d)", "second edge of the pair not varied"),
+    ("triplets64", "den = np.sqrt((a * a).sum(1)) * np.sqrt((b * b).sum(1))", "den = (a * a).sum(1)",
+     "angle normalised by the first edge's squared length"),
     ("geometry64", "+ np.asarray(image, np.float64)", "+ 0.0 * np.asarray(image, np.float64)",
      "image offset dropped from the edge vector"),
     ("geometry64", 'v = np.einsum("ek,ekm->em", f, lattices[s])', 'v = np.einsum("ek,emk->em", f, lattices[s])',
