@@ -107,6 +107,9 @@ size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_cap
 /* Workspace bytes for mg_edge_geometry / mg_edge_geometry_backward. */
 size_t mg_geometry_workspace_bytes(int32_t B, int64_t N);
 
+/* Workspace bytes for mg_triplets on a graph of N source atoms (0 if N < 0). */
+size_t mg_triplets_workspace_bytes(int64_t N);
+
 /*
  * Periodic cutoff multigraph (Definition def6 with a constant cutoff c_i = cutoff).
  *
@@ -129,6 +132,24 @@ mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_
                           int32_t* src, int32_t* dst, int32_t* image, float* length,
                           int64_t* row_ptr, mg_report* report,
                           void* workspace, size_t workspace_bytes, int32_t opts, void* stream);
+
+/*
+ * Periodic cutoff multigraph with per-atom cutoffs (Definition def6: the edge
+ * (i, j, t) exists when its length is < c_i, the cutoff of its SOURCE atom, so
+ * the graph need not be symmetric).
+ *
+ *  radii         float32 [N] device, c_i in Angstrom for every atom (global index);
+ *                each must be finite and > 0, else that structure is skipped and
+ *                MG_FLAG_NONFINITE is set. A structure's image range is taken at its
+ *                largest c_i. May be NULL only when N == 0.
+ *  All other arguments, outputs, ordering and errors as for mg_cutoff_graph; the
+ *  workspace size is the same (mg_cutoff_workspace_bytes).
+ */
+mg_status mg_cutoff_graph_radii(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                                int32_t B, int64_t N, const float* radii, int64_t capacity,
+                                int32_t* src, int32_t* dst, int32_t* image, float* length,
+                                int64_t* row_ptr, mg_report* report,
+                                void* workspace, size_t workspace_bytes, int32_t opts, void* stream);
 
 /*
  * Periodic k-nearest-neighbour multigraph (Sec. 1; Sec. 2.2 Algorithms 1-2).
@@ -176,6 +197,30 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac,
                                     const float* grad_vec, const float* grad_length,
                                     float* grad_frac, float* grad_lattice,
                                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Triplets (Definition def6, Gamma_2): every ordered pair (e1, e2) of two
+ * different edges with the same source, for pair-based (angle) message passing.
+ *
+ *  row_ptr       int64 [N+1] device: the graph's edges of source i are
+ *                row_ptr[i] .. row_ptr[i+1]-1 (mg_cutoff_graph's row_ptr; i*k for a
+ *                KNN graph). Sources with an invalid range (negative, decreasing, past
+ *                E, or more than 65536 edges) get no triplets and set MG_FLAG_RANGE.
+ *  E             number of edges of the graph (< 2^31; edge indices are int32).
+ *  vec           float32 [E][3] edge vectors (mg_edge_geometry) or NULL.
+ *  capacity      slots in e1/e2/cos_theta (>= 0).
+ *  e1, e2        int32 [capacity]: edge indices of the pair, ordered by source, then
+ *                e1, then e2 (e2 != e1).
+ *  cos_theta     float32 [capacity] or NULL: (v1 . v2) / (|v1| |v2|), 0 if a vector is 0.
+ *  trip_ptr      int64 [N+1] or NULL: triplets of source i are trip_ptr[i] .. trip_ptr[i+1]-1.
+ *  report        mg_report: num_edges = number of triplets (exact even past capacity;
+ *                MG_FLAG_CAPACITY then, and nothing is written past capacity).
+ * Errors: MG_ERR_INVALID_ARG (N < 0, E out of range, NULL row_ptr/report, NULL e1/e2
+ * with capacity > 0, cos_theta without vec), MG_ERR_WORKSPACE.
+ */
+mg_status mg_triplets(const int64_t* row_ptr, int64_t N, int64_t E, const float* vec, int64_t capacity,
+                      int32_t* e1, int32_t* e2, float* cos_theta, int64_t* trip_ptr, mg_report* report,
+                      void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---- launch tuning and profiling (host-side state, per process) ---------- */
 

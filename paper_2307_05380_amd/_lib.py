@@ -61,10 +61,14 @@ SIGNATURES = {
     "mg_geometry_workspace_bytes": (_SZ, [_I32, _I64]),
     "mg_cutoff_graph": (_I32, [_P, _P, _P, _I32, _I64, _F, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ,
                                _I32, _P]),
+    "mg_cutoff_graph_radii": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
+                                     _SZ, _I32, _P]),
     "mg_knn_graph": (_I32, [_P, _P, _P, _I32, _I64, _I32, _P, _P, _P, _P, _P, _P, _SZ, _I32, _P]),
     "mg_edge_geometry": (_I32, [_P, _P, _P, _I32, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "mg_edge_geometry_backward": (_I32, [_P, _P, _P, _I32, _I64, _P, _P, _P, _I64, _P, _P, _P, _P,
                                          _P, _P, _SZ, _P]),
+    "mg_triplets_workspace_bytes": (_SZ, [_I64]),
+    "mg_triplets": (_I32, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "mg_get_tuning": (_I32, [ctypes.POINTER(MgTuning)]),
     "mg_set_tuning": (_I32, [ctypes.POINTER(MgTuning)]),
     "mg_profile_enable": (_I32, [_I32]),

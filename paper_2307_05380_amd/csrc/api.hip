@@ -127,6 +127,7 @@ struct CutoffWs {
     int64_t* offsets;
     int64_t* bsum;
     int64_t* partials;
+    float* thr;
     mg::ClWs cl;
     mg::ImageEntry* table;
     int64_t table_cap;
@@ -151,6 +152,7 @@ CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
     w.offsets = c.take<int64_t>((size_t)N + 1);
     w.bsum = c.take<int64_t>((size_t)mg::scan_block_count(N) + 1);
     w.partials = c.take<int64_t>((size_t)mg::MAX_GRID_WAVES);
+    w.thr = c.take<float>((size_t)N);
     carve_cl(c, B, N, w.ctr, w.cl);
     w.table = c.take<mg::ImageEntry>(0);
     w.fixed = c.used;
@@ -205,6 +207,23 @@ GeomWs carve_geom(void* ws, int B, int64_t N) {
     return w;
 }
 
+struct TripWs {
+    uint32_t* counts;
+    int64_t* offsets;
+    int64_t* bsum;
+    size_t fixed;
+};
+
+TripWs carve_triplets(void* ws, int64_t N) {
+    Carver c{static_cast<char*>(ws)};
+    TripWs w;
+    w.counts = c.take<uint32_t>((size_t)N);
+    w.offsets = c.take<int64_t>((size_t)N + 1);
+    w.bsum = c.take<int64_t>((size_t)mg::scan_block_count(N) + 1);
+    w.fixed = mg::align_up(c.used, 256);
+    return w;
+}
+
 // Smallest float y with sqrtf(y) >= c, so that l2 < y  <=>  sqrtf(l2) < c.
 float cutoff_threshold(float c) {
     float y = c * c;
@@ -253,20 +272,29 @@ size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_cap
     return w.fixed + (size_t)image_capacity * sizeof(mg::ImageEntry);
 }
 
+size_t mg_triplets_workspace_bytes(int64_t N) {
+    if (N < 0) return 0;
+    return carve_triplets(nullptr, N).fixed;
+}
+
 size_t mg_geometry_workspace_bytes(int32_t B, int64_t N) {
     if (B < 0 || N < 0) return 0;
     return carve_geom(nullptr, B, N).fixed;
 }
 
-mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_t* batch_ptr,
-                          int32_t B, int64_t N, float cutoff, int64_t capacity, int32_t* src,
-                          int32_t* dst, int32_t* image, float* length, int64_t* row_ptr,
-                          mg_report* report, void* workspace, size_t workspace_bytes, int32_t opts,
-                          void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Both cutoff entry points: one constant cutoff, or per-atom cutoffs (radii).
+mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
+                       int64_t N, float cutoff, const float* radii, int64_t capacity, int32_t* src,
+                       int32_t* dst, int32_t* image, float* length, int64_t* row_ptr, mg_report* report,
+                       void* workspace, size_t workspace_bytes, int32_t opts, void* stream) {
     g_err.clear();
     mg_status st = check_common(lattices, frac, batch_ptr, B, N);
     if (st != MG_OK) return st;
-    if (!(cutoff > 0.0f) || !std::isfinite(cutoff))
+    if (!radii && (!(cutoff > 0.0f) || !std::isfinite(cutoff)))
         return fail(MG_ERR_INVALID_ARG, "cutoff must be finite and > 0 (got %g)", (double)cutoff);
     if (capacity < 0) return fail(MG_ERR_INVALID_ARG, "capacity must be >= 0");
     if (capacity > 0 && (!src || !dst || !image || !length))
@@ -281,7 +309,8 @@ mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_
                     workspace_bytes, w.fixed);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const mg_tuning tu = tuning();
-    const float c2 = cutoff_threshold(cutoff);
+    const float c2 = radii ? 0.0f : cutoff_threshold(cutoff);
+    float* thr = radii ? w.thr : nullptr;
     int64_t* offs = row_ptr ? row_ptr : w.offsets;
     const int grid = sweep_grid(tu.cutoff_wgs_per_cu);
     const bool sum = B > 0 && N > 0;
@@ -289,8 +318,8 @@ mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_
     if ((e = mg::launch_zero_report(report, w.ctr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
     const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
     if ((e = phase("cutoff.bounds", s, [&] {
-             return mg::launch_bounds(lattices, batch_ptr, frac, B, N, cutoff, 0, 0.f, w.info, w.ctr,
-                                      report, 0, opts, s);
+             return mg::launch_bounds(lattices, batch_ptr, frac, B, N, cutoff, radii, thr, 0, 0.f, w.info,
+                                      w.ctr, report, 0, opts, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("cutoff.plan", s, [&] {
@@ -304,7 +333,7 @@ mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_
                   hipSuccess)
         return hip_fail(e, "cell lists");
     if ((e = phase("cutoff.count", s, [&] {
-             hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.table, frac, c2, w.counts, offs,
+             hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.table, frac, c2, thr, w.counts, offs,
                                                     capacity, src, dst, image, length, w.ctr, report, w.partials,
                                                     grid, tu.cutoff_slots, s);
              if (r != hipSuccess || !sum) return r;
@@ -312,7 +341,7 @@ mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_
          })) != hipSuccess)
         return hip_fail(e, "count");
     if (cl && (e = phase("cutoff.cells.count", s, [&] {
-                   hipError_t r = mg::launch_cl_cutoff_sweep(0, B, w.info, w.cl, frac, c2, w.counts, offs,
+                   hipError_t r = mg::launch_cl_cutoff_sweep(0, B, w.info, w.cl, frac, c2, thr, w.counts, offs,
                                                              capacity, src, dst, image, length, w.ctr, report,
                                                              w.partials, grid, s);
                    if (r != hipSuccess || !sum) return r;
@@ -324,17 +353,44 @@ mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_
          })) != hipSuccess)
         return hip_fail(e, "scan");
     if ((e = phase("cutoff.fill", s, [&] {
-             return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.table, frac, c2, w.counts, offs,
+             return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.table, frac, c2, thr, w.counts, offs,
                                             capacity, src, dst, image, length, w.ctr, report, w.partials,
                                             grid, tu.cutoff_slots, s);
          })) != hipSuccess)
         return hip_fail(e, "fill");
     if (cl && (e = phase("cutoff.cells.fill", s, [&] {
-                   return mg::launch_cl_cutoff_sweep(1, B, w.info, w.cl, frac, c2, w.counts, offs, capacity, src,
+                   return mg::launch_cl_cutoff_sweep(1, B, w.info, w.cl, frac, c2, thr, w.counts, offs, capacity, src,
                                                      dst, image, length, w.ctr, report, w.partials, grid, s);
                })) != hipSuccess)
         return hip_fail(e, "cell-list fill");
     return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                          int32_t B, int64_t N, float cutoff, int64_t capacity, int32_t* src,
+                          int32_t* dst, int32_t* image, float* length, int64_t* row_ptr,
+                          mg_report* report, void* workspace, size_t workspace_bytes, int32_t opts,
+                          void* stream) {
+    return cutoff_graph(lattices, frac, batch_ptr, B, N, cutoff, nullptr, capacity, src, dst, image, length,
+                        row_ptr, report, workspace, workspace_bytes, opts, stream);
+}
+
+mg_status mg_cutoff_graph_radii(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                                int32_t B, int64_t N, const float* radii, int64_t capacity, int32_t* src,
+                                int32_t* dst, int32_t* image, float* length, int64_t* row_ptr,
+                                mg_report* report, void* workspace, size_t workspace_bytes, int32_t opts,
+                                void* stream) {
+    if (N > 0 && !radii) {
+        g_err.clear();
+        return fail(MG_ERR_INVALID_ARG, "radii is NULL");
+    }
+    // with no atoms there is nothing to read: any valid constant gives the same (empty) graph
+    return cutoff_graph(lattices, frac, batch_ptr, B, N, 1.0f, N > 0 ? radii : nullptr, capacity, src, dst,
+                        image, length, row_ptr, report, workspace, workspace_bytes, opts, stream);
 }
 
 mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
@@ -366,8 +422,8 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
     if ((e = mg::launch_zero_report(report, w.ctr, N * (int64_t)k, s)) != hipSuccess) return hip_fail(e, "zero");
     const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
     if ((e = phase("knn.bounds", s, [&] {
-             return mg::launch_bounds(lattices, batch_ptr, frac, B, N, 0.f, k, lambda, w.info, w.ctr,
-                                      report, 1, opts, s);
+             return mg::launch_bounds(lattices, batch_ptr, frac, B, N, 0.f, nullptr, nullptr, k, lambda,
+                                      w.info, w.ctr, report, 1, opts, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("knn.plan", s, [&] {
@@ -462,6 +518,33 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac, co
                                             num_edges, grad_vec, grad_length, grad_frac, grad_lattice, w.bwd, s);
          })) != hipSuccess)
         return hip_fail(e, "geometry backward");
+    return MG_OK;
+}
+
+mg_status mg_triplets(const int64_t* row_ptr, int64_t N, int64_t E, const float* vec, int64_t capacity,
+                      int32_t* e1, int32_t* e2, float* cos_theta, int64_t* trip_ptr, mg_report* report,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+    g_err.clear();
+    if (N < 0) return fail(MG_ERR_INVALID_ARG, "N must be >= 0");
+    if (E < 0 || E > (int64_t)INT32_MAX) return fail(MG_ERR_INVALID_ARG, "E must be in [0, 2^31) (got %lld)", (long long)E);
+    if (!row_ptr) return fail(MG_ERR_INVALID_ARG, "row_ptr is NULL");
+    if (capacity < 0) return fail(MG_ERR_INVALID_ARG, "capacity must be >= 0");
+    if (capacity > 0 && (!e1 || !e2)) return fail(MG_ERR_INVALID_ARG, "e1/e2 must be non-NULL when capacity > 0");
+    if (cos_theta && !vec) return fail(MG_ERR_INVALID_ARG, "cos_theta needs the edge vectors (vec is NULL)");
+    if (!report) return fail(MG_ERR_INVALID_ARG, "report is NULL");
+    if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    TripWs w = carve_triplets(workspace, N);
+    if (workspace_bytes < w.fixed)
+        return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    workspace_bytes, w.fixed);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = mg::launch_zero_report(report, nullptr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
+    if ((e = phase("triplets", s, [&] {
+             return mg::launch_triplets(row_ptr, N, E, vec, capacity, e1, e2, cos_theta,
+                                        trip_ptr ? trip_ptr : w.offsets, w.counts, w.bsum, report, s);
+         })) != hipSuccess)
+        return hip_fail(e, "triplets");
     return MG_OK;
 }
 

@@ -32,12 +32,33 @@ hipError_t launch_zero_report(mg_report* report, Counters* ctr, int64_t num_edge
 
 // ------------------------------------------------------------------- bounds
 
-// mode 0: cutoff, radius = cutoff; mode 1: KNN first search, radius from density.
+// Smallest float y whose correctly rounded square root is >= c, so that the
+// sweep's test l^2 < y is exactly sqrtf(l^2) < c (the strict cutoff on the
+// FP32 length). The FP64 square root rounded to FP32 is the correctly rounded
+// FP32 square root (53 >= 2 * 24 + 2 bits).
+__device__ inline float cutoff_threshold_dev(float c) {
+    auto csqrt = [](float v) { return (float)sqrt((double)v); };
+    float y = (float)((double)c * (double)c);
+    if (csqrt(y) >= c) {
+        for (int it = 0; it < 16; ++it) {
+            const float d = nextafterf(y, 0.0f);
+            if (d <= 0.0f || csqrt(d) < c) break;
+            y = d;
+        }
+    } else {
+        for (int it = 0; it < 16 && csqrt(y) < c; ++it) y = nextafterf(y, INFINITY);
+    }
+    return y;
+}
+
+// mode 0: cutoff, radius = cutoff (or the largest per-atom cutoff of the
+// structure); mode 1: KNN first search, radius from density.
 // One wave per structure: every lane scans coordinates for non-finite values,
 // lane 0 does the FP64 lattice work.
 __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattices,
                                                const int64_t* __restrict__ ptr,
                                                const float* __restrict__ frac, int B, float radius,
+                                               const float* __restrict__ radii, float* __restrict__ thr,
                                                int knn_k, float knn_lambda,
                                                StructInfo* __restrict__ info,
                                                mg_report* __restrict__ rep, int mode, int opts) {
@@ -46,11 +67,21 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     const int lane = threadIdx.x;
     const int64_t a0 = ptr[b], a1 = ptr[b + 1];
     bool bad = false;
+    float rmax = 0.0f;
     for (int64_t a = a0 + lane; a < a1; a += WAVE) {
         float x = frac[3 * a], y = frac[3 * a + 1], z = frac[3 * a + 2];
         bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+        if (radii) {
+            const float r = radii[a];
+            const bool ok = isfinite(r) && r > 0.0f;
+            bad |= !ok;
+            rmax = ok ? fmaxf(rmax, r) : rmax;
+            thr[a] = ok ? cutoff_threshold_dev(r) : 0.0f;
+        }
     }
     const bool any_bad = ballot(bad) != 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, d, WAVE));
     if (lane != 0) return;
 
     StructInfo si;
@@ -82,7 +113,7 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     if (!(fabs(det) >= 1e-9 * scale) || !(scale > 0.0)) flags |= MG_FLAG_SINGULAR;
     const int n = (int)(a1 - a0);
 
-    double R = (double)radius;
+    double R = radii ? (double)rmax : (double)radius;
     if (mode == 1 && n > 0 && !(flags & (MG_FLAG_SINGULAR | MG_FLAG_NONFINITE))) {
         // expected number of candidates inside R for a uniform density n / V is
         // n (4/3) pi R^3 / V; aim for lambda of them
@@ -171,12 +202,13 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
 }
 
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
-                         int64_t N, float radius, int knn_k, float knn_lambda, StructInfo* info,
-                         Counters* ctr, mg_report* report, int mode, int opts, hipStream_t s) {
+                         int64_t N, float radius, const float* radii, float* thr, int knn_k,
+                         float knn_lambda, StructInfo* info, Counters* ctr, mg_report* report, int mode,
+                         int opts, hipStream_t s) {
     (void)N;
     (void)ctr;
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bounds, dim3(B), dim3(64), 0, s, lattices, batch_ptr, frac, B, radius,
+    hipLaunchKernelGGL(k_bounds, dim3(B), dim3(64), 0, s, lattices, batch_ptr, frac, B, radius, radii, thr,
                        knn_k, knn_lambda, info, report, mode, opts);
     return hipGetLastError();
 }

@@ -221,6 +221,7 @@ hipError_t launch_cl_build(int B, int64_t N, const float* frac, const int64_t* b
 template <int MODE>
 __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __restrict__ info, ClWs w,
                                                   const float* __restrict__ frac, float c2thr,
+                                                  const float* __restrict__ thr,
                                                   uint32_t* __restrict__ counts,
                                                   const int64_t* __restrict__ offsets, int64_t capacity,
                                                   int32_t* __restrict__ src, int32_t* __restrict__ dst,
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
         }
         const StructInfo* si = info + lo;
         const int64_t i = si->atom0 + (q - w.cl_off[lo]);
+        const float c2 = thr ? thr[i] : c2thr;   // the source's cutoff
         const int m[3] = {si->m[0], si->m[1], si->m[2]};
         double L[9];
 #pragma unroll
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                     const float dy = e.y + fmaf(kz, sty, qy);
                     const float dz = e.z + fmaf(kz, stz, qz);
                     l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    hit = l2 < c2thr && (int64_t)j != i;
+                    hit = l2 < c2 && (int64_t)j != i;
                 }
                 if (MODE == 0) {
                     cnt += hit ? 1u : 0u;
@@ -330,16 +332,16 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
 }
 
 hipError_t launch_cl_cutoff_sweep(int mode, int B, const StructInfo* info, const ClWs& w,
-                                  const float* frac, float c2thr, uint32_t* counts,
+                                  const float* frac, float c2thr, const float* thr, uint32_t* counts,
                                   const int64_t* offsets, int64_t capacity, int32_t* src,
                                   int32_t* dst, int32_t* image, float* length, Counters* ctr,
                                   mg_report* report, int64_t* partials, int grid, hipStream_t s) {
     if (B == 0) return hipSuccess;
     if (mode == 0)
-        hipLaunchKernelGGL((k_cl_sweep<0>), dim3(grid), dim3(256), 0, s, B, info, w, frac, c2thr, counts, offsets,
+        hipLaunchKernelGGL((k_cl_sweep<0>), dim3(grid), dim3(256), 0, s, B, info, w, frac, c2thr, thr, counts, offsets,
                            capacity, src, dst, image, length, ctr, report, partials);
     else
-        hipLaunchKernelGGL((k_cl_sweep<1>), dim3(grid), dim3(256), 0, s, B, info, w, frac, c2thr, counts, offsets,
+        hipLaunchKernelGGL((k_cl_sweep<1>), dim3(grid), dim3(256), 0, s, B, info, w, frac, c2thr, thr, counts, offsets,
                            capacity, src, dst, image, length, ctr, report, partials);
     return hipGetLastError();
 }

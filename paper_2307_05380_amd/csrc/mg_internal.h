@@ -162,9 +162,12 @@ __device__ inline int structure_of(const int64_t* __restrict__ ptr, int B, int64
 // Each returns hipSuccess or the launch error. All are asynchronous on `stream`.
 namespace mg {
 
+// radii (nullable, cutoff mode only): per-atom cutoffs; then thr[a] receives
+// the per-atom threshold on l^2 and the structure's radius is its largest c_a.
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
-                         int64_t N, float radius, int knn_k, float knn_lambda, StructInfo* info,
-                         Counters* ctr, mg_report* report, int mode, int opts, hipStream_t s);
+                         int64_t N, float radius, const float* radii, float* thr, int knn_k,
+                         float knn_lambda, StructInfo* info, Counters* ctr, mg_report* report, int mode,
+                         int opts, hipStream_t s);
 hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, int64_t* cl_off,
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
                               hipStream_t s);
@@ -185,7 +188,7 @@ struct ClWs {
 hipError_t launch_cl_build(int B, int64_t N, const float* frac, const int64_t* batch_ptr,
                            const StructInfo* info, const ClWs& w, hipStream_t s);
 hipError_t launch_cl_cutoff_sweep(int mode, int B, const StructInfo* info, const ClWs& w,
-                                  const float* frac, float c2thr, uint32_t* counts,
+                                  const float* frac, float c2thr, const float* thr, uint32_t* counts,
                                   const int64_t* offsets, int64_t capacity, int32_t* src,
                                   int32_t* dst, int32_t* image, float* length, Counters* ctr,
                                   mg_report* report, int64_t* partials, int grid, hipStream_t s);
@@ -197,7 +200,7 @@ hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const 
                          ImageEntry* table, int64_t image_capacity, hipStream_t s);
 hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
                                const ImageEntry* table, const float* frac, float c2thr,
-                               uint32_t* counts, const int64_t* offsets, int64_t capacity,
+                               const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
                                int32_t* src, int32_t* dst, int32_t* image, float* length,
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
                                hipStream_t s);
@@ -232,6 +235,9 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
                                const int32_t* dst, const int32_t* image, int64_t E,
                                const int64_t* num_edges, const float* grad_vec, const float* grad_length,
                                float* grad_frac, float* grad_lattice, const GeomBwdWs& w, hipStream_t s);
+hipError_t launch_triplets(const int64_t* row_ptr, int64_t N, int64_t E, const float* vec, int64_t capacity,
+                           int32_t* e1, int32_t* e2, float* cosv, int64_t* offsets, uint32_t* counts,
+                           int64_t* bsum, mg_report* report, hipStream_t s);
 // Per-wave partial counts (candidates evaluated) are written to a workspace
 // array and summed by one block afterwards: no shared-counter atomics in the
 // sweeps. The array holds MAX_GRID_WAVES entries.

@@ -83,7 +83,7 @@ template <int MODE, int SLOTS>
 __global__ __launch_bounds__(256) void k_cutoff_sweep(
     int B, const StructInfo* __restrict__ info, const int64_t* __restrict__ item_off,
     const ImageEntry* __restrict__ table, const float* __restrict__ frac, float c2thr,
-    uint32_t* __restrict__ counts, const int64_t* __restrict__ offsets, int64_t capacity,
+    const float* __restrict__ thr, uint32_t* __restrict__ counts, const int64_t* __restrict__ offsets, int64_t capacity,
     int32_t* __restrict__ src, int32_t* __restrict__ dst, int32_t* __restrict__ image,
     float* __restrict__ length, Counters* __restrict__ ctr, mg_report* __restrict__ rep,
     int64_t* __restrict__ partials) {
@@ -123,6 +123,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
             const bool act = a < nsrc;
             const int il = i_first + a;
             const Pair P = make_pair(frac, L, atom0, il, j, act);
+            const float c2 = (thr && act) ? thr[atom0 + il] : c2thr;   // the source's cutoff
             uint32_t cnt = 0;
             uint32_t run = 0;
             int64_t base = 0;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
             }
             auto step = [&](const ImageEntry& e, bool zero) {
                 const float l2 = dist2(P, e);
-                bool hit = l2 < c2thr;
+                bool hit = l2 < c2;
                 if (zero) hit = hit && !P.self;
                 if (MODE == MODE_COUNT) {
                     cnt += hit ? 1u : 0u;
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
         } else {
             // ---- one source per item, SLOTS destinations per lane, chunks of 64*SLOTS
             const int il = i_first;
+            const float c2 = thr ? thr[atom0 + il] : c2thr;
             uint32_t cnt = 0;
             uint32_t run = 0;
             const int64_t base = (MODE == MODE_FILL) ? offsets[atom0 + il] : 0;
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
 #pragma unroll
                     for (int r = 0; r < SLOTS; ++r) {
                         const float l2 = dist2(P[r], e);
-                        bool hit = l2 < c2thr;
+                        bool hit = l2 < c2;
                         if (zero) hit = hit && !P[r].self;
                         if (MODE == MODE_COUNT) {
                             cnt += hit ? 1u : 0u;
@@ -206,14 +208,15 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
 
 hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
                                const ImageEntry* table, const float* frac, float c2thr,
-                               uint32_t* counts, const int64_t* offsets, int64_t capacity,
+                               const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
                                int32_t* src, int32_t* dst, int32_t* image, float* length,
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
                                hipStream_t s) {
     if (B == 0) return hipSuccess;
 #define MG_SWEEP(M, S)                                                                              \
     hipLaunchKernelGGL((k_cutoff_sweep<M, S>), dim3(grid), dim3(256), 0, s, B, info, item_off, table, \
-                       frac, c2thr, counts, offsets, capacity, src, dst, image, length, ctr, report, partials)
+                       frac, c2thr, thr, counts, offsets, capacity, src, dst, image, length, ctr, report, \
+                       partials)
     if (mode == MODE_COUNT) {
         if (slots <= 1) MG_SWEEP(MODE_COUNT, 1);
         else if (slots == 2) MG_SWEEP(MODE_COUNT, 2);

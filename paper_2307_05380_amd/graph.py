@@ -20,7 +20,7 @@ import torch
 from . import _lib
 
 __all__ = ["Graph", "Report", "cutoff_graph", "knn_graph", "edge_geometry", "EdgeGeometry",
-           "CutoffBuilder", "KnnBuilder", "GeometryRunner", "auto_opts"]
+           "CutoffBuilder", "KnnBuilder", "GeometryRunner", "auto_opts", "Triplets", "triplets"]
 
 
 @dataclasses.dataclass
@@ -101,6 +101,12 @@ def _strict_check(rep: Report):
         raise _lib.MatgraphError(-1, "structures skipped: " + ",".join(rep.flag_names()))
 
 
+def _radii(r: torch.Tensor, N: int) -> torch.Tensor:
+    if not r.is_cuda or r.dtype != torch.float32 or r.shape != (N,):
+        raise ValueError(f"per-atom cutoffs must be a float32 device tensor of shape [{N}]")
+    return r.contiguous()
+
+
 class CutoffBuilder:
     """Preallocated cutoff-graph call: fixed batch shape, edge capacity and
     image-table capacity. ``run`` only enqueues kernels (no host sync), so it can
@@ -124,7 +130,16 @@ class CutoffBuilder:
         nbytes = self.lib.mg_cutoff_workspace_bytes(self.B, self.N, self.image_capacity)
         self.workspace = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=d)
 
-    def run(self, lattices, frac, batch_ptr, cutoff: float, opts: int = 0):
+    def run(self, lattices, frac, batch_ptr, cutoff, opts: int = 0):
+        """``cutoff``: one distance (float) or per-atom cutoffs (float32 device tensor [N])."""
+        if isinstance(cutoff, torch.Tensor):
+            radii = _radii(cutoff, self.N)
+            _lib.check(self.lib.mg_cutoff_graph_radii(
+                _ptr(lattices), _ptr(frac), _ptr(batch_ptr), self.B, self.N, _ptr(radii),
+                self.capacity, _ptr(self.src), _ptr(self.dst), _ptr(self.image), _ptr(self.length),
+                _ptr(self.row_ptr), _ptr(self.rep), _ptr(self.workspace), self.workspace.numel(),
+                int(opts), _stream(self.device)), self.lib)
+            return
         _lib.check(self.lib.mg_cutoff_graph(
             _ptr(lattices), _ptr(frac), _ptr(batch_ptr), self.B, self.N, float(cutoff),
             self.capacity, _ptr(self.src), _ptr(self.dst), _ptr(self.image), _ptr(self.length),
@@ -140,10 +155,12 @@ class CutoffBuilder:
         return Graph(self.src[:E], self.dst[:E], self.image[:E], self.length[:E], self.row_ptr, rep)
 
 
-def cutoff_graph(lattices, frac, batch_ptr, cutoff: float, capacity: int | None = None,
+def cutoff_graph(lattices, frac, batch_ptr, cutoff, capacity: int | None = None,
                  image_capacity: int | None = None, strict: bool = False,
                  opts: int | None = None) -> Graph:
-    """Periodic cutoff multigraph (Definition def6, constant cutoff, strict <).
+    """Periodic cutoff multigraph (Definition def6, strict <). ``cutoff`` is one
+    distance, or a float32 device tensor [N] of per-atom cutoffs c_i (an edge
+    uses its source's cutoff).
 
     Allocates outputs, runs the library and, when the edge or image-table
     capacity was too small, reruns once with the exact sizes the device
@@ -293,3 +310,48 @@ class EdgeGeometry(torch.autograd.Function):
 def edge_geometry(lattices, frac, batch_ptr, src, dst, image):
     """Differentiable (vec, length) of the given edges (see ``EdgeGeometry``)."""
     return EdgeGeometry.apply(lattices, frac, batch_ptr, src, dst, image)
+
+
+@dataclasses.dataclass
+class Triplets:
+    e1: torch.Tensor           # int32 [T] first edge of each pair
+    e2: torch.Tensor           # int32 [T] second edge (same source, e2 != e1)
+    cos_theta: torch.Tensor | None
+    trip_ptr: torch.Tensor     # int64 [N+1]
+    report: Report
+
+
+def triplets(row_ptr: torch.Tensor, num_edges: int, vec: torch.Tensor | None = None,
+             capacity: int | None = None) -> Triplets:
+    """Ordered pairs of different edges sharing a source (Definition def6,
+    Gamma_2) for a graph grouped by source (``row_ptr`` int64 [N+1] on the
+    device), with the angle between the edge vectors when ``vec`` [E,3] is
+    given. Reruns once with the exact size when ``capacity`` was too small."""
+    if not row_ptr.is_cuda or row_ptr.dtype != torch.int64 or row_ptr.dim() != 1:
+        raise ValueError("row_ptr must be an int64 device tensor [N+1]")
+    lib = _lib.load()
+    d = row_ptr.device
+    N = int(row_ptr.shape[0]) - 1
+    E = int(num_edges)
+    if vec is not None:
+        if vec.dtype != torch.float32 or vec.shape != (E, 3) or not vec.is_cuda:
+            raise ValueError(f"vec must be a float32 device tensor [{E}, 3]")
+        vec = vec.contiguous()
+    row_ptr = row_ptr.contiguous()
+    cap = int(capacity) if capacity is not None else max(1024, 16 * E)
+    ws = torch.empty(max(int(lib.mg_triplets_workspace_bytes(N)), 256), dtype=torch.uint8, device=d)
+    rep_t = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=d)
+    trip_ptr = torch.empty(N + 1, dtype=torch.int64, device=d)
+    for _ in range(2):
+        e1 = torch.empty(cap, dtype=torch.int32, device=d)
+        e2 = torch.empty(cap, dtype=torch.int32, device=d)
+        cs = torch.empty(cap, dtype=torch.float32, device=d) if vec is not None else None
+        _lib.check(lib.mg_triplets(_ptr(row_ptr), N, E, _ptr(vec), cap, _ptr(e1), _ptr(e2), _ptr(cs),
+                                   _ptr(trip_ptr), _ptr(rep_t), _ptr(ws), ws.numel(), _stream(d)), lib)
+        rep = Report.from_tensor(rep_t)
+        if rep.flags & _lib.MG_FLAG_CAPACITY:
+            cap = int(rep.num_edges)
+            continue
+        break
+    T = min(rep.num_edges, cap)
+    return Triplets(e1[:T], e2[:T], cs[:T] if cs is not None else None, trip_ptr, rep)

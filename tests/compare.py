@@ -29,15 +29,24 @@ def _void(a):
     return a.view(np.dtype((np.void, a.dtype.itemsize * a.shape[1]))).ravel()
 
 
+def _cut_of(radii, cutoff, src):
+    """The cutoff of every edge: its source's radius, or the constant."""
+    if radii is None:
+        return np.full(len(src), float(cutoff))
+    return np.asarray(radii, np.float64)[np.asarray(src, np.int64)]
+
+
 def cutoff_check(batch, g_src, g_dst, g_img, g_len, structures=None, band=BAND, len_tol=LEN_TOL,
-                 processes=None):
+                 processes=None, radii=None):
     """Compare GPU cutoff edges (numpy, global indices) with the oracle on the
-    given structures. Returns a stats dict; raises AssertionError on mismatch."""
+    given structures (``radii``: optional per-atom cutoffs [N], float32 values
+    as given to the GPU). Returns a stats dict; raises AssertionError on mismatch."""
     ptr = batch.batch_ptr
     if structures is None:
         structures = list(range(batch.B))
     structures = [int(s) for s in structures]
-    og = oracle.cutoff_graph64(batch.lattices, batch.frac, ptr, batch.cutoff, band=band,
+    cut = batch.cutoff if radii is None else np.asarray(radii, np.float32).astype(np.float64)
+    og = oracle.cutoff_graph64(batch.lattices, batch.frac, ptr, cut, band=band,
                                structures=structures, processes=processes)
     # GPU edges of the selected structures
     s_of_src = np.searchsorted(ptr, g_src, side="right") - 1
@@ -48,7 +57,8 @@ def cutoff_check(batch, g_src, g_dst, g_img, g_len, structures=None, band=BAND, 
     OL = og.length
     gv, ov = _void(G), _void(O)
     assert np.unique(gv).shape[0] == gv.shape[0], "duplicate GPU edges"
-    c = batch.cutoff
+    c = _cut_of(radii, batch.cutoff, og.src)
+    cg = _cut_of(None if radii is None else np.asarray(radii, np.float32), batch.cutoff, G[:, 0])
     must = OL < c - band
     near = np.abs(OL - c) <= band
     in_o = np.isin(gv, ov)
@@ -60,8 +70,8 @@ def cutoff_check(batch, g_src, g_dst, g_img, g_len, structures=None, band=BAND, 
     pos = order_o[np.searchsorted(ov[order_o], gv)]
     err = np.abs(GL - OL[pos])
     assert err.max(initial=0.0) <= len_tol, f"length error {err.max():.3g} > {len_tol}"
-    # the strict cutoff holds in the GPU's own precision
-    assert (GL < c).all()
+    # the strict cutoff holds in the GPU's own precision (FP32 length vs FP32 cutoff)
+    assert (np.asarray(g_len)[sel] < cg.astype(np.float32)).all()
     return {"edges": int(G.shape[0]), "oracle_inside": int(must.sum()), "near": int(near.sum()),
             "near_on_gpu": int(np.isin(ov[near], gv).sum()), "max_len_err": float(err.max(initial=0.0))}
 
@@ -111,11 +121,14 @@ def knn_check(batch, k, g_src, g_dst, g_img, g_len, sources=None, band=BAND, len
             "max_len_err": float(np.abs(l64 - g_len[atoms]).max(initial=0.0))}
 
 
-def cutoff_sources_check(batch, s, sources, g_src, g_dst, g_img, g_len, band=BAND, len_tol=LEN_TOL):
+def cutoff_sources_check(batch, s, sources, g_src, g_dst, g_img, g_len, band=BAND, len_tol=LEN_TOL,
+                         radii=None):
     """cutoff_check restricted to some sources (local indices) of structure s."""
     a0 = int(batch.batch_ptr[s])
     L, x = batch.structure(s)
-    os_, od, oi, ol = oracle.cutoff_sources64(L, x, batch.cutoff, sources, band=band)
+    a1 = int(batch.batch_ptr[s + 1])
+    cut = batch.cutoff if radii is None else np.asarray(radii, np.float32)[a0:a1].astype(np.float64)
+    os_, od, oi, ol = oracle.cutoff_sources64(L, x, cut, sources, band=band)
     glob = a0 + np.asarray(sources, np.int64)
     sel = np.isin(g_src, glob)
     G = _rows(g_src[sel], g_dst[sel], g_img[sel])
@@ -123,7 +136,7 @@ def cutoff_sources_check(batch, s, sources, g_src, g_dst, g_img, g_len, band=BAN
     O = _rows(os_ + a0, od + a0, oi)
     gv, ov = _void(G), _void(O)
     assert np.unique(gv).shape[0] == gv.shape[0], "duplicate GPU edges"
-    c = batch.cutoff
+    c = _cut_of(None if radii is None else np.asarray(radii, np.float64)[a0:a1], batch.cutoff, os_)
     must = ol < c - band
     in_o = np.isin(gv, ov)
     assert in_o.all(), f"{int((~in_o).sum())} GPU edges are not edges of the oracle (first: {G[~in_o][:3]})"
