@@ -17,11 +17,12 @@ Conventions (also documented in the C header of the library):
 - the self-image (i, i, 0) is not an edge; (i, i, t != 0) is.
 
 Parity status of every function is listed in ``oracle/graph64.py``,
-``oracle/geometry64.py`` and ``oracle/triplets64.py``; all are pinned by CPU tests (closed forms,
+``oracle/geometry64.py``, ``oracle/triplets64.py`` and ``oracle/symmetrize64.py``; all are pinned by CPU tests (closed forms,
 invariants, brute force, finite differences).
 """
 from .graph64 import (Graph64, KnnResult64, cutoff_graph64, cutoff_sources64, cutoff_structure64,
                       image_ranges64, knn_graph64, knn_structure64)
+from .symmetrize64 import symmetrize64
 from .triplets64 import triplet_cos64, triplets64
 from .geometry64 import (edge_geometry64, edge_geometry_vjp64, fd_vjp64, gaussian_loss64,
                          gaussian_loss_grad_len64)
@@ -30,4 +31,5 @@ __all__ = [
     "Graph64", "KnnResult64", "cutoff_graph64", "cutoff_sources64", "cutoff_structure64", "image_ranges64",
     "knn_graph64", "knn_structure64", "edge_geometry64", "edge_geometry_vjp64", "fd_vjp64",
     "gaussian_loss64", "gaussian_loss_grad_len64", "triplets64", "triplet_cos64",
+    "symmetrize64",
 ]

@@ -395,8 +395,51 @@ def pin_triplets_brute_force(O, seed=9):
     assert len(e1) == int((deg * (deg - 1)).sum())
 
 
+# ------------------------------------------------------------- symmetrisation
+
+
+def pin_symmetrize_chain(O):
+    """Atoms at x = 0, 1, 3 (Angstrom) on a line in a 100 A cubic cell, k = 1:
+    0 -> 1, 1 -> 0, 2 -> 1. The closure adds 1 -> 2 only, after 1's own edge."""
+    L = 100.0 * np.eye(3)
+    x = np.array([[0.0, 0, 0], [0.01, 0, 0], [0.03, 0, 0]])
+    src, dst, img, ln, dk, near, inside = O.knn_structure64(L, x, 1)
+    assert dst.tolist() == [1, 0, 1]
+    ptr = np.arange(4, dtype=np.int64)
+    sp, ss, sd, si, sl = O.symmetrize64(ptr, dst, img, ln)
+    assert sp.tolist() == [0, 1, 3, 4]
+    assert ss.tolist() == [0, 1, 1, 2] and sd.tolist() == [1, 0, 2, 1]
+    assert np.allclose(sl, [1.0, 1.0, 2.0, 2.0])
+
+
+def pin_symmetrize_properties(O, seed=10):
+    """KNN graph of a random cell (k = 5, self images allowed): the closure is
+    symmetric, equals E union reverse(E) as a set, keeps every source's own
+    edges first and in order, and adds nothing when applied again; a cutoff
+    graph (already symmetric) is returned unchanged."""
+    rng = np.random.default_rng(seed)
+    L, x = _random_structure(rng, 7)
+    src, dst, img, ln, dk, near, inside = O.knn_structure64(L, x, 5)
+    ptr = np.arange(0, 7 * 5 + 1, 5, dtype=np.int64)
+    sp, ss, sd, si, sl = O.symmetrize64(ptr, dst, img, ln)
+    S = _edges_set(ss, sd, si)
+    E = _edges_set(src, dst, img)
+    R = {(b, a, -t0, -t1, -t2) for a, b, t0, t1, t2 in E}
+    assert S == E | R and len(S) == len(ss)
+    assert all((b, a, -t0, -t1, -t2) in S for a, b, t0, t1, t2 in S)
+    for i in range(7):
+        assert np.array_equal(sd[sp[i]:sp[i] + 5], dst[5 * i:5 * i + 5])
+    assert np.allclose(O.edge_geometry64(L[None], x, np.array([0, 7]), ss, sd, si)[1], sl, atol=1e-12)
+    sp2, ss2, sd2, si2, _ = O.symmetrize64(sp, sd, si)
+    assert np.array_equal(sp2, sp) and np.array_equal(sd2, sd) and np.array_equal(si2, si)
+    cs, cd, ct, cl = O.cutoff_structure64(L, x, 4.0)
+    cptr = np.concatenate([[0], np.cumsum(np.bincount(cs, minlength=7))])
+    qp, qs, qd, qi, _ = O.symmetrize64(cptr, cd, ct)
+    assert np.array_equal(qp, cptr) and np.array_equal(qd, cd) and np.array_equal(qi, ct)
+
+
 ALL_PINS = [pin_cubic_shells, pin_sc_sum_of_three_squares, pin_strict_cutoff, pin_row_convention,
             pin_figure1, pin_knn_tie_break, pin_knn_single_atom_and_cluster, pin_symmetry,
             pin_supercell, pin_unimodular, pin_translation, pin_enormous_range, pin_knn_vs_cutoff,
             pin_gradients, pin_radii_closed_form, pin_radii_restriction, pin_triplets_closed_form,
-            pin_triplets_brute_force]
+            pin_triplets_brute_force, pin_symmetrize_chain, pin_symmetrize_properties]

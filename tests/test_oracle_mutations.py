@@ -36,6 +36,9 @@ MUTATIONS = [
     ("graph64", "order = np.lexsort((t[:, 2], t[:, 1], t[:, 0], j, ln))",
      "order = np.lexsort((t[:, 2], t[:, 1], t[:, 0], ln, j))", "KNN ordered by dst before length"),
     ("graph64", "sel = order[:k]", "sel = order[1:k + 1]", "KNN off-by-one selection"),
+    ("symmetrize64", "out_img.append(-img[e])", "out_img.append(img[e])", "reverse edge keeps +t"),
+    ("symmetrize64", "if (j, i, -int(t[0]), -int(t[1]), -int(t[2])) not in present:",
+     "if (j, i, int(t[0]), int(t[1]), int(t[2])) not in present:", "presence test on (j, i, +t)"),
     ("triplets64", "keep = a != b", "keep = a >= 0", "triplets include the pair (g, g)"),
     ("triplets64", "b = np.tile(idx, d)", "b = np.repeat(idx, d)", "second edge of the pair not varied"),
     ("triplets64", "den = np.sqrt((a * a).sum(1)) * np.sqrt((b * b).sum(1))", "den = (a * a).sum(1)",
