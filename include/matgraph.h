@@ -110,6 +110,9 @@ size_t mg_geometry_workspace_bytes(int32_t B, int64_t N);
 /* Workspace bytes for mg_triplets on a graph of N source atoms (0 if N < 0). */
 size_t mg_triplets_workspace_bytes(int64_t N);
 
+/* Workspace bytes for mg_symmetrize on N atoms and E input edges (0 if negative). */
+size_t mg_symmetrize_workspace_bytes(int64_t N, int64_t E);
+
 /*
  * Periodic cutoff multigraph (Definition def6 with a constant cutoff c_i = cutoff).
  *
@@ -197,6 +200,36 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac,
                                     const float* grad_vec, const float* grad_length,
                                     float* grad_frac, float* grad_lattice,
                                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Symmetric closure (Sec. 2.2, symmetric-graph procedure): the input edges plus,
+ * for every edge (i, j, t) whose reverse (j, i, -t) is not an input edge, the
+ * edge (j, i, -t) with the same length. Input edges must be unique; no edge is
+ * added twice.
+ *
+ *  row_ptr       int64 [N+1] device: input edges of source i are row_ptr[i] ..
+ *                row_ptr[i+1]-1 (i*k for a KNN graph). A range outside [0, E] is
+ *                clamped and sets MG_FLAG_RANGE.
+ *  dst, image    int32 [E], int32 [E][3]: the input edges (global atom indices).
+ *                An edge with dst outside [0, N) is kept, not reversed, and sets
+ *                MG_FLAG_RANGE.
+ *  length        float32 [E] or NULL (needed only for out_length).
+ *  capacity      slots in the outputs (>= 0).
+ *  out_*         src/dst int32 [capacity], image int32 [capacity][3], length float32
+ *                [capacity] or NULL. Order: by source; each source's input edges in
+ *                input order, then the reverse edges it receives, ordered by the
+ *                index of the input edge they reverse.
+ *  out_row_ptr   int64 [N+1] or NULL.
+ *  report        mg_report: num_edges = edges of the closure (exact even past
+ *                capacity; MG_FLAG_CAPACITY then, nothing written past capacity).
+ * Cost: each edge scans its destination's out-list, so the call suits modest
+ * degrees (KNN graphs); cutoff graphs are already symmetric.
+ * Errors: MG_ERR_INVALID_ARG (sizes, NULL pointers), MG_ERR_WORKSPACE.
+ */
+mg_status mg_symmetrize(const int64_t* row_ptr, int64_t N, const int32_t* dst, const int32_t* image,
+                        const float* length, int64_t E, int64_t capacity, int32_t* out_src, int32_t* out_dst,
+                        int32_t* out_image, float* out_length, int64_t* out_row_ptr, mg_report* report,
+                        void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Triplets (Definition def6, Gamma_2): every ordered pair (e1, e2) of two

@@ -68,6 +68,8 @@ SIGNATURES = {
     "mg_edge_geometry_backward": (_I32, [_P, _P, _P, _I32, _I64, _P, _P, _P, _I64, _P, _P, _P, _P,
                                          _P, _P, _SZ, _P]),
     "mg_triplets_workspace_bytes": (_SZ, [_I64]),
+    "mg_symmetrize_workspace_bytes": (_SZ, [_I64, _I64]),
+    "mg_symmetrize": (_I32, [_P, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "mg_triplets": (_I32, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "mg_get_tuning": (_I32, [ctypes.POINTER(MgTuning)]),
     "mg_set_tuning": (_I32, [ctypes.POINTER(MgTuning)]),

@@ -224,6 +224,27 @@ TripWs carve_triplets(void* ws, int64_t N) {
     return w;
 }
 
+struct SymWsHost {
+    mg::SymWs w;
+    int64_t* out_off;
+    size_t fixed;
+};
+
+SymWsHost carve_symmetrize(void* ws, int64_t N, int64_t E) {
+    Carver c{static_cast<char*>(ws)};
+    SymWsHost h;
+    h.w.addcnt = c.take<uint32_t>((size_t)N);
+    h.w.cursor = c.take<uint32_t>((size_t)N);
+    h.w.total = c.take<uint32_t>((size_t)N);
+    h.w.aoff = c.take<int64_t>((size_t)N + 1);
+    h.w.bsum = c.take<int64_t>((size_t)mg::scan_block_count(N) + 1);
+    h.out_off = c.take<int64_t>((size_t)N + 1);
+    h.w.bucket = c.take<uint64_t>((size_t)E);
+    h.w.miss = c.take<uint8_t>((size_t)E);
+    h.fixed = mg::align_up(c.used, 256);
+    return h;
+}
+
 // Smallest float y with sqrtf(y) >= c, so that l2 < y  <=>  sqrtf(l2) < c.
 float cutoff_threshold(float c) {
     float y = c * c;
@@ -270,6 +291,11 @@ size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_cap
     if (B < 0 || N < 0 || image_capacity < 0 || k < 1 || k > 64) return 0;
     KnnWs w = carve_knn(nullptr, 0, B, N);
     return w.fixed + (size_t)image_capacity * sizeof(mg::ImageEntry);
+}
+
+size_t mg_symmetrize_workspace_bytes(int64_t N, int64_t E) {
+    if (N < 0 || E < 0) return 0;
+    return carve_symmetrize(nullptr, N, E).fixed;
 }
 
 size_t mg_triplets_workspace_bytes(int64_t N) {
@@ -518,6 +544,36 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac, co
                                             num_edges, grad_vec, grad_length, grad_frac, grad_lattice, w.bwd, s);
          })) != hipSuccess)
         return hip_fail(e, "geometry backward");
+    return MG_OK;
+}
+
+mg_status mg_symmetrize(const int64_t* row_ptr, int64_t N, const int32_t* dst, const int32_t* image,
+                        const float* length, int64_t E, int64_t capacity, int32_t* out_src, int32_t* out_dst,
+                        int32_t* out_image, float* out_length, int64_t* out_row_ptr, mg_report* report,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    g_err.clear();
+    if (N < 0 || N > (int64_t)INT32_MAX) return fail(MG_ERR_INVALID_ARG, "N must be in [0, 2^31)");
+    if (E < 0 || E > (int64_t)INT32_MAX) return fail(MG_ERR_INVALID_ARG, "E must be in [0, 2^31)");
+    if (!row_ptr) return fail(MG_ERR_INVALID_ARG, "row_ptr is NULL");
+    if (E > 0 && (!dst || !image)) return fail(MG_ERR_INVALID_ARG, "dst/image must be non-NULL when E > 0");
+    if (out_length && E > 0 && !length) return fail(MG_ERR_INVALID_ARG, "out_length needs the input lengths");
+    if (capacity < 0) return fail(MG_ERR_INVALID_ARG, "capacity must be >= 0");
+    if (capacity > 0 && (!out_src || !out_dst || !out_image))
+        return fail(MG_ERR_INVALID_ARG, "out_src/out_dst/out_image must be non-NULL when capacity > 0");
+    if (!report) return fail(MG_ERR_INVALID_ARG, "report is NULL");
+    if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    SymWsHost h = carve_symmetrize(workspace, N, E);
+    if (workspace_bytes < h.fixed)
+        return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    workspace_bytes, h.fixed);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = mg::launch_zero_report(report, nullptr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
+    if ((e = phase("symmetrize", s, [&] {
+             return mg::launch_symmetrize(row_ptr, N, E, dst, image, length, capacity, out_src, out_dst, out_image,
+                                          out_length, out_row_ptr ? out_row_ptr : h.out_off, h.w, report, s);
+         })) != hipSuccess)
+        return hip_fail(e, "symmetrize");
     return MG_OK;
 }
 

@@ -235,6 +235,21 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
                                const int32_t* dst, const int32_t* image, int64_t E,
                                const int64_t* num_edges, const float* grad_vec, const float* grad_length,
                                float* grad_frac, float* grad_lattice, const GeomBwdWs& w, hipStream_t s);
+// Workspace of the symmetric closure: per-atom received counts, cursors and
+// totals (N), received offsets (N + 1), scan partials, per-edge flags (E) and
+// the received-edge buckets (E).
+struct SymWs {
+    uint32_t* addcnt;
+    uint32_t* cursor;
+    uint32_t* total;
+    int64_t* aoff;
+    int64_t* bsum;
+    uint8_t* miss;
+    uint64_t* bucket;
+};
+hipError_t launch_symmetrize(const int64_t* row_ptr, int64_t N, int64_t E, const int32_t* dst, const int32_t* image,
+                             const float* length, int64_t capacity, int32_t* osrc, int32_t* odst, int32_t* oimg,
+                             float* olen, int64_t* out_off, const SymWs& w, mg_report* report, hipStream_t s);
 hipError_t launch_triplets(const int64_t* row_ptr, int64_t N, int64_t E, const float* vec, int64_t capacity,
                            int32_t* e1, int32_t* e2, float* cosv, int64_t* offsets, uint32_t* counts,
                            int64_t* bsum, mg_report* report, hipStream_t s);

@@ -20,7 +20,7 @@ import torch
 from . import _lib
 
 __all__ = ["Graph", "Report", "cutoff_graph", "knn_graph", "edge_geometry", "EdgeGeometry",
-           "CutoffBuilder", "KnnBuilder", "GeometryRunner", "auto_opts", "Triplets", "triplets"]
+           "CutoffBuilder", "KnnBuilder", "GeometryRunner", "auto_opts", "Triplets", "triplets", "symmetrize"]
 
 
 @dataclasses.dataclass
@@ -355,3 +355,45 @@ def triplets(row_ptr: torch.Tensor, num_edges: int, vec: torch.Tensor | None = N
         break
     T = min(rep.num_edges, cap)
     return Triplets(e1[:T], e2[:T], cs[:T] if cs is not None else None, trip_ptr, rep)
+
+
+def symmetrize(row_ptr: torch.Tensor, dst: torch.Tensor, image: torch.Tensor,
+               length: torch.Tensor | None = None, capacity: int | None = None) -> Graph:
+    """Symmetric closure of a graph grouped by source (``row_ptr`` int64 [N+1],
+    ``dst`` int32 [E], ``image`` int32 [E,3], optional ``length`` [E]): adds
+    every missing reverse edge (j, i, -t) once, with the same length. For a
+    KNN graph pass ``row_ptr = arange(0, N*k + 1, k)``."""
+    if not row_ptr.is_cuda or row_ptr.dtype != torch.int64 or row_ptr.dim() != 1:
+        raise ValueError("row_ptr must be an int64 device tensor [N+1]")
+    E = int(dst.shape[0])
+    for t, nm in ((dst, "dst"), (image, "image")):
+        if not t.is_cuda or t.dtype != torch.int32:
+            raise ValueError(f"{nm} must be an int32 device tensor")
+    if image.shape != (E, 3):
+        raise ValueError("image must be [E, 3]")
+    if length is not None and (length.dtype != torch.float32 or length.shape != (E,)):
+        raise ValueError("length must be float32 [E]")
+    lib = _lib.load()
+    d = row_ptr.device
+    N = int(row_ptr.shape[0]) - 1
+    row_ptr, dst, image = row_ptr.contiguous(), dst.contiguous(), image.contiguous()
+    length = length.contiguous() if length is not None else None
+    cap = int(capacity) if capacity is not None else 2 * E
+    ws = torch.empty(max(int(lib.mg_symmetrize_workspace_bytes(N, E)), 256), dtype=torch.uint8, device=d)
+    rep_t = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=d)
+    out_ptr = torch.empty(N + 1, dtype=torch.int64, device=d)
+    for _ in range(2):
+        s_ = torch.empty(cap, dtype=torch.int32, device=d)
+        d_ = torch.empty(cap, dtype=torch.int32, device=d)
+        i_ = torch.empty((cap, 3), dtype=torch.int32, device=d)
+        l_ = torch.empty(cap, dtype=torch.float32, device=d) if length is not None else None
+        _lib.check(lib.mg_symmetrize(_ptr(row_ptr), N, _ptr(dst), _ptr(image), _ptr(length), E, cap, _ptr(s_),
+                                     _ptr(d_), _ptr(i_), _ptr(l_), _ptr(out_ptr), _ptr(rep_t), _ptr(ws),
+                                     ws.numel(), _stream(d)), lib)
+        rep = Report.from_tensor(rep_t)
+        if rep.flags & _lib.MG_FLAG_CAPACITY:
+            cap = int(rep.num_edges)
+            continue
+        break
+    S = min(rep.num_edges, cap)
+    return Graph(s_[:S], d_[:S], i_[:S], l_[:S] if l_ is not None else None, out_ptr, rep)
