@@ -21,7 +21,7 @@ Parity status of every function is listed in ``oracle/graph64.py``,
 invariants, brute force, finite differences).
 """
 from .graph64 import (Graph64, KnnResult64, cutoff_graph64, cutoff_sources64, cutoff_structure64,
-                      image_ranges64, knn_graph64, knn_structure64)
+                      image_ranges64, knn_graph64, knn_structure64, knn_ties_structure64)
 from .symmetrize64 import symmetrize64
 from .triplets64 import triplet_cos64, triplets64
 from .geometry64 import (edge_geometry64, edge_geometry_vjp64, fd_vjp64, gaussian_loss64,
@@ -29,7 +29,7 @@ from .geometry64 import (edge_geometry64, edge_geometry_vjp64, fd_vjp64, gaussia
 
 __all__ = [
     "Graph64", "KnnResult64", "cutoff_graph64", "cutoff_sources64", "cutoff_structure64", "image_ranges64",
-    "knn_graph64", "knn_structure64", "edge_geometry64", "edge_geometry_vjp64", "fd_vjp64",
+    "knn_graph64", "knn_structure64", "knn_ties_structure64", "edge_geometry64", "edge_geometry_vjp64", "fd_vjp64",
     "gaussian_loss64", "gaussian_loss_grad_len64", "triplets64", "triplet_cos64",
     "symmetrize64",
 ]

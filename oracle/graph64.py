@@ -199,6 +199,37 @@ def knn_structure64(L, x, k: int, band: float = 0.0, sources=None):
     return src, dst, img, length, dk, near, inside
 
 
+def knn_ties_structure64(L, x, k: int, sources=None):
+    """Algorithm 2's selection with ties kept: every (j, t) of a source whose
+    length is <= the source's k-th distance d_k (Sec. 2.2), so a source can get
+    more than k edges when several candidates share the k-th distance.
+
+    Returns (src, dst, image, length, row_ptr) with local indices, each source's
+    edges in key order (length, dst, t0, t1, t2).
+    """
+    L = np.asarray(L, np.float64)
+    x = np.asarray(x, np.float64)
+    srcs = list(range(x.shape[0])) if sources is None else [int(i) for i in sources]
+    _, _, _, _, dk, _, _ = knn_structure64(L, x, k, sources=srcs)
+    out = [[], [], [], []]
+    ptr = [0]
+    for r, i in enumerate(srcs):
+        j, t, ln = _candidates_within(L, x, i, float(dk[r]))
+        keep = ln <= dk[r]
+        j, t, ln = j[keep], t[keep], ln[keep]
+        by_key = np.lexsort((t[:, 2], t[:, 1], t[:, 0], j, ln))      # (length, dst, t0, t1, t2)
+        out[0].append(np.full(by_key.shape[0], i, np.int64))
+        out[1].append(j[by_key])
+        out[2].append(t[by_key])
+        out[3].append(ln[by_key])
+        ptr.append(ptr[-1] + by_key.shape[0])
+    if not srcs:
+        z = np.zeros(0, np.int64)
+        return z, z, np.zeros((0, 3), np.int64), np.zeros(0), np.zeros(1, np.int64)
+    return (np.concatenate(out[0]), np.concatenate(out[1]), np.concatenate(out[2]).reshape(-1, 3),
+            np.concatenate(out[3]), np.asarray(ptr, np.int64))
+
+
 def _structure_slices(batch_ptr, structures):
     ptr = np.asarray(batch_ptr, np.int64)
     if structures is None:

@@ -438,8 +438,41 @@ def pin_symmetrize_properties(O, seed=10):
     assert np.array_equal(qp, cptr) and np.array_equal(qd, cd) and np.array_equal(qi, ct)
 
 
+# ------------------------------------------------------------ KNN with ties
+
+
+def pin_knn_ties_shells(O):
+    """Keeping ties returns whole coordination shells: sc (a = 1) with k = 4
+    gives the 6 nearest, k = 7 gives 6 + 12 = 18; bcc (conventional, a = 1)
+    with k = 3 gives 8; fcc with k = 13 gives 12 + 6 = 18."""
+    g = golden("cubic_shells.json")
+    one = np.zeros((1, 3))
+    for k, want in ((4, 6), (7, 18), (1, 6), (6, 6)):
+        s, d, t, ln, ptr = O.knn_ties_structure64(np.eye(3), one, k)
+        assert len(s) == want and ptr.tolist() == [0, want], (k, len(s))
+    bcc = np.array(g["bcc"]["frac"], np.float64)
+    s, d, t, ln, ptr = O.knn_ties_structure64(np.eye(3), bcc, 3)
+    assert np.diff(ptr).tolist() == [8] * len(bcc)
+    fcc = np.array(g["fcc"]["frac"], np.float64)
+    s, d, t, ln, ptr = O.knn_ties_structure64(np.eye(3), fcc, 13)
+    assert np.diff(ptr).tolist() == [18] * len(fcc)
+    assert np.allclose(np.sort(ln[:18]), [math.sqrt(0.5)] * 12 + [1.0] * 6)
+
+
+def pin_knn_ties_generic(O, seed=11):
+    """Without ties (random coordinates) the selection is exactly the KNN graph,
+    in the same key order."""
+    rng = np.random.default_rng(seed)
+    L, x = _random_structure(rng, 6)
+    s, d, t, ln, ptr = O.knn_ties_structure64(L, x, 5)
+    ks, kd, kt, kl, dk, near, inside = O.knn_structure64(L, x, 5)
+    assert np.array_equal(ptr, np.arange(0, 31, 5))
+    assert np.array_equal(d, kd) and np.array_equal(t, kt) and np.allclose(ln, kl)
+
+
 ALL_PINS = [pin_cubic_shells, pin_sc_sum_of_three_squares, pin_strict_cutoff, pin_row_convention,
             pin_figure1, pin_knn_tie_break, pin_knn_single_atom_and_cluster, pin_symmetry,
             pin_supercell, pin_unimodular, pin_translation, pin_enormous_range, pin_knn_vs_cutoff,
             pin_gradients, pin_radii_closed_form, pin_radii_restriction, pin_triplets_closed_form,
-            pin_triplets_brute_force, pin_symmetrize_chain, pin_symmetrize_properties]
+            pin_triplets_brute_force, pin_symmetrize_chain, pin_symmetrize_properties,
+            pin_knn_ties_shells, pin_knn_ties_generic]

@@ -36,6 +36,7 @@ MUTATIONS = [
     ("graph64", "order = np.lexsort((t[:, 2], t[:, 1], t[:, 0], j, ln))",
      "order = np.lexsort((t[:, 2], t[:, 1], t[:, 0], ln, j))", "KNN ordered by dst before length"),
     ("graph64", "sel = order[:k]", "sel = order[1:k + 1]", "KNN off-by-one selection"),
+    ("graph64", "keep = ln <= dk[r]", "keep = ln < dk[r]", "ties at the k-th distance dropped"),
     ("symmetrize64", "out_img.append(-img[e])", "out_img.append(img[e])", "reverse edge keeps +t"),
     ("symmetrize64", "if (j, i, -int(t[0]), -int(t[1]), -int(t[2])) not in present:",
      "if (j, i, int(t[0]), int(t[1]), int(t[2])) not in present:", "presence test on (j, i, +t)"),
