@@ -68,7 +68,9 @@ enum {
                                    mg_report.images_needed holds the entries required */
     MG_FLAG_RANGE = 16u,        /* an image offset beyond |t_k| <= 511 or a KNN key space beyond 2^32
                                    would be needed: that structure (or source) has no edges */
-    MG_FLAG_KNN_EXTENDED = 32u  /* informational: some KNN sources needed the extended search */
+    MG_FLAG_KNN_EXTENDED = 32u, /* informational: some KNN sources needed the extended search */
+    MG_FLAG_TIES = 64u          /* keep-ties KNN: a source had more candidates at its k-th distance
+                                   than the search keeps (64 keys per source); its set is truncated */
 };
 
 /* Device-resident summary written by the graph calls (64 bytes). */
@@ -109,6 +111,9 @@ size_t mg_geometry_workspace_bytes(int32_t B, int64_t N);
 
 /* Workspace bytes for mg_triplets on a graph of N source atoms (0 if N < 0). */
 size_t mg_triplets_workspace_bytes(int64_t N);
+
+/* Workspace bytes for mg_knn_graph_ties (k in 1..63; 0 otherwise). */
+size_t mg_knn_ties_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_capacity);
 
 /* Workspace bytes for mg_symmetrize on N atoms and E input edges (0 if negative). */
 size_t mg_symmetrize_workspace_bytes(int64_t N, int64_t E);
@@ -200,6 +205,26 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac,
                                     const float* grad_vec, const float* grad_length,
                                     float* grad_frac, float* grad_lattice,
                                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * KNN multigraph with ties kept (Sec. 2.2, Algorithm 2: every candidate with
+ * d <= d_k): the k nearest of every source plus every further (j, t) whose FP32
+ * length equals the k-th one, in (length, dst, t) key order. The search keeps 64
+ * keys per source; a source with more candidates at its k-th distance than fit
+ * gets the first 64 and sets MG_FLAG_TIES.
+ *
+ *  k             1..63.
+ *  capacity      edge slots in src/dst/image/length (>= 0).
+ *  row_ptr       int64 [N+1] or NULL: edges of source i are row_ptr[i] .. row_ptr[i+1]-1.
+ *  report        as for mg_knn_graph, except num_edges = the number of edges kept
+ *                (exact even past capacity; MG_FLAG_CAPACITY then).
+ *  Skipped structures (MG_FLAG_SINGULAR / NONFINITE / RANGE) contribute no edges.
+ * Errors: as mg_knn_graph; MG_ERR_INVALID_ARG for k outside 1..63.
+ */
+mg_status mg_knn_graph_ties(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
+                            int64_t N, int32_t k, int64_t capacity, int32_t* src, int32_t* dst, int32_t* image,
+                            float* length, int64_t* row_ptr, mg_report* report, void* workspace,
+                            size_t workspace_bytes, int32_t opts, void* stream);
 
 /*
  * Symmetric closure (Sec. 2.2, symmetric-graph procedure): the input edges plus,

@@ -25,6 +25,7 @@ MG_FLAG_NONFINITE = 4
 MG_FLAG_IMAGES = 8
 MG_FLAG_RANGE = 16
 MG_FLAG_KNN_EXTENDED = 32
+MG_FLAG_TIES = 64
 
 MG_OPT_DEFAULT = 0
 MG_OPT_CELL_LIST_OFF = 2
@@ -69,6 +70,9 @@ SIGNATURES = {
                                          _P, _P, _SZ, _P]),
     "mg_triplets_workspace_bytes": (_SZ, [_I64]),
     "mg_symmetrize_workspace_bytes": (_SZ, [_I64, _I64]),
+    "mg_knn_ties_workspace_bytes": (_SZ, [_I32, _I64, _I32, _I64]),
+    "mg_knn_graph_ties": (_I32, [_P, _P, _P, _I32, _I64, _I32, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ, _I32,
+                                 _P]),
     "mg_symmetrize": (_I32, [_P, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "mg_triplets": (_I32, [_P, _I64, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "mg_get_tuning": (_I32, [ctypes.POINTER(MgTuning)]),

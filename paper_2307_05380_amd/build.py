@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmatgraph.so")
-SOURCES = ["api.hip", "bounds.hip", "sweep.hip", "knn.hip", "celllist.hip", "geometry.hip", "triplets.hip", "symmetrize.hip"]
+SOURCES = ["api.hip", "bounds.hip", "sweep.hip", "knn.hip", "celllist.hip", "geometry.hip", "triplets.hip", "symmetrize.hip", "ties.hip"]
 ARCH = "gfx950"
 
 

@@ -245,6 +245,34 @@ SymWsHost carve_symmetrize(void* ws, int64_t N, int64_t E) {
     return h;
 }
 
+struct TiesWs {
+    int32_t* src;
+    int32_t* dst;
+    int32_t* image;
+    float* length;
+    uint32_t* counts;
+    int64_t* offsets;
+    int64_t* bsum;
+    char* knn;          // the KNN search's own workspace follows
+    size_t fixed;
+};
+
+TiesWs carve_ties(void* ws, int64_t N) {
+    Carver c{static_cast<char*>(ws)};
+    TiesWs w;
+    const size_t M = (size_t)N * mg::TIES_K;
+    w.src = c.take<int32_t>(M);
+    w.dst = c.take<int32_t>(M);
+    w.image = c.take<int32_t>(3 * M);
+    w.length = c.take<float>(M);
+    w.counts = c.take<uint32_t>((size_t)N);
+    w.offsets = c.take<int64_t>((size_t)N + 1);
+    w.bsum = c.take<int64_t>((size_t)mg::scan_block_count(N) + 1);
+    w.fixed = mg::align_up(c.used, 256);
+    w.knn = static_cast<char*>(ws) + w.fixed;
+    return w;
+}
+
 // Smallest float y with sqrtf(y) >= c, so that l2 < y  <=>  sqrtf(l2) < c.
 float cutoff_threshold(float c) {
     float y = c * c;
@@ -291,6 +319,11 @@ size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_cap
     if (B < 0 || N < 0 || image_capacity < 0 || k < 1 || k > 64) return 0;
     KnnWs w = carve_knn(nullptr, 0, B, N);
     return w.fixed + (size_t)image_capacity * sizeof(mg::ImageEntry);
+}
+
+size_t mg_knn_ties_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_capacity) {
+    if (B < 0 || N < 0 || image_capacity < 0 || k < 1 || k >= mg::TIES_K) return 0;
+    return carve_ties(nullptr, N).fixed + mg_knn_workspace_bytes(B, N, mg::TIES_K, image_capacity);
 }
 
 size_t mg_symmetrize_workspace_bytes(int64_t N, int64_t E) {
@@ -544,6 +577,34 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac, co
                                             num_edges, grad_vec, grad_length, grad_frac, grad_lattice, w.bwd, s);
          })) != hipSuccess)
         return hip_fail(e, "geometry backward");
+    return MG_OK;
+}
+
+mg_status mg_knn_graph_ties(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
+                            int64_t N, int32_t k, int64_t capacity, int32_t* src, int32_t* dst, int32_t* image,
+                            float* length, int64_t* row_ptr, mg_report* report, void* workspace,
+                            size_t workspace_bytes, int32_t opts, void* stream) {
+    g_err.clear();
+    if (k < 1 || k >= mg::TIES_K) return fail(MG_ERR_INVALID_ARG, "k must be in 1..%d (got %d)", mg::TIES_K - 1, k);
+    if (capacity < 0) return fail(MG_ERR_INVALID_ARG, "capacity must be >= 0");
+    if (capacity > 0 && (!src || !dst || !image || !length))
+        return fail(MG_ERR_INVALID_ARG, "src/dst/image/length must be non-NULL when capacity > 0");
+    if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    if (N < 0) return fail(MG_ERR_INVALID_ARG, "N must be >= 0");
+    TiesWs w = carve_ties(workspace, N);
+    if (workspace_bytes < w.fixed)
+        return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    workspace_bytes, w.fixed);
+    mg_status st = mg_knn_graph(lattices, frac, batch_ptr, B, N, mg::TIES_K, w.src, w.dst, w.image, w.length,
+                                report, w.knn, workspace_bytes - w.fixed, opts, stream);
+    if (st != MG_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = phase("knn.ties", s, [&] {
+             return mg::launch_ties(N, k, w.src, w.dst, w.image, w.length, capacity, src, dst, image, length,
+                                    row_ptr ? row_ptr : w.offsets, w.counts, w.bsum, report, s);
+         })) != hipSuccess)
+        return hip_fail(e, "ties");
     return MG_OK;
 }
 

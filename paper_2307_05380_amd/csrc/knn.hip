@@ -209,23 +209,42 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
         }
         wave_lds_sync();
         const uint32_t nq = (uint32_t)nj * I;
+        // candidate ql = jl * I + img of this lane; the table entry of the next
+        // batch is loaded while the current one is evaluated
+        auto split = [&](uint32_t ql, uint32_t& jl, uint32_t& img) {
+            jl = (uint32_t)((float)ql * invI);
+            if (jl * I > ql) --jl;
+            if ((jl + 1) * I <= ql) ++jl;
+            img = ql - jl * I;
+        };
+        float4 ent = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (S.tab && (uint32_t)lane < nq) {
+            uint32_t jl0, im0;
+            split((uint32_t)lane, jl0, im0);
+            const ImageEntry e = S.tab[im0];
+            ent = make_float4(e.sx, e.sy, e.sz, 0.f);
+        }
         for (uint32_t b0 = 0; b0 < nq; b0 += WAVE) {
             const uint32_t ql = b0 + (uint32_t)lane;
             const bool valid = ql < nq;
-            uint32_t jl = (uint32_t)((float)ql * invI);
-            if (jl * I > ql) --jl;
-            if ((jl + 1) * I <= ql) ++jl;
-            const uint32_t img = ql - jl * I;
+            uint32_t jl, img;
+            split(ql, jl, img);
+            const float4 cur = ent;
+            if (S.tab && ql + WAVE < nq) {
+                uint32_t jn, in;
+                split(ql + WAVE, jn, in);
+                const ImageEntry e = S.tab[in];
+                ent = make_float4(e.sx, e.sy, e.sz, 0.f);
+            }
             bool pass = false;
             float l2 = 0.0f;
             if (valid) {
                 const float4 pp = P[jl];
                 float sx, sy, sz;
                 if (S.tab) {
-                    const ImageEntry e = S.tab[img];
-                    sx = e.sx;
-                    sy = e.sy;
-                    sz = e.sz;
+                    sx = cur.x;
+                    sy = cur.y;
+                    sz = cur.z;
                 } else {
                     int t0, t1, t2;
                     image_t(S, img, t0, t1, t2);

@@ -250,6 +250,12 @@ struct SymWs {
 hipError_t launch_symmetrize(const int64_t* row_ptr, int64_t N, int64_t E, const int32_t* dst, const int32_t* image,
                              const float* length, int64_t capacity, int32_t* osrc, int32_t* odst, int32_t* oimg,
                              float* olen, int64_t* out_off, const SymWs& w, mg_report* report, hipStream_t s);
+// KNN with ties: the search runs with TIES_K neighbours per source.
+constexpr int TIES_K = 64;
+hipError_t launch_ties(int64_t N, int k, const int32_t* src, const int32_t* dst, const int32_t* image,
+                       const float* length, int64_t capacity, int32_t* osrc, int32_t* odst, int32_t* oimg,
+                       float* olen, int64_t* offsets, uint32_t* counts, int64_t* bsum, mg_report* report,
+                       hipStream_t s);
 hipError_t launch_triplets(const int64_t* row_ptr, int64_t N, int64_t E, const float* vec, int64_t capacity,
                            int32_t* e1, int32_t* e2, float* cosv, int64_t* offsets, uint32_t* counts,
                            int64_t* bsum, mg_report* report, hipStream_t s);

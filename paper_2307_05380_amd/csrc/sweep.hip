@@ -3,8 +3,8 @@
 //
 // Work item = (structure, group of source atoms). Lanes hold (source,
 // destination) pairs; the image loop is uniform over the wave, so every image
-// (an FP64-derived shift s_t = t.L rounded once to FP32) is read with scalar
-// loads and shared by all lanes. The per-pair part p_ij = wrap(x_j - x_i).L is
+// (an FP64-derived shift s_t = t.L rounded once to FP32) is loaded once per
+// wave and broadcast to all lanes. The per-pair part p_ij = wrap(x_j - x_i).L is
 // computed once per item in FP64 and rounded to FP32; the inner step is
 // d = p_ij + s_t, l^2 = d.d and the strict test l < c (as l^2 < c2thr, the
 // smallest float whose correctly rounded square root reaches c).
@@ -55,6 +55,37 @@ __device__ inline Pair make_pair(const float* __restrict__ frac, const double* L
     P.w1 = (int)w1;
     P.w2 = (int)w2;
     return P;
+}
+
+// The image loop: the wave loads 64 table entries at a time, one per lane
+// (one coalesced 1 KB load, the next block in flight while the current one is
+// used), and broadcasts entry u to every lane with readlane, so the inner step
+// never waits on memory and its operands are scalar registers.
+__device__ __forceinline__ ImageEntry entry_of(const ImageEntry& mine, int u) {
+    ImageEntry e;
+    e.sx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.sx), u));
+    e.sy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.sy), u));
+    e.sz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.sz), u));
+    e.tpk = __builtin_amdgcn_readlane(mine.tpk, u);
+    return e;
+}
+
+__device__ __forceinline__ ImageEntry load_entry(const ImageEntry* __restrict__ tab, int m, int I) {
+    ImageEntry e{0.0f, 0.0f, 0.0f, 0};
+    if (m < I) e = tab[m];
+    return e;
+}
+
+template <class Step>
+__device__ __forceinline__ void for_images(const ImageEntry* __restrict__ tab, int I, int zimg, int lane,
+                                           Step&& step) {
+    ImageEntry cur = load_entry(tab, lane, I);
+    for (int m0 = 0; m0 < I; m0 += WAVE) {
+        const ImageEntry nxt = load_entry(tab, m0 + WAVE + lane, I);
+        const int cnt = min(WAVE, I - m0);
+        for (int u = 0; u < cnt; ++u) step(entry_of(cur, u), m0 + u == zimg);
+        cur = nxt;
+    }
 }
 
 __device__ inline float dist2(const Pair& P, const ImageEntry& e) {
@@ -146,11 +177,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
                     run += (uint32_t)__popcll(m);
                 }
             };
-#pragma unroll 4
-            for (int m = 0; m < zimg; ++m) step(tab[m], false);
-            step(tab[zimg], true);
-#pragma unroll 4
-            for (int m = zimg + 1; m < I; ++m) step(tab[m], false);
+            for_images(tab, I, zimg, lane, step);
             if (MODE == MODE_COUNT) {
                 const int inc = wave_incl_scan_i32(act ? (int)cnt : 0);
                 const int end = min((lane + 1) * n - 1, WAVE - 1);
@@ -191,11 +218,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
                         }
                     }
                 };
-#pragma unroll 2
-                for (int m = 0; m < zimg; ++m) step(tab[m], false);
-                step(tab[zimg], true);
-#pragma unroll 2
-                for (int m = zimg + 1; m < I; ++m) step(tab[m], false);
+                for_images(tab, I, zimg, lane, step);
             }
             if (MODE == MODE_COUNT) {
                 const int tot = wave_incl_scan_i32((int)cnt);

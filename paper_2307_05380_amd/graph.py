@@ -20,7 +20,8 @@ import torch
 from . import _lib
 
 __all__ = ["Graph", "Report", "cutoff_graph", "knn_graph", "edge_geometry", "EdgeGeometry",
-           "CutoffBuilder", "KnnBuilder", "GeometryRunner", "auto_opts", "Triplets", "triplets", "symmetrize"]
+           "CutoffBuilder", "KnnBuilder", "GeometryRunner", "auto_opts", "Triplets", "triplets", "symmetrize",
+           "knn_graph_ties"]
 
 
 @dataclasses.dataclass
@@ -39,7 +40,8 @@ class Report:
     def flag_names(self):
         names = {_lib.MG_FLAG_CAPACITY: "capacity", _lib.MG_FLAG_SINGULAR: "singular",
                  _lib.MG_FLAG_NONFINITE: "nonfinite", _lib.MG_FLAG_IMAGES: "images",
-                 _lib.MG_FLAG_RANGE: "range", _lib.MG_FLAG_KNN_EXTENDED: "knn_extended"}
+                 _lib.MG_FLAG_RANGE: "range", _lib.MG_FLAG_KNN_EXTENDED: "knn_extended",
+                 _lib.MG_FLAG_TIES: "ties"}
         return [n for b, n in names.items() if self.flags & b]
 
 
@@ -397,3 +399,42 @@ def symmetrize(row_ptr: torch.Tensor, dst: torch.Tensor, image: torch.Tensor,
         break
     S = min(rep.num_edges, cap)
     return Graph(s_[:S], d_[:S], i_[:S], l_[:S] if l_ is not None else None, out_ptr, rep)
+
+
+def knn_graph_ties(lattices, frac, batch_ptr, k: int, capacity: int | None = None,
+                   image_capacity: int | None = None, opts: int | None = None) -> Graph:
+    """KNN multigraph with ties at the k-th distance kept (Algorithm 2's d <= d_k):
+    variable edges per source, grouped by source (row_ptr), in (length, dst, t)
+    order. Reruns with the exact sizes when a capacity was too small."""
+    lattices, frac, batch_ptr, B, N = _check_inputs(lattices, frac, batch_ptr)
+    opts = auto_opts(batch_ptr, opts)
+    lib = _lib.load()
+    d = frac.device
+    cap = int(capacity) if capacity is not None else max(1024, N * (int(k) + 8))
+    icap = int(image_capacity) if image_capacity is not None else 64 * B + 4096
+    rep_t = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=d)
+    row_ptr = torch.empty(N + 1, dtype=torch.int64, device=d)
+    for _ in range(3):
+        nbytes = lib.mg_knn_ties_workspace_bytes(B, N, int(k), icap)
+        if nbytes == 0:
+            raise ValueError("invalid sizes (k must be in 1..63)")
+        ws = torch.empty(int(nbytes), dtype=torch.uint8, device=d)
+        s_ = torch.empty(cap, dtype=torch.int32, device=d)
+        d_ = torch.empty(cap, dtype=torch.int32, device=d)
+        i_ = torch.empty((cap, 3), dtype=torch.int32, device=d)
+        l_ = torch.empty(cap, dtype=torch.float32, device=d)
+        _lib.check(lib.mg_knn_graph_ties(_ptr(lattices), _ptr(frac), _ptr(batch_ptr), B, N, int(k), cap, _ptr(s_),
+                                         _ptr(d_), _ptr(i_), _ptr(l_), _ptr(row_ptr), _ptr(rep_t), _ptr(ws),
+                                         ws.numel(), int(opts), _stream(d)), lib)
+        rep = Report.from_tensor(rep_t)
+        retry = False
+        if rep.flags & _lib.MG_FLAG_IMAGES:
+            icap = int(rep.images_needed)
+            retry = True
+        if rep.flags & _lib.MG_FLAG_CAPACITY:
+            cap = int(rep.num_edges)
+            retry = True
+        if not retry:
+            break
+    E = min(rep.num_edges, cap)
+    return Graph(s_[:E], d_[:E], i_[:E], l_[:E], row_ptr, rep)
