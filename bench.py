@@ -57,6 +57,12 @@ def _parse(argv=None):
                     help="also run a plain device copy of this many MiB (profiler counter calibration)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch parameters")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP graph")
+    ap.add_argument("--update-loop", type=int, default=0, metavar="STEPS",
+                    help="also time STEPS steps of the 64-supercell update loop (cell lists): move the "
+                         "atoms, rebuild cutoff and KNN graphs, geometry forward and backward")
+    ap.add_argument("--batch-sweep", action="store_true",
+                    help="also time KNN k = 32 with ties kept on batches of 32..512 structures "
+                         "(n ~ U{4..64}), with peak device memory")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args(argv)
 
@@ -286,11 +292,132 @@ def main(argv=None):
         bb.copy_(a)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = n * 4
+    if args.batch_sweep:
+        out["batch_sweep"] = batch_sweep(dev)
+    if args.update_loop > 0:
+        out["update_loop"] = update_loop(dev, args.update_loop)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 2)
     print(json.dumps(out))
     return 0
+
+
+def update_loop(dev, steps: int, warmup: int = 2):
+    """64 supercells (8-atom base cells tiled 8..16 times per direction, ~10^6
+    atoms): every step adds a Cartesian N(0, 0.02 A) move to every atom, then
+    rebuilds the cutoff graph (5 A) and the KNN graph (k = 32), both through
+    cell lists, and runs the edge geometry forward and backward (a fixed random
+    upstream gradient on the lengths). Moves are drawn beforehand; the timed
+    region holds the coordinate update and the four library calls."""
+    import numpy as np
+    import torch
+
+    from paper_2307_05380_amd import _lib, graph, inputs
+
+    b = inputs.make_config5()
+    L = torch.from_numpy(b.lattices).to(dev)
+    X = torch.from_numpy(b.frac).to(dev)
+    P = torch.from_numpy(b.batch_ptr).to(dev)
+    n_steps = warmup + steps
+    deltas = torch.from_numpy(np.stack([inputs.config5_step_delta(b, s) for s in range(n_steps)])).to(dev)
+    g0 = graph.cutoff_graph(L, X, P, b.cutoff)
+    cap = int(g0.num_edges * 1.15) + 4096
+    del g0
+    cb = graph.CutoffBuilder(b.B, b.N, cap, 4096, dev)
+    kb = graph.KnnBuilder(b.B, b.N, b.k, 4096, dev)
+    geo = graph.GeometryRunner(b.B, b.N, dev)
+    vec = torch.empty((cap, 3), device=dev)
+    length = torch.empty(cap, device=dev)
+    gf = torch.empty_like(X)
+    gL = torch.empty_like(L)
+    glen = torch.from_numpy(np.random.default_rng(5).normal(size=cap).astype(np.float32)).to(dev)
+    ne = cb.rep[:1]
+    hist = torch.zeros(n_steps, dtype=torch.int64, device=dev)
+    flags = torch.zeros(n_steps, dtype=torch.int64, device=dev)
+
+    def step(s):
+        X.add_(deltas[s])
+        cb.run(L, X, P, b.cutoff, 0)
+        kb.run(L, X, P, 0)
+        geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
+        geo.backward(L, X, P, cb.src, cb.dst, cb.image, None, glen, gf, gL, num_edges=ne)
+        hist[s] = cb.rep[0]
+        flags[s] = cb.rep[4] | kb.rep[4]
+
+    for s in range(warmup):
+        step(s)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for s in range(warmup, n_steps):
+        step(s)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    h = hist.cpu().numpy()[warmup:]
+    f = int(np.bitwise_or.reduce(flags.cpu().numpy() & 0xFFFFFFFF))
+    bad = f & ~_lib.MG_FLAG_KNN_EXTENDED
+    assert not bad, f"update loop flags 0x{f:x}"
+    E = float(h.mean())
+    return {"supercells": b.B, "atoms": b.N, "steps": steps, "ms_per_step": round(ms, 4),
+            "cutoff_edges_mean": int(E), "knn_edges": b.N * b.k, "cutoff": b.cutoff, "k": b.k,
+            "edges_per_s": round((E + b.N * b.k) / (ms / 1e3), 1),
+            "structures_per_s": round(b.B / (ms / 1e3), 1)}
+
+
+def batch_sweep(dev, sizes=(32, 64, 128, 256, 512), k=32, reps=10):
+    """KNN graph with ties kept (the paper's selection d <= d_k) at k = 32 for
+    batches of 32..512 structures drawn like the 256-structure batch (n ~ U{4..64},
+    lengths 3-15 A, angles 60-120 deg): milliseconds per batch (device events,
+    one library call per batch, buffers preallocated) and the peak device memory
+    of a call (outputs + workspace), per batch size."""
+    import torch
+
+    from paper_2307_05380_amd import _lib, graph, inputs
+    from paper_2307_05380_amd.graph import _ptr, _stream
+
+    res = []
+    lib = _lib.load()
+    for B in sizes:
+        b = inputs.make_config2(B=B)
+        L = torch.from_numpy(b.lattices).to(dev)
+        X = torch.from_numpy(b.frac).to(dev)
+        P = torch.from_numpy(b.batch_ptr).to(dev)
+        g = graph.knn_graph_ties(L, X, P, k, opts=_lib.MG_OPT_CELL_LIST_OFF)     # sizes
+        cap, icap = max(g.report.num_edges, 1), max(g.report.images_needed, 1)
+        del g
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats(dev)
+        base = torch.cuda.memory_allocated(dev)
+        ws = torch.empty(int(lib.mg_knn_ties_workspace_bytes(B, b.N, k, icap)), dtype=torch.uint8, device=dev)
+        outs = [torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+                torch.empty((cap, 3), dtype=torch.int32, device=dev), torch.empty(cap, device=dev)]
+        row_ptr = torch.empty(b.N + 1, dtype=torch.int64, device=dev)
+        rep = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=dev)
+
+        def call():
+            _lib.check(lib.mg_knn_graph_ties(_ptr(L), _ptr(X), _ptr(P), B, b.N, k, cap, *[_ptr(o) for o in outs],
+                                             _ptr(row_ptr), _ptr(rep), _ptr(ws), ws.numel(),
+                                             _lib.MG_OPT_CELL_LIST_OFF, _stream(dev)), lib)
+
+        call()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        peak = torch.cuda.max_memory_allocated(dev) - base
+        r = graph.Report.from_tensor(rep)
+        res.append({"structures": B, "atoms": b.N, "edges": r.num_edges, "ms_per_batch": round(ms, 4),
+                    "structures_per_s": round(B / (ms / 1e3), 1), "peak_mb": round(peak / 2 ** 20, 2)})
+        del ws, outs
+    return res
 
 
 def plain_form(args, batch, L, X, P, cb, dev):
