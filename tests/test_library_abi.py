@@ -81,6 +81,49 @@ def test_host_validation(lib):
     assert st == _lib.MG_ERR_INVALID_ARG
 
 
+def test_host_validation_extra_entry_points(lib):
+    """Argument checks of the per-atom-cutoff, keep-ties, symmetrisation and
+    triplet calls (all rejected on the host, before any device work)."""
+    from paper_2307_05380_amd import _lib
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    ERR, WS = _lib.MG_ERR_INVALID_ARG, _lib.MG_ERR_WORKSPACE
+    # per-atom cutoffs: radii NULL with atoms
+    st = lib.mg_cutoff_graph_radii(fake, fake, fake, 1, 2, None, 0, None, None, None, None, None, fake, fake,
+                                   1 << 20, 0, None)
+    assert st == ERR and b"radii" in lib.mg_last_error()
+    # keep-ties KNN: k outside 1..63, NULL outputs with capacity, NULL workspace
+    for k in (0, 64):
+        st = lib.mg_knn_graph_ties(fake, fake, fake, 1, 2, k, 0, None, None, None, None, None, fake, fake,
+                                   1 << 20, 0, None)
+        assert st == ERR and b"k must be" in lib.mg_last_error()
+    st = lib.mg_knn_graph_ties(fake, fake, fake, 1, 2, 4, 8, None, None, None, None, None, fake, fake, 1 << 20,
+                               0, None)
+    assert st == ERR
+    st = lib.mg_knn_graph_ties(fake, fake, fake, 1, 2, 4, 0, None, None, None, None, None, fake, None, 0, 0, None)
+    assert st == WS
+    assert lib.mg_knn_ties_workspace_bytes(2, 10, 64, 0) == 0
+    assert lib.mg_knn_ties_workspace_bytes(2, 10, 16, 0) > lib.mg_knn_workspace_bytes(2, 10, 64, 0)
+    # symmetrisation: NULL row_ptr, NULL edges, out_length without lengths, small workspace
+    st = lib.mg_symmetrize(None, 2, fake, fake, None, 4, 0, None, None, None, None, None, fake, fake, 1 << 20, None)
+    assert st == ERR and b"row_ptr" in lib.mg_last_error()
+    st = lib.mg_symmetrize(fake, 2, None, None, None, 4, 0, None, None, None, None, None, fake, fake, 1 << 20, None)
+    assert st == ERR
+    st = lib.mg_symmetrize(fake, 2, fake, fake, None, 4, 8, fake, fake, fake, fake, None, fake, fake, 1 << 20, None)
+    assert st == ERR and b"out_length" in lib.mg_last_error()
+    st = lib.mg_symmetrize(fake, 2, fake, fake, None, 4, 0, None, None, None, None, None, fake, fake, 8, None)
+    assert st == WS
+    assert lib.mg_symmetrize_workspace_bytes(-1, 4) == 0
+    # triplets: E beyond int32, cos without vectors, NULL outputs with capacity
+    st = lib.mg_triplets(fake, 2, 1 << 31, None, 0, None, None, None, None, fake, fake, 1 << 20, None)
+    assert st == ERR
+    st = lib.mg_triplets(fake, 2, 4, None, 8, fake, fake, fake, None, fake, fake, 1 << 20, None)
+    assert st == ERR and b"vec" in lib.mg_last_error()
+    st = lib.mg_triplets(fake, 2, 4, None, 8, None, None, None, None, fake, fake, 1 << 20, None)
+    assert st == ERR
+    assert lib.mg_triplets_workspace_bytes(-1) == 0 and lib.mg_triplets_workspace_bytes(10) > 0
+
+
 def test_tuning_roundtrip(lib):
     from paper_2307_05380_amd import _lib
     t0 = _lib.get_tuning()
