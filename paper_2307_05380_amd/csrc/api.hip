@@ -545,8 +545,8 @@ mg_status mg_edge_geometry(const float* lattices, const float* frac, const int64
         hipSuccess)
         return hip_fail(e, "atom map");
     if ((e = phase("geometry.fwd", s, [&] {
-             return mg::launch_geometry_fwd(lattices, frac, w.atom_struct, N, src, dst, image, E, num_edges,
-                                            vec, length, s);
+             return mg::launch_geometry_fwd(lattices, frac, w.atom_struct, batch_ptr, B, N, src, dst, image, E,
+                                            num_edges, vec, length, w.bwd, s);
          })) != hipSuccess)
         return hip_fail(e, "geometry");
     return MG_OK;

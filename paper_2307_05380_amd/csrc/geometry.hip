@@ -23,6 +23,9 @@ __device__ inline int64_t edge_count(int64_t E, const int64_t* __restrict__ num_
 
 }  // namespace
 
+// Forward pass for edges in any order (runs when the grouped path is off:
+// flag != 0): grid-stride over edges, gathers of the source's structure, its
+// lattice and both coordinates.
 __global__ __launch_bounds__(256) void k_geom_fwd(const float* __restrict__ lattices,
                                                   const float* __restrict__ frac,
                                                   const int32_t* __restrict__ atom_struct, int64_t N,
@@ -30,7 +33,9 @@ __global__ __launch_bounds__(256) void k_geom_fwd(const float* __restrict__ latt
                                                   const int32_t* __restrict__ dst,
                                                   const int32_t* __restrict__ image, int64_t E,
                                                   const int64_t* __restrict__ num_edges,
+                                                  const int32_t* __restrict__ flag,
                                                   float* __restrict__ vec, float* __restrict__ length) {
+    if (*flag == 0) return;
     const int64_t Ee = edge_count(E, num_edges);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < Ee; e += stride) {
@@ -88,7 +93,7 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_
 //   global atomic.
 // Both kernels are launched; each leaves the items of the other at once.
 constexpr int BW_CHUNK = 16384;   // edges per item
-constexpr int BW_WIN = 2048;      // atoms of a structure held in LDS
+constexpr int BW_WIN = 1024;      // atoms of a structure held in LDS
 
 // Lane index of the start of this lane's run (runs of equal key over lanes);
 // `heads` has bit l set where lane l starts a run (bit 0 always set).
@@ -117,22 +122,16 @@ __device__ __forceinline__ T seg_scan(T v, int rs, int lane) {
     return v;
 }
 
-// Structure of edge e, or -1 if an endpoint is out of range or the endpoints
-// lie in different structures.
-__device__ __forceinline__ int32_t edge_struct(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
-                                               const int32_t* __restrict__ atom_struct, int64_t N, int64_t e) {
-    const int32_t i = src[e], j = dst[e];
-    if (i < 0 || j < 0 || i >= N || j >= N) return -1;
-    const int32_t si = atom_struct[i];
-    return si == atom_struct[j] ? si : -1;
-}
-
-// Plan: edge ranges start[s] .. start[s+1] of every structure, and flag = 1 if
-// the edges are not grouped by structure in ascending order.
-__global__ __launch_bounds__(256) void k_bwd_plan(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
-                                                  const int32_t* __restrict__ atom_struct, int64_t N, int B,
-                                                  int64_t E, const int64_t* __restrict__ num_edges,
-                                                  int64_t* __restrict__ start, int32_t* __restrict__ flag) {
+// Plan of the grouped path: the edges must come with non-decreasing src (what
+// the graph builders emit: grouped by source, sources in atom order, hence by
+// structure). One streaming pass over src records every structure's edge range
+// start[s] .. start[s+1] (atom_struct is read only where src changes) and sets
+// flag bit 0 if src decreases or leaves [0, N). A dst outside its source's
+// structure is found later by the item kernels (flag bit 1).
+__global__ __launch_bounds__(256) void k_geom_plan(const int32_t* __restrict__ src,
+                                                   const int32_t* __restrict__ atom_struct, int64_t N, int B,
+                                                   int64_t E, const int64_t* __restrict__ num_edges,
+                                                   int64_t* __restrict__ start, int32_t* __restrict__ flag) {
     const int64_t Ee = edge_count(E, num_edges);
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -141,21 +140,45 @@ __global__ __launch_bounds__(256) void k_bwd_plan(const int32_t* __restrict__ sr
         for (int64_t q = t0; q <= B; q += stride) start[q] = 0;
         return;
     }
-    // whole waves step together so that lane - 1 holds edge e - 1
+    bool bad = false;
+    // whole waves step together so that lane - 1 holds edge e - 1; four
+    // wave-rows of edges per step, their loads issued together
+    constexpr int U = 4;
+    const int64_t wstride = stride * U;
     const int64_t span = (Ee + WAVE - 1) / WAVE * WAVE;
-    for (int64_t e = t0; e < span; e += stride) {
-        const int32_t k = e < Ee ? edge_struct(src, dst, atom_struct, N, e) : B;
-        int32_t kp = __shfl_up(k, 1, WAVE);
-        if (lane == 0) kp = e == 0 ? -1 : edge_struct(src, dst, atom_struct, N, e - 1);
-        if (e >= Ee) continue;
-        if (k < 0 || (e > 0 && kp < 0) || k < kp) {
-            atomicOr(flag, 1);
-            continue;
+    const int64_t wbase = (t0 - lane) * U;            // this wave's first edge of the step
+    for (int64_t b0 = wbase; b0 < span; b0 += wstride) {
+        int32_t iv[U], ipv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = b0 + u * WAVE + lane;
+            const int32_t v = src[min(e, Ee - 1)];               // clamped: no branch around the load
+            const int32_t vp = src[min(max(e - 1, (int64_t)0), Ee - 1)];
+            iv[u] = e < Ee ? v : INT32_MAX;
+            ipv[u] = (e > 0 && e <= Ee) ? vp : -1;
         }
-        for (int32_t q = kp + 1; q <= k; ++q) start[q] = e;
-        if (e == Ee - 1)
-            for (int32_t q = k + 1; q <= B; ++q) start[q] = Ee;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = b0 + u * WAVE + lane;
+            const int32_t i = iv[u];
+            int32_t ip = __shfl_up(i, 1, WAVE);
+            if (lane == 0) ip = ipv[u];
+            if (e >= Ee) continue;
+            if (i < 0 || i >= N || i < ip) {
+                bad = true;
+                continue;
+            }
+            if (e == 0 || i != ip) {
+                const int32_t sc = atom_struct[i];
+                const int32_t sp = (e == 0 || ip < 0) ? -1 : atom_struct[ip];
+                for (int32_t q = sp + 1; q <= sc; ++q) start[q] = e;
+            }
+            if (e == Ee - 1) {
+                for (int32_t q = atom_struct[i] + 1; q <= B; ++q) start[q] = Ee;
+            }
+        }
     }
+    if (ballot(bad) != 0 && lane == 0) atomicOr(flag, 1);
 }
 
 // Items: item_off[s] = number of items of structures < s (one item per
@@ -229,7 +252,85 @@ __device__ __forceinline__ double block_lattice(const double (&la)[9], double (&
     return tid < 9 ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
 }
 
-// Grouped order, structures of at most BW_WIN atoms: LDS accumulation.
+// Forward pass of the grouped path: one workgroup per item; the structure's
+// coordinates are staged in LDS (structures of at most BW_WIN atoms), its
+// lattice is uniform, so an edge costs its streamed src/dst/image reads, two
+// LDS reads and its vec/length writes. A dst outside the structure sets flag
+// bit 1 and the generic kernel then redoes the whole pass.
+__global__ __launch_bounds__(256) void k_geom_fwd_items(const float* __restrict__ lattices,
+                                                        const float* __restrict__ frac,
+                                                        const int64_t* __restrict__ batch_ptr, int B,
+                                                        const int32_t* __restrict__ src,
+                                                        const int32_t* __restrict__ dst,
+                                                        const int32_t* __restrict__ image,
+                                                        const int64_t* __restrict__ start,
+                                                        const int64_t* __restrict__ item_off,
+                                                        int32_t* __restrict__ flag,
+                                                        float* __restrict__ vec, float* __restrict__ length) {
+    __shared__ float xs[BW_WIN * 3];
+    if (*flag != 0) return;
+    BwdItem it;
+    if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it)) return;
+    const int tid = threadIdx.x;
+    const bool lds = it.n <= BW_WIN;
+    const float* fr = frac + 3 * it.atom0;
+    if (lds) {
+        for (int q = tid; q < 3 * it.n; q += 256) xs[q] = fr[q];
+        __syncthreads();
+    }
+    const float* Lp = lattices + 9 * (int64_t)it.st;
+    double L[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) L[q] = (double)Lp[q];
+    const int32_t a0 = (int32_t)it.atom0;
+    bool bad = false;
+    // four edges per thread per step, all streamed loads issued before any use
+    constexpr int U = 4;
+    for (int64_t e0 = it.c0 + tid; e0 < it.c1; e0 += 256 * U) {
+        int li[U], lj[U], t[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = min(e0 + 256 * u, it.c1 - 1);   // clamped: no branch around the loads
+            li[u] = src[e] - a0;
+            lj[u] = dst[e] - a0;
+            t[u][0] = image[3 * e];
+            t[u][1] = image[3 * e + 1];
+            t[u][2] = image[3 * e + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + 256 * u;
+            if (e >= it.c1) break;
+            const bool okj = (unsigned)lj[u] < (unsigned)it.n;
+            bad |= !okj;
+            const float* X = lds ? xs : fr;
+            const int i3 = 3 * li[u], j3 = okj ? 3 * lj[u] : 0;
+            const double f0 = (double)X[j3] - (double)X[i3] + (double)t[u][0];
+            const double f1 = (double)X[j3 + 1] - (double)X[i3 + 1] + (double)t[u][1];
+            const double f2 = (double)X[j3 + 2] - (double)X[i3 + 2] + (double)t[u][2];
+            const double nan = __builtin_nan("");
+            const double v0 = okj ? f0 * L[0] + f1 * L[3] + f2 * L[6] : nan;
+            const double v1 = okj ? f0 * L[1] + f1 * L[4] + f2 * L[7] : nan;
+            const double v2 = okj ? f0 * L[2] + f1 * L[5] + f2 * L[8] : nan;
+            if (vec) {
+                vec[3 * e] = (float)v0;
+                vec[3 * e + 1] = (float)v1;
+                vec[3 * e + 2] = (float)v2;
+            }
+            if (length) length[e] = (float)sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+        }
+    }
+    if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
+}
+
+// Backward pass of the grouped path, structures of at most BW_WIN atoms: the
+// structure's coordinates and its coordinate gradients both live in LDS
+// (FP32 LDS atomics; a wave whose edges share the source keeps the source's
+// sum in registers), the lattice gradient in FP64 registers; each wave walks
+// a contiguous quarter of the item with the next 64 edges' streamed inputs in
+// flight. A dst outside the structure sets flag bit 1 (the results are then
+// cleared and recomputed by the general kernel).
+template <bool GV, bool GL>
 __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ lattices,
                                                       const float* __restrict__ frac,
                                                       const int64_t* __restrict__ batch_ptr, int B,
@@ -240,9 +341,10 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
                                                       const float* __restrict__ glen,
                                                       const int64_t* __restrict__ start,
                                                       const int64_t* __restrict__ item_off,
-                                                      const int32_t* __restrict__ flag,
+                                                      int32_t* __restrict__ flag,
                                                       float* __restrict__ grad_frac,
                                                       double* __restrict__ acc) {
+    __shared__ float xs[BW_WIN * 3];
     __shared__ float win[BW_WIN * 3];
     __shared__ double red[4][9];
     if (*flag != 0) return;
@@ -250,15 +352,16 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
     if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it) || it.n > BW_WIN) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const bool gf = grad_frac != nullptr;
-    if (gf) {
-        for (int q = tid; q < 3 * it.n; q += 256) win[q] = 0.0f;
-        __syncthreads();
+    const int n = it.n;
+    for (int q = tid; q < 3 * n; q += 256) {
+        xs[q] = frac[3 * it.atom0 + q];
+        win[q] = 0.0f;
     }
+    __syncthreads();
     const float* Lp = lattices + 9 * (int64_t)it.st;
     float Lf[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) Lf[q] = Lp[q];
-    const float* fr = frac + 3 * it.atom0;
     const int32_t a0 = (int32_t)it.atom0;
     // this wave's contiguous quarter of the item
     const int64_t qlen = ((it.c1 - it.c0 + 3) / 4 + WAVE - 1) / WAVE * WAVE;
@@ -268,78 +371,96 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
     double la[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) la[q] = 0.0;
-    for (int64_t base = w0; base < w1; base += WAVE) {
-        const bool act = base + lane < w1;
-        const int32_t* sw = src + base;
-        const int32_t* dw = dst + base;
-        const int32_t* iw = image + 3 * base;
-        int li = 0, lj = 0;
-        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-        double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-        if (act) {
-            li = sw[lane] - a0;
-            lj = dw[lane] - a0;
-            f0 = (double)fr[3 * lj] - (double)fr[3 * li] + (double)iw[3 * lane];
-            f1 = (double)fr[3 * lj + 1] - (double)fr[3 * li + 1] + (double)iw[3 * lane + 1];
-            f2 = (double)fr[3 * lj + 2] - (double)fr[3 * li + 2] + (double)iw[3 * lane + 2];
-            if (gvec) {
-                const float* gw = gvec + 3 * base;
-                g0 = gw[3 * lane];
-                g1 = gw[3 * lane + 1];
-                g2 = gw[3 * lane + 2];
-            }
-            if (glen) {
+    bool bad = false;
+    // U groups of 64 edges per step; all their streamed loads are issued before
+    // the first group is used
+    constexpr int U = 4;
+    for (int64_t b0 = w0; b0 < w1; b0 += WAVE * U) {
+        int ai[U], aj[U], at[U][3];
+        float ag[U][3], al[U];
+        // loads without branches (the index is clamped into the range; lanes past
+        // the end are masked later), so all U groups stay in flight together
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = min(b0 + u * WAVE + lane, w1 - 1);
+            ai[u] = src[e] - a0;
+            aj[u] = dst[e] - a0;
+            at[u][0] = image[3 * e];
+            at[u][1] = image[3 * e + 1];
+            at[u][2] = image[3 * e + 2];
+            ag[u][0] = GV ? gvec[3 * e] : 0.0f;
+            ag[u][1] = GV ? gvec[3 * e + 1] : 0.0f;
+            ag[u][2] = GV ? gvec[3 * e + 2] : 0.0f;
+            al[u] = GL ? glen[e] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t base = b0 + u * WAVE;
+            if (base >= w1) break;                       // uniform
+            // no branches between the loads and their use: lanes past the end or
+            // with a dst outside the structure compute on clamped indices and
+            // contribute zeros
+            const bool inr = base + lane < w1;
+            const bool okj = (unsigned)aj[u] < (unsigned)n;
+            bad |= inr && !okj;
+            const bool act = inr && okj;
+            const int li = ai[u], lj = okj ? aj[u] : 0;
+            const double f0 = (double)xs[3 * lj] - (double)xs[3 * li] + (double)at[u][0];
+            const double f1 = (double)xs[3 * lj + 1] - (double)xs[3 * li + 1] + (double)at[u][1];
+            const double f2 = (double)xs[3 * lj + 2] - (double)xs[3 * li + 2] + (double)at[u][2];
+            float g0 = ag[u][0], g1 = ag[u][1], g2 = ag[u][2];
+            if (GL) {
                 // v in FP64 (large image offsets), the length term in FP32
                 const double v0 = f0 * (double)Lf[0] + f1 * (double)Lf[3] + f2 * (double)Lf[6];
                 const double v1 = f0 * (double)Lf[1] + f1 * (double)Lf[4] + f2 * (double)Lf[7];
                 const double v2 = f0 * (double)Lf[2] + f1 * (double)Lf[5] + f2 * (double)Lf[8];
                 const float l2 = (float)(v0 * v0 + v1 * v1 + v2 * v2);
-                const float c = l2 > 0.0f ? glen[base + lane] / sqrtf(l2) : 0.0f;
+                const float c = l2 > 0.0f ? al[u] * __frsqrt_rn(l2) : 0.0f;
                 g0 += c * (float)v0;
                 g1 += c * (float)v1;
                 g2 += c * (float)v2;
             }
+            g0 = act ? g0 : 0.0f;
+            g1 = act ? g1 : 0.0f;
+            g2 = act ? g2 : 0.0f;
             // g L^T: component k is g . (row k of L)
-            x0 = g0 * Lf[0] + g1 * Lf[1] + g2 * Lf[2];
-            x1 = g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
-            x2 = g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
-        }
-        if (gf) {
-            if (act) {
-                atomicAdd(&win[3 * lj], x0);
+            const float x0 = g0 * Lf[0] + g1 * Lf[1] + g2 * Lf[2];
+            const float x1 = g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
+            const float x2 = g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
+            if (gf) {
+                atomicAdd(&win[3 * lj], x0);           // +0 from inactive lanes
                 atomicAdd(&win[3 * lj + 1], x1);
                 atomicAdd(&win[3 * lj + 2], x2);
-            }
-            const int iu = __builtin_amdgcn_readfirstlane(li);   // lane 0 is active
-            const bool uni = ballot(act && li != iu) == 0;
-            if (!(uni && iu == src_cur)) {
-                if (src_cur >= 0) {
-                    const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
-                    if (lane == 0) {
-                        atomicAdd(&win[3 * src_cur], r0);
-                        atomicAdd(&win[3 * src_cur + 1], r1);
-                        atomicAdd(&win[3 * src_cur + 2], r2);
+                const int iu = __builtin_amdgcn_readfirstlane(li);   // lane 0 is always in range
+                const bool uni = ballot(act && li != iu) == 0;
+                if (!(uni && iu == src_cur)) {
+                    if (src_cur >= 0) {
+                        const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
+                        if (lane == 0) {
+                            atomicAdd(&win[3 * src_cur], r0);
+                            atomicAdd(&win[3 * src_cur + 1], r1);
+                            atomicAdd(&win[3 * src_cur + 2], r2);
+                        }
                     }
+                    sa0 = sa1 = sa2 = 0.f;
+                    src_cur = uni ? iu : -1;
                 }
-                sa0 = sa1 = sa2 = 0.f;
-                src_cur = uni ? iu : -1;
+                if (src_cur >= 0) {
+                    sa0 -= x0;
+                    sa1 -= x1;
+                    sa2 -= x2;
+                } else {
+                    atomicAdd(&win[3 * li], -x0);
+                    atomicAdd(&win[3 * li + 1], -x1);
+                    atomicAdd(&win[3 * li + 2], -x2);
+                }
             }
-            if (src_cur >= 0) {
-                sa0 -= x0;
-                sa1 -= x1;
-                sa2 -= x2;
-            } else if (act) {
-                atomicAdd(&win[3 * li], -x0);
-                atomicAdd(&win[3 * li + 1], -x1);
-                atomicAdd(&win[3 * li + 2], -x2);
+            if (acc) {
+                const double h0 = g0, h1 = g1, h2 = g2;   // zero for inactive lanes
+                la[0] += f0 * h0; la[1] += f0 * h1; la[2] += f0 * h2;
+                la[3] += f1 * h0; la[4] += f1 * h1; la[5] += f1 * h2;
+                la[6] += f2 * h0; la[7] += f2 * h1; la[8] += f2 * h2;
             }
-        }
-        if (acc) {
-            const double h0 = g0, h1 = g1, h2 = g2;
-            la[0] += f0 * h0; la[1] += f0 * h1; la[2] += f0 * h2;
-            la[3] += f1 * h0; la[4] += f1 * h1; la[5] += f1 * h2;
-            la[6] += f2 * h0; la[7] += f2 * h1; la[8] += f2 * h2;
         }
     }
     if (gf && src_cur >= 0) {
@@ -350,6 +471,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
             atomicAdd(&win[3 * src_cur + 2], r2);
         }
     }
+    if (ballot(bad) != 0 && lane == 0) atomicOr(flag, 2);
     const double lt = block_lattice(la, red, tid);   // also orders the LDS atomics before the reads below
     if (acc && tid < 9) {
         if (it.whole) acc[9 * (int64_t)it.st + tid] = lt;
@@ -357,10 +479,26 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
     }
     if (gf) {
         float* out = grad_frac + 3 * it.atom0;
-        for (int q = tid; q < 3 * it.n; q += 256) {
+        for (int q = tid; q < 3 * n; q += 256) {
             const float v = win[q];
             if (it.whole) out[q] = v;
             else if (v != 0.0f) unsafeAtomicAdd(&out[q], v);
+        }
+    }
+}
+
+// After the grouped kernels: if one of them found a dst outside its structure
+// (flag bit 1), clear what they wrote so that the general kernel, which then
+// takes every edge, starts from zero.
+__global__ __launch_bounds__(256) void k_bwd_fix(const int32_t* __restrict__ flag, float* __restrict__ grad_frac,
+                                                 int64_t n3, double* __restrict__ acc, int64_t n9) {
+    if ((*flag & 2) == 0) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n3 + n9; q += stride) {
+        if (q < n3) {
+            if (grad_frac) grad_frac[q] = 0.0f;
+        } else if (acc) {
+            acc[q - n3] = 0.0;
         }
     }
 }
@@ -549,14 +687,29 @@ static int grid_for(int64_t work, int per_block, int cap) {
     return (int)g;
 }
 
+// Plan shared by both passes: flag cleared, edge ranges, items.
+static void launch_plan(const int32_t* src, const int32_t* atom_struct, int B, int64_t N, int64_t E,
+                        const int64_t* num_edges, const GeomBwdWs& w, int cu, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, w.flag, 1);
+    hipLaunchKernelGGL(k_geom_plan, dim3(grid_for(E, 256 * 4, cu * 16)), dim3(256), 0, s, src, atom_struct, N, B, E,
+                       num_edges, w.start, w.flag);
+    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, B, w.item_off);
+}
+
+// Enough workgroups for either order: sum_s max(1, ceil(E_s / chunk)) <= B + ceil(E / chunk).
+static unsigned item_grid(int B, int64_t E) { return (unsigned)((int64_t)B + (E + BW_CHUNK - 1) / BW_CHUNK); }
+
 hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const int32_t* atom_struct,
-                               int64_t N, const int32_t* src, const int32_t* dst,
-                                 const int32_t* image, int64_t E, const int64_t* num_edges,
-                                 float* vec, float* length, hipStream_t s) {
-    if (E == 0) return hipSuccess;
-    const int grid = grid_for(E, 256, device_cu_count() * 16);
-    hipLaunchKernelGGL(k_geom_fwd, dim3(grid), dim3(256), 0, s, lattices, frac, atom_struct, N, src,
-                       dst, image, E, num_edges, vec, length);
+                               const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
+                               const int32_t* dst, const int32_t* image, int64_t E, const int64_t* num_edges,
+                               float* vec, float* length, const GeomBwdWs& w, hipStream_t s) {
+    if (E == 0 || B == 0) return hipSuccess;
+    const int cu = device_cu_count();
+    launch_plan(src, atom_struct, B, N, E, num_edges, w, cu, s);
+    hipLaunchKernelGGL(k_geom_fwd_items, dim3(item_grid(B, E)), dim3(256), 0, s, lattices, frac, batch_ptr, B, src,
+                       dst, image, w.start, w.item_off, w.flag, vec, length);
+    hipLaunchKernelGGL(k_geom_fwd, dim3(grid_for(E, 256, cu * 16)), dim3(256), 0, s, lattices, frac, atom_struct, N,
+                       src, dst, image, E, num_edges, w.flag, vec, length);
     return hipGetLastError();
 }
 
@@ -572,18 +725,22 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
         hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(9 * (int64_t)B, 256, cu * 4)), dim3(256), 0, s, w.acc,
                            9 * (int64_t)B);
     if (E > 0 && B > 0 && (grad_frac || grad_lattice) && (grad_vec || grad_length)) {
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, w.flag, 1);
-        hipLaunchKernelGGL(k_bwd_plan, dim3(grid_for(E, 256, cu * 16)), dim3(256), 0, s, src, dst, atom_struct, N,
-                           B, E, num_edges, w.start, w.flag);
-        hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, B, w.item_off);
-        // enough workgroups for either order: sum_s max(1, ceil(E_s / chunk)) <= B + ceil(E / chunk)
-        const int64_t grid = (int64_t)B + (E + BW_CHUNK - 1) / BW_CHUNK;
+        launch_plan(src, atom_struct, B, N, E, num_edges, w, cu, s);
+        const unsigned grid = item_grid(B, E);
         double* acc = grad_lattice ? w.acc : nullptr;
-        hipLaunchKernelGGL(k_geom_bwd_lds, dim3((unsigned)grid), dim3(256), 0, s, lattices, frac, batch_ptr, B,
-                           src, dst, image, grad_vec, grad_length, w.start, w.item_off, w.flag, grad_frac, acc);
-        hipLaunchKernelGGL(k_geom_bwd_any, dim3((unsigned)grid), dim3(256), 0, s, lattices, frac, atom_struct,
-                           batch_ptr, B, N, src, dst, image, E, num_edges, grad_vec, grad_length, w.start,
-                           w.item_off, w.flag, grad_frac, acc);
+#define MG_BWD_LDS(GV, GL)                                                                                     \
+    hipLaunchKernelGGL((k_geom_bwd_lds<GV, GL>), dim3(grid), dim3(256), 0, s, lattices, frac, batch_ptr, B, src, \
+                       dst, image, grad_vec, grad_length, w.start, w.item_off, w.flag, grad_frac, acc)
+        if (grad_vec && grad_length) MG_BWD_LDS(true, true);
+        else if (grad_vec) MG_BWD_LDS(true, false);
+        else MG_BWD_LDS(false, true);
+#undef MG_BWD_LDS
+        const int64_t n3 = grad_frac ? 3 * N : 0, n9 = acc ? 9 * (int64_t)B : 0;
+        hipLaunchKernelGGL(k_bwd_fix, dim3(grid_for(n3 + n9, 256, cu * 4)), dim3(256), 0, s, w.flag, grad_frac, n3,
+                           acc, n9);
+        hipLaunchKernelGGL(k_geom_bwd_any, dim3(grid), dim3(256), 0, s, lattices, frac, atom_struct, batch_ptr, B, N,
+                           src, dst, image, E, num_edges, grad_vec, grad_length, w.start, w.item_off, w.flag,
+                           grad_frac, acc);
     }
     if (grad_lattice && B > 0)
         hipLaunchKernelGGL(k_finalize_lattice, dim3(grid_for(9 * (int64_t)B, 256, 1 << 30)), dim3(256), 0, s,

@@ -218,18 +218,18 @@ hipError_t launch_knn_extended(int B, int64_t N, int k, const StructInfo* info, 
                                Counters* ctr, mg_report* report, int grid, hipStream_t s);
 hipError_t launch_atom_struct(const int64_t* batch_ptr, int B, int64_t N, int32_t* atom_struct,
                               hipStream_t s);
-hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const int32_t* atom_struct,
-                               int64_t N, const int32_t* src, const int32_t* dst, const int32_t* image,
-                               int64_t E, const int64_t* num_edges, float* vec, float* length,
-                               hipStream_t s);
-// Workspace of the geometry backward pass: lattice accumulators (9 B), edge
-// range of every structure (B + 1), items per structure (B + 1), order flag.
+// Workspace of the geometry passes: lattice accumulators (9 B), edge range of
+// every structure (B + 1), items per structure (B + 1), order flag.
 struct GeomBwdWs {
     double* acc;
     int64_t* start;
     int64_t* item_off;
     int32_t* flag;
 };
+hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const int32_t* atom_struct,
+                               const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
+                               const int32_t* dst, const int32_t* image, int64_t E, const int64_t* num_edges,
+                               float* vec, float* length, const GeomBwdWs& w, hipStream_t s);
 hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const int32_t* atom_struct,
                                const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
                                const int32_t* dst, const int32_t* image, int64_t E,

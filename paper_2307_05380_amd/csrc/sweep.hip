@@ -57,34 +57,28 @@ __device__ inline Pair make_pair(const float* __restrict__ frac, const double* L
     return P;
 }
 
-// The image loop: the wave loads 64 table entries at a time, one per lane
-// (one coalesced 1 KB load, the next block in flight while the current one is
-// used), and broadcasts entry u to every lane with readlane, so the inner step
-// never waits on memory and its operands are scalar registers.
-__device__ __forceinline__ ImageEntry entry_of(const ImageEntry& mine, int u) {
-    ImageEntry e;
-    e.sx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.sx), u));
-    e.sy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.sy), u));
-    e.sz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.sz), u));
-    e.tpk = __builtin_amdgcn_readlane(mine.tpk, u);
-    return e;
-}
-
-__device__ __forceinline__ ImageEntry load_entry(const ImageEntry* __restrict__ tab, int m, int I) {
-    ImageEntry e{0.0f, 0.0f, 0.0f, 0};
-    if (m < I) e = tab[m];
-    return e;
-}
+// The image loop: every lane uses the same image, so the entries are read
+// through the constant address space (scalar loads into SGPRs, waited on by
+// their own counter, never behind the fill's vector stores) and the step's
+// shift operands are scalar registers.
+typedef const __attribute__((address_space(4))) ImageEntry* ConstTable;
 
 template <class Step>
-__device__ __forceinline__ void for_images(const ImageEntry* __restrict__ tab, int I, int zimg, int lane,
+__device__ __forceinline__ void for_images(const ImageEntry* __restrict__ table, int I, int zimg, int lane,
                                            Step&& step) {
-    ImageEntry cur = load_entry(tab, lane, I);
-    for (int m0 = 0; m0 < I; m0 += WAVE) {
-        const ImageEntry nxt = load_entry(tab, m0 + WAVE + lane, I);
-        const int cnt = min(WAVE, I - m0);
-        for (int u = 0; u < cnt; ++u) step(entry_of(cur, u), m0 + u == zimg);
-        cur = nxt;
+    (void)lane;
+    // the table address is wave-uniform; make that explicit so the loads are scalar
+    const uint64_t a = (uint64_t)table;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    ConstTable tab = (ConstTable)(((uint64_t)hi << 32) | lo);
+    for (int m = 0; m < I; ++m) {
+        ImageEntry e;
+        e.sx = tab[m].sx;
+        e.sy = tab[m].sy;
+        e.sz = tab[m].sz;
+        e.tpk = tab[m].tpk;
+        step(e, m == zimg);
     }
 }
 

@@ -40,15 +40,49 @@ def test_ties_shells(name, frac, k, want):
     assert np.abs(ln - ol).max() <= 2e-5
 
 
-def test_ties_generic_equals_knn():
+def test_ties_random_batch():
+    """Random coordinates: the first k edges of every source are its KNN edges;
+    further edges tie the k-th FP32 length exactly (a self image t always ties
+    its mirror -t); and the kept set agrees with the oracle's d <= d_k set except
+    for candidates within 1e-4 A of d_k that are not exact ties."""
     rng = np.random.default_rng(70)
     b = inputs.random_batch(rng, 40, 1, 60, 3.0, 10.0, cutoff=5.0, k=12)
-    g = _ties(b, 12)
+    k = 12
+    g = _ties(b, k)
     kg = gu.knn(b)
-    assert g.report.num_edges == b.N * 12
-    assert torch.equal(g.row_ptr, torch.arange(0, b.N * 12 + 1, 12, device="cuda"))
-    for a, c in zip(gu.np_graph(g), gu.np_graph(kg)):
-        assert np.array_equal(a, c)
+    assert g.report.flags == 0, g.report.flag_names()
+    rp = g.row_ptr.cpu().numpy()
+    s, d, t, ln = gu.np_graph(g)
+    ks, kd, kt, kl = gu.np_graph(kg)
+    cnt = np.diff(rp)
+    assert (cnt >= k).all()
+    extra = 0
+    for i in range(b.N):
+        a0 = rp[i]
+        assert np.array_equal(d[a0:a0 + k], kd[i * k:(i + 1) * k])
+        assert np.array_equal(t[a0:a0 + k], kt[i * k:(i + 1) * k])
+        assert (ln[a0 + k:rp[i + 1]] == ln[a0 + k - 1]).all()
+        extra += cnt[i] - k
+    print("edges beyond k (exact ties):", extra)
+    for q in range(b.B):
+        a0, a1 = int(b.batch_ptr[q]), int(b.batch_ptr[q + 1])
+        L, x = b.structure(q)
+        os_, od, ot, ol, optr = oracle.knn_ties_structure64(L, x, k)
+        for r in range(a1 - a0):
+            i = a0 + r
+            got = {(int(dd),) + tuple(int(v) for v in tt) for dd, tt in zip(d[rp[i]:rp[i + 1]], t[rp[i]:rp[i + 1]])}
+            sl = slice(optr[r], optr[r + 1])
+            want = {(int(dd) + a0,) + tuple(int(v) for v in tt) for dd, tt in zip(od[sl], ot[sl])}
+            dk = ol[sl].max()
+            # candidates that are not exact ties but lie within the band are not judged
+            _, l_got = oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, np.full(len(got), i),
+                                              np.array([g_[0] for g_ in got]), np.array([g_[1:] for g_ in got]))
+            assert (l_got <= dk + 1e-4).all()
+            missing = want - got
+            if missing:
+                _, l_m = oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, np.full(len(missing), i),
+                                                np.array([m[0] for m in missing]), np.array([m[1:] for m in missing]))
+                assert (l_m >= dk - 1e-4).all(), (i, missing)
 
 
 def test_ties_capacity_and_truncation():
