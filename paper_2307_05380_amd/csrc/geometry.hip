@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_
 //   global atomic.
 // Both kernels are launched; each leaves the items of the other at once.
 constexpr int BW_CHUNK = 16384;   // edges per item
-constexpr int BW_WIN = 1024;      // atoms of a structure held in LDS
+constexpr int BW_WIN = 512;       // atoms of a structure held in LDS
 
 // Lane index of the start of this lane's run (runs of equal key over lanes);
 // `heads` has bit l set where lane l starts a run (bit 0 always set).
@@ -323,14 +323,22 @@ __global__ __launch_bounds__(256) void k_geom_fwd_items(const float* __restrict_
     if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
 }
 
-// Backward pass of the grouped path, structures of at most BW_WIN atoms: the
-// structure's coordinates and its coordinate gradients both live in LDS
-// (FP32 LDS atomics; a wave whose edges share the source keeps the source's
-// sum in registers), the lattice gradient in FP64 registers; each wave walks
-// a contiguous quarter of the item with the next 64 edges' streamed inputs in
-// flight. A dst outside the structure sets flag bit 1 (the results are then
-// cleared and recomputed by the general kernel).
-template <bool GV, bool GL>
+// Backward pass of the grouped path, structures of at most WIN atoms. The
+// structure's coordinates are staged in LDS; every wave accumulates the
+// coordinate gradients of its edges in a private LDS copy with plain
+// read-modify-writes (FP32 LDS atomics are several times slower than the
+// whole rest of the pass): lanes whose dst is unique in the wave update at
+// once, and a lane whose dst another lane of the same step also targets waits
+// for a later round (each round every contended atom has one owner, the last
+// lane that wrote its tag). Runs of one source are summed in registers (the
+// edges are ordered by source), or by a segmented scan when a step mixes
+// sources. The lattice gradient stays in FP64 registers. The four copies are
+// summed at the end and written with plain stores when the item is the whole
+// structure. Each wave walks a contiguous quarter of the item, four groups of
+// 64 edges per step with all their loads issued first. A dst outside the
+// structure sets flag bit 1 (the results are then cleared and recomputed by
+// the general kernel).
+template <bool GV, bool GL, int WIN>
 __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ lattices,
                                                       const float* __restrict__ frac,
                                                       const int64_t* __restrict__ batch_ptr, int B,
@@ -343,19 +351,23 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
                                                       const int64_t* __restrict__ item_off,
                                                       int32_t* __restrict__ flag,
                                                       float* __restrict__ grad_frac,
-                                                      double* __restrict__ acc) {
-    __shared__ float xs[BW_WIN * 3];
-    __shared__ float win[BW_WIN * 3];
+                                                      double* __restrict__ acc,
+                                                      int n_lo) {
+    __shared__ float xs[WIN * 3];
+    __shared__ float wacc[4][WIN * 3];
+    __shared__ int tag[4][WIN];
     __shared__ double red[4][9];
     if (*flag != 0) return;
     BwdItem it;
-    if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it) || it.n > BW_WIN) return;
+    if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it) || it.n > WIN || it.n <= n_lo) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const bool gf = grad_frac != nullptr;
     const int n = it.n;
+    float* my = wacc[wv];
+    int* mytag = tag[wv];
     for (int q = tid; q < 3 * n; q += 256) {
         xs[q] = frac[3 * it.atom0 + q];
-        win[q] = 0.0f;
+        wacc[0][q] = wacc[1][q] = wacc[2][q] = wacc[3][q] = 0.0f;
     }
     __syncthreads();
     const float* Lp = lattices + 9 * (int64_t)it.st;
@@ -372,8 +384,18 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
 #pragma unroll
     for (int q = 0; q < 9; ++q) la[q] = 0.0;
     bool bad = false;
-    // U groups of 64 edges per step; all their streamed loads are issued before
-    // the first group is used
+    auto add_src_run = [&]() {   // lane 0 adds the wave's source run
+        if (src_cur >= 0) {
+            const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
+            if (lane == 0) {
+                my[3 * src_cur] -= r0;
+                my[3 * src_cur + 1] -= r1;
+                my[3 * src_cur + 2] -= r2;
+            }
+            wave_lds_sync();
+        }
+        sa0 = sa1 = sa2 = 0.f;
+    };
     constexpr int U = 4;
     for (int64_t b0 = w0; b0 < w1; b0 += WAVE * U) {
         int ai[U], aj[U], at[U][3];
@@ -397,9 +419,6 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
         for (int u = 0; u < U; ++u) {
             const int64_t base = b0 + u * WAVE;
             if (base >= w1) break;                       // uniform
-            // no branches between the loads and their use: lanes past the end or
-            // with a dst outside the structure compute on clamped indices and
-            // contribute zeros
             const bool inr = base + lane < w1;
             const bool okj = (unsigned)aj[u] < (unsigned)n;
             bad |= inr && !okj;
@@ -428,31 +447,45 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
             const float x1 = g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
             const float x2 = g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
             if (gf) {
-                atomicAdd(&win[3 * lj], x0);           // +0 from inactive lanes
-                atomicAdd(&win[3 * lj + 1], x1);
-                atomicAdd(&win[3 * lj + 2], x2);
+                // destination side: rounds of owner lanes (bounded: every round
+                // retires at least the owner of each contended atom)
+                bool pend = act;
+                for (int round = 0; round < WAVE && ballot(pend) != 0; ++round) {
+                    if (pend) mytag[lj] = lane;
+                    wave_lds_sync();
+                    const bool own = pend && mytag[lj] == lane;
+                    if (own) {
+                        my[3 * lj] += x0;
+                        my[3 * lj + 1] += x1;
+                        my[3 * lj + 2] += x2;
+                    }
+                    wave_lds_sync();
+                    pend = pend && !own;
+                }
+                // source side
                 const int iu = __builtin_amdgcn_readfirstlane(li);   // lane 0 is always in range
                 const bool uni = ballot(act && li != iu) == 0;
                 if (!(uni && iu == src_cur)) {
-                    if (src_cur >= 0) {
-                        const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
-                        if (lane == 0) {
-                            atomicAdd(&win[3 * src_cur], r0);
-                            atomicAdd(&win[3 * src_cur + 1], r1);
-                            atomicAdd(&win[3 * src_cur + 2], r2);
-                        }
-                    }
-                    sa0 = sa1 = sa2 = 0.f;
+                    add_src_run();
                     src_cur = uni ? iu : -1;
                 }
                 if (src_cur >= 0) {
-                    sa0 -= x0;
-                    sa1 -= x1;
-                    sa2 -= x2;
+                    sa0 += x0;
+                    sa1 += x1;
+                    sa2 += x2;
                 } else {
-                    atomicAdd(&win[3 * li], -x0);
-                    atomicAdd(&win[3 * li + 1], -x1);
-                    atomicAdd(&win[3 * li + 2], -x2);
+                    // mixed sources: sources are sorted, so each one is a run of lanes
+                    const int key = act ? li : -1 - lane;   // inactive lanes are runs of their own
+                    const uint64_t heads = run_heads(key, lane);
+                    const int rs = run_start(heads, lane);
+                    const float y0 = seg_scan(x0, rs, lane), y1 = seg_scan(x1, rs, lane),
+                                y2 = seg_scan(x2, rs, lane);
+                    if (act && run_tail(heads, lane)) {
+                        my[3 * li] -= y0;
+                        my[3 * li + 1] -= y1;
+                        my[3 * li + 2] -= y2;
+                    }
+                    wave_lds_sync();
                 }
             }
             if (acc) {
@@ -463,16 +496,9 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
             }
         }
     }
-    if (gf && src_cur >= 0) {
-        const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
-        if (lane == 0) {
-            atomicAdd(&win[3 * src_cur], r0);
-            atomicAdd(&win[3 * src_cur + 1], r1);
-            atomicAdd(&win[3 * src_cur + 2], r2);
-        }
-    }
+    if (gf) add_src_run();
     if (ballot(bad) != 0 && lane == 0) atomicOr(flag, 2);
-    const double lt = block_lattice(la, red, tid);   // also orders the LDS atomics before the reads below
+    const double lt = block_lattice(la, red, tid);   // also orders the LDS updates before the reads below
     if (acc && tid < 9) {
         if (it.whole) acc[9 * (int64_t)it.st + tid] = lt;
         else unsafeAtomicAdd(&acc[9 * (int64_t)it.st + tid], lt);
@@ -480,7 +506,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
     if (gf) {
         float* out = grad_frac + 3 * it.atom0;
         for (int q = tid; q < 3 * n; q += 256) {
-            const float v = win[q];
+            const float v = (wacc[0][q] + wacc[1][q]) + (wacc[2][q] + wacc[3][q]);
             if (it.whole) out[q] = v;
             else if (v != 0.0f) unsafeAtomicAdd(&out[q], v);
         }
@@ -728,12 +754,19 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
         launch_plan(src, atom_struct, B, N, E, num_edges, w, cu, s);
         const unsigned grid = item_grid(B, E);
         double* acc = grad_lattice ? w.acc : nullptr;
-#define MG_BWD_LDS(GV, GL)                                                                                     \
-    hipLaunchKernelGGL((k_geom_bwd_lds<GV, GL>), dim3(grid), dim3(256), 0, s, lattices, frac, batch_ptr, B, src, \
-                       dst, image, grad_vec, grad_length, w.start, w.item_off, w.flag, grad_frac, acc)
-        if (grad_vec && grad_length) MG_BWD_LDS(true, true);
-        else if (grad_vec) MG_BWD_LDS(true, false);
-        else MG_BWD_LDS(false, true);
+        // two LDS sizes: structures of up to 128 atoms (most), and 129..BW_WIN atoms
+#define MG_BWD_LDS(GV, GL, WIN, LO)                                                                           \
+    hipLaunchKernelGGL((k_geom_bwd_lds<GV, GL, WIN>), dim3(grid), dim3(256), 0, s, lattices, frac, batch_ptr, B, \
+                       src, dst, image, grad_vec, grad_length, w.start, w.item_off, w.flag, grad_frac, acc, LO)
+#define MG_BWD_LDS2(GV, GL)              \
+    do {                                 \
+        MG_BWD_LDS(GV, GL, 128, 0);      \
+        MG_BWD_LDS(GV, GL, BW_WIN, 128); \
+    } while (0)
+        if (grad_vec && grad_length) MG_BWD_LDS2(true, true);
+        else if (grad_vec) MG_BWD_LDS2(true, false);
+        else MG_BWD_LDS2(false, true);
+#undef MG_BWD_LDS2
 #undef MG_BWD_LDS
         const int64_t n3 = grad_frac ? 3 * N : 0, n9 = acc ? 9 * (int64_t)B : 0;
         hipLaunchKernelGGL(k_bwd_fix, dim3(grid_for(n3 + n9, 256, cu * 4)), dim3(256), 0, s, w.flag, grad_frac, n3,
