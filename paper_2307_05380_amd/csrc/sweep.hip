@@ -87,17 +87,36 @@ __device__ inline float dist2(const Pair& P, const ImageEntry& e) {
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
-__device__ inline void write_edge(int64_t e, int64_t capacity, int64_t src_atom, int64_t dst_atom,
-                                  const Pair& P, int32_t tpk, float l2, int32_t* __restrict__ src,
-                                  int32_t* __restrict__ dst, int32_t* __restrict__ image,
-                                  float* __restrict__ length) {
-    if (e >= capacity) return;
-    src[e] = (int32_t)src_atom;
-    dst[e] = (int32_t)dst_atom;
-    image[3 * e] = unpack_t0(tpk) - P.w0;
-    image[3 * e + 1] = unpack_t1(tpk) - P.w1;
-    image[3 * e + 2] = unpack_t2(tpk) - P.w2;
-    length[e] = sqrtf(l2);
+// Output arrays rebased at the item's first edge (a wave-uniform offset), so a
+// store needs only a 32-bit per-lane offset from a scalar base.
+struct OutRel {
+    int32_t* src;
+    int32_t* dst;
+    int32_t* image;
+    float* length;
+    int64_t cap;   // capacity - base: relative edges >= cap are not written
+};
+
+__device__ __forceinline__ OutRel rebase(int64_t base, int64_t capacity, int32_t* src, int32_t* dst, int32_t* image,
+                                         float* length) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)base >> 32));
+    const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
+    return OutRel{src + b, dst + b, image + 3 * b, length + b, capacity - b};
+}
+
+__device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t src_atom, int32_t dst_atom,
+                                           const Pair& P, int32_t tpk, float l2) {
+    if ((int64_t)e >= o.cap) return;
+    // 32-bit byte offsets from the scalar bases (an item's edges are far fewer than 2^28)
+    const uint32_t b4 = e * 4u, b12 = e * 12u;
+    *(int32_t*)((char*)o.src + b4) = src_atom;
+    *(int32_t*)((char*)o.dst + b4) = dst_atom;
+    int32_t* im = (int32_t*)((char*)o.image + b12);
+    im[0] = unpack_t0(tpk) - P.w0;
+    im[1] = unpack_t1(tpk) - P.w1;
+    im[2] = unpack_t2(tpk) - P.w2;
+    *(float*)((char*)o.length + b4) = sqrtf(l2);
 }
 
 }  // namespace
@@ -151,12 +170,16 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
             const float c2 = (thr && act) ? thr[atom0 + il] : c2thr;   // the source's cutoff
             uint32_t cnt = 0;
             uint32_t run = 0;
-            int64_t base = 0;
+            uint32_t base = 0;      // this lane's source's first edge, relative to the item's
             uint64_t seg = 0;
+            OutRel out{};
             if (MODE == MODE_FILL) {
-                base = act ? offsets[atom0 + il] : 0;
+                const int64_t ibase = offsets[atom0 + i_first];
+                out = rebase(ibase, capacity, src, dst, image, length);
+                base = act ? (uint32_t)(offsets[atom0 + il] - ibase) : 0u;
                 seg = (n == WAVE) ? ~0ull : (((1ull << n) - 1ull) << (a * n));
             }
+            const int32_t sa = (int32_t)(atom0 + il), da = (int32_t)(atom0 + j);
             auto step = [&](const ImageEntry& e, bool zero) {
                 const float l2 = dist2(P, e);
                 bool hit = l2 < c2;
@@ -165,9 +188,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
                     cnt += hit ? 1u : 0u;
                 } else {
                     const uint64_t m = ballot(hit) & seg;
-                    if (hit)
-                        write_edge(base + run + mbcnt(m), capacity, atom0 + il, atom0 + j, P, e.tpk, l2,
-                                   src, dst, image, length);
+                    if (hit) write_edge(base + run + mbcnt(m), out, sa, da, P, e.tpk, l2);
                     run += (uint32_t)__popcll(m);
                 }
             };
@@ -186,7 +207,9 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
             const float c2 = thr ? thr[atom0 + il] : c2thr;
             uint32_t cnt = 0;
             uint32_t run = 0;
-            const int64_t base = (MODE == MODE_FILL) ? offsets[atom0 + il] : 0;
+            OutRel out{};
+            if (MODE == MODE_FILL) out = rebase(offsets[atom0 + il], capacity, src, dst, image, length);
+            const int32_t sa = (int32_t)(atom0 + il);
             for (int jc = 0; jc < n; jc += WAVE * SLOTS) {
                 Pair P[SLOTS];
 #pragma unroll
@@ -205,9 +228,8 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
                         } else {
                             const uint64_t m = ballot(hit);
                             if (hit)
-                                write_edge(base + run + mbcnt(m), capacity, atom0 + il,
-                                           atom0 + jc + r * WAVE + lane, P[r], e.tpk, l2, src, dst,
-                                           image, length);
+                                write_edge(run + mbcnt(m), out, sa, (int32_t)(atom0 + jc + r * WAVE + lane), P[r],
+                                           e.tpk, l2);
                             run += (uint32_t)__popcll(m);
                         }
                     }
