@@ -283,6 +283,8 @@ __global__ __launch_bounds__(256) void k_geom_fwd_items(const float* __restrict_
 #pragma unroll
     for (int q = 0; q < 9; ++q) L[q] = (double)Lp[q];
     const int32_t a0 = (int32_t)it.atom0;
+    float* vec_b = vec ? vec + 3 * it.c0 : nullptr;
+    float* len_b = length ? length + it.c0 : nullptr;
     bool bad = false;
     // four edges per thread per step, all streamed loads issued before any use
     constexpr int U = 4;
@@ -312,12 +314,16 @@ __global__ __launch_bounds__(256) void k_geom_fwd_items(const float* __restrict_
             const double v0 = okj ? f0 * L[0] + f1 * L[3] + f2 * L[6] : nan;
             const double v1 = okj ? f0 * L[1] + f1 * L[4] + f2 * L[7] : nan;
             const double v2 = okj ? f0 * L[2] + f1 * L[5] + f2 * L[8] : nan;
+            // 32-bit byte offsets from the item's first edge (scalar bases)
+            const uint32_t r = (uint32_t)(e - it.c0);
             if (vec) {
-                vec[3 * e] = (float)v0;
-                vec[3 * e + 1] = (float)v1;
-                vec[3 * e + 2] = (float)v2;
+                float* vp = (float*)((char*)vec_b + 12u * r);
+                vp[0] = (float)v0;
+                vp[1] = (float)v1;
+                vp[2] = (float)v2;
             }
-            if (length) length[e] = (float)sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+            // the FP32 square root of the FP64 square, rounded once: within a few ulps
+            if (length) *(float*)((char*)len_b + 4u * r) = sqrtf((float)(v0 * v0 + v1 * v1 + v2 * v2));
         }
     }
     if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
