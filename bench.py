@@ -38,7 +38,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 # algorithmic work per unit: bytes per edge / flops per candidate
 BYTES_PER_EDGE_FILL = 24.0     # src, dst (4+4), image (12), length (4)
-BYTES_PER_EDGE_GEOM = 36.0     # read src, dst, image (20) + write vec, length (16)  /  read grads (16)
+BYTES_PER_EDGE_GEOM = 36.0     # forward: read src, dst, image (20) + write vec, length (16)
+BYTES_PER_EDGE_GEOM_BWD = 24.0 # backward with the length gradient only: read src, dst, image (20) + grad (4)
 FLOPS_PER_CANDIDATE = 8.0      # 3 add + 1 mul + 2 fma (= 8 flops) per (source, destination, image)
 
 
@@ -65,6 +66,35 @@ def _parse(argv=None):
                          "(n ~ U{4..64}), with peak device memory")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args(argv)
+
+
+def source_digest() -> str:
+    """Digest of the HIP sources: hardware counters recorded for an older build
+    no longer describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2307_05380_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(phase: str):
+    """HBM bytes per launch of a phase's kernels from the committed hardware-counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    device copy of known size), or None when the summary is missing or was taken
+    on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_config3.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    v = t.get("phases", {}).get(phase)
+    return None if v is None else v.get("bytes_per_launch")
 
 
 def _log(args, *a):
@@ -235,7 +265,7 @@ def main(argv=None):
         "cutoff.count": ("alu", FLOPS_PER_CANDIDATE * rep_c.candidates),
         "knn.select": ("alu", FLOPS_PER_CANDIDATE * rep_k.candidates),
         "geometry.fwd": ("hbm", BYTES_PER_EDGE_GEOM * E),
-        "geometry.bwd": ("hbm", BYTES_PER_EDGE_GEOM * E),
+        "geometry.bwd": ("hbm", BYTES_PER_EDGE_GEOM_BWD * E),
     }
     for name, (ms, cnt) in phases.items():
         avg = ms / max(cnt, 1)
@@ -256,7 +286,7 @@ def main(argv=None):
     if dom:
         d = per[dom]
         roof = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
-                "unit": d["unit"], "frac": d["frac"], "traffic": None}
+                "unit": d["unit"], "frac": d["frac"], "traffic": measured_traffic(dom)}
 
     # ---- per-structure launch form (the plain method, one launch sequence per structure)
     plain = None
@@ -271,7 +301,7 @@ def main(argv=None):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "ms_per_step_events": round(ms_step_ev, 4),
         "ms_per_step_eager": round(ms_eager, 4), "timed": "eager" if args.no_graph else "hip_graph",
-        "ms_loss_model_part": round(ms_loss, 4), "tuning": tuning,
+        "ms_loss_model_part": round(ms_loss, 4), "tuning": tuning, "source_digest": source_digest(),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"config{args.config}: {B} structures, {N} atoms, cutoff {c} A, k {k}, "
