@@ -23,9 +23,11 @@ __device__ inline int64_t edge_count(int64_t E, const int64_t* __restrict__ num_
 
 }  // namespace
 
-// Forward pass for edges in any order (runs when the grouped path is off:
-// flag != 0): grid-stride over edges, gathers of the source's structure, its
-// lattice and both coordinates.
+// Forward pass: grid-stride over edges, four edges per thread per step with
+// every streamed load (src, dst, image) issued before the gathers that depend
+// on them (the source's structure, its lattice, both coordinates) and no
+// branch between a load and its use (indices are clamped; an edge with an
+// endpoint outside [0, N) gets NaN). FP64 arithmetic, FP32 results.
 __global__ __launch_bounds__(256) void k_geom_fwd(const float* __restrict__ lattices,
                                                   const float* __restrict__ frac,
                                                   const int32_t* __restrict__ atom_struct, int64_t N,
@@ -33,29 +35,54 @@ __global__ __launch_bounds__(256) void k_geom_fwd(const float* __restrict__ latt
                                                   const int32_t* __restrict__ dst,
                                                   const int32_t* __restrict__ image, int64_t E,
                                                   const int64_t* __restrict__ num_edges,
-                                                  const int32_t* __restrict__ flag,
                                                   float* __restrict__ vec, float* __restrict__ length) {
-    if (*flag == 0) return;
     const int64_t Ee = edge_count(E, num_edges);
+    if (Ee == 0) return;
+    constexpr int U = 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < Ee; e += stride) {
-        const int32_t i = src[e], j = dst[e];
-        double v0 = __builtin_nan(""), v1 = v0, v2 = v0;
-        if (i >= 0 && j >= 0 && i < N && j < N) {
-            const float* L = lattices + 9 * (int64_t)atom_struct[i];
-            const double f0 = (double)frac[3 * (int64_t)j] - (double)frac[3 * (int64_t)i] + (double)image[3 * e];
-            const double f1 = (double)frac[3 * (int64_t)j + 1] - (double)frac[3 * (int64_t)i + 1] + (double)image[3 * e + 1];
-            const double f2 = (double)frac[3 * (int64_t)j + 2] - (double)frac[3 * (int64_t)i + 2] + (double)image[3 * e + 2];
-            v0 = f0 * (double)L[0] + f1 * (double)L[3] + f2 * (double)L[6];
-            v1 = f0 * (double)L[1] + f1 * (double)L[4] + f2 * (double)L[7];
-            v2 = f0 * (double)L[2] + f1 * (double)L[5] + f2 * (double)L[8];
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < Ee; e0 += stride * U) {
+        int32_t i[U], j[U], t[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = min(e0 + u * stride, Ee - 1);
+            i[u] = src[e];
+            j[u] = dst[e];
+            t[u][0] = image[3 * e];
+            t[u][1] = image[3 * e + 1];
+            t[u][2] = image[3 * e + 2];
         }
-        if (vec) {
-            vec[3 * e] = (float)v0;
-            vec[3 * e + 1] = (float)v1;
-            vec[3 * e + 2] = (float)v2;
+        bool ok[U];
+        int32_t ic[U], jc[U], st[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ok[u] = (uint64_t)(uint32_t)i[u] < (uint64_t)N && (uint64_t)(uint32_t)j[u] < (uint64_t)N;
+            ic[u] = ok[u] ? i[u] : 0;
+            jc[u] = ok[u] ? j[u] : 0;
+            st[u] = atom_struct[ic[u]];
         }
-        if (length) length[e] = (float)sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * stride;
+            const float* L = lattices + 9 * (int64_t)st[u];
+            const float* xi = frac + 3 * (int64_t)ic[u];
+            const float* xj = frac + 3 * (int64_t)jc[u];
+            const double f0 = (double)xj[0] - (double)xi[0] + (double)t[u][0];
+            const double f1 = (double)xj[1] - (double)xi[1] + (double)t[u][1];
+            const double f2 = (double)xj[2] - (double)xi[2] + (double)t[u][2];
+            const double nan = __builtin_nan("");
+            const double v0 = ok[u] ? f0 * (double)L[0] + f1 * (double)L[3] + f2 * (double)L[6] : nan;
+            const double v1 = ok[u] ? f0 * (double)L[1] + f1 * (double)L[4] + f2 * (double)L[7] : nan;
+            const double v2 = ok[u] ? f0 * (double)L[2] + f1 * (double)L[5] + f2 * (double)L[8] : nan;
+            if (e < Ee) {
+                if (vec) {
+                    vec[3 * e] = (float)v0;
+                    vec[3 * e + 1] = (float)v1;
+                    vec[3 * e + 2] = (float)v2;
+                }
+                // the FP32 square root of the FP64 square, rounded once: within a few ulps
+                if (length) length[e] = sqrtf((float)(v0 * v0 + v1 * v1 + v2 * v2));
+            }
+        }
     }
 }
 
@@ -250,83 +277,6 @@ __device__ __forceinline__ double block_lattice(const double (&la)[9], double (&
     }
     __syncthreads();
     return tid < 9 ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
-}
-
-// Forward pass of the grouped path: one workgroup per item; the structure's
-// coordinates are staged in LDS (structures of at most BW_WIN atoms), its
-// lattice is uniform, so an edge costs its streamed src/dst/image reads, two
-// LDS reads and its vec/length writes. A dst outside the structure sets flag
-// bit 1 and the generic kernel then redoes the whole pass.
-__global__ __launch_bounds__(256) void k_geom_fwd_items(const float* __restrict__ lattices,
-                                                        const float* __restrict__ frac,
-                                                        const int64_t* __restrict__ batch_ptr, int B,
-                                                        const int32_t* __restrict__ src,
-                                                        const int32_t* __restrict__ dst,
-                                                        const int32_t* __restrict__ image,
-                                                        const int64_t* __restrict__ start,
-                                                        const int64_t* __restrict__ item_off,
-                                                        int32_t* __restrict__ flag,
-                                                        float* __restrict__ vec, float* __restrict__ length) {
-    __shared__ float xs[BW_WIN * 3];
-    if (*flag != 0) return;
-    BwdItem it;
-    if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it)) return;
-    const int tid = threadIdx.x;
-    const bool lds = it.n <= BW_WIN;
-    const float* fr = frac + 3 * it.atom0;
-    if (lds) {
-        for (int q = tid; q < 3 * it.n; q += 256) xs[q] = fr[q];
-        __syncthreads();
-    }
-    const float* Lp = lattices + 9 * (int64_t)it.st;
-    double L[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) L[q] = (double)Lp[q];
-    const int32_t a0 = (int32_t)it.atom0;
-    float* vec_b = vec ? vec + 3 * it.c0 : nullptr;
-    float* len_b = length ? length + it.c0 : nullptr;
-    bool bad = false;
-    // four edges per thread per step, all streamed loads issued before any use
-    constexpr int U = 4;
-    for (int64_t e0 = it.c0 + tid; e0 < it.c1; e0 += 256 * U) {
-        int li[U], lj[U], t[U][3];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t e = min(e0 + 256 * u, it.c1 - 1);   // clamped: no branch around the loads
-            li[u] = src[e] - a0;
-            lj[u] = dst[e] - a0;
-            t[u][0] = image[3 * e];
-            t[u][1] = image[3 * e + 1];
-            t[u][2] = image[3 * e + 2];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t e = e0 + 256 * u;
-            if (e >= it.c1) break;
-            const bool okj = (unsigned)lj[u] < (unsigned)it.n;
-            bad |= !okj;
-            const float* X = lds ? xs : fr;
-            const int i3 = 3 * li[u], j3 = okj ? 3 * lj[u] : 0;
-            const double f0 = (double)X[j3] - (double)X[i3] + (double)t[u][0];
-            const double f1 = (double)X[j3 + 1] - (double)X[i3 + 1] + (double)t[u][1];
-            const double f2 = (double)X[j3 + 2] - (double)X[i3 + 2] + (double)t[u][2];
-            const double nan = __builtin_nan("");
-            const double v0 = okj ? f0 * L[0] + f1 * L[3] + f2 * L[6] : nan;
-            const double v1 = okj ? f0 * L[1] + f1 * L[4] + f2 * L[7] : nan;
-            const double v2 = okj ? f0 * L[2] + f1 * L[5] + f2 * L[8] : nan;
-            // 32-bit byte offsets from the item's first edge (scalar bases)
-            const uint32_t r = (uint32_t)(e - it.c0);
-            if (vec) {
-                float* vp = (float*)((char*)vec_b + 12u * r);
-                vp[0] = (float)v0;
-                vp[1] = (float)v1;
-                vp[2] = (float)v2;
-            }
-            // the FP32 square root of the FP64 square, rounded once: within a few ulps
-            if (length) *(float*)((char*)len_b + 4u * r) = sqrtf((float)(v0 * v0 + v1 * v1 + v2 * v2));
-        }
-    }
-    if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 2);
 }
 
 // Backward pass of the grouped path, structures of at most WIN atoms. The
@@ -735,13 +685,12 @@ hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const i
                                const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
                                const int32_t* dst, const int32_t* image, int64_t E, const int64_t* num_edges,
                                float* vec, float* length, const GeomBwdWs& w, hipStream_t s) {
+    (void)batch_ptr;
+    (void)w;
     if (E == 0 || B == 0) return hipSuccess;
     const int cu = device_cu_count();
-    launch_plan(src, atom_struct, B, N, E, num_edges, w, cu, s);
-    hipLaunchKernelGGL(k_geom_fwd_items, dim3(item_grid(B, E)), dim3(256), 0, s, lattices, frac, batch_ptr, B, src,
-                       dst, image, w.start, w.item_off, w.flag, vec, length);
-    hipLaunchKernelGGL(k_geom_fwd, dim3(grid_for(E, 256, cu * 16)), dim3(256), 0, s, lattices, frac, atom_struct, N,
-                       src, dst, image, E, num_edges, w.flag, vec, length);
+    hipLaunchKernelGGL(k_geom_fwd, dim3(grid_for(E, 256 * 4, cu * 16)), dim3(256), 0, s, lattices, frac, atom_struct,
+                       N, src, dst, image, E, num_edges, vec, length);
     return hipGetLastError();
 }
 
