@@ -65,7 +65,7 @@ enum {
     MG_FLAG_SINGULAR = 2u,      /* a lattice with |det| < 1e-9 * |a1||a2||a3|: that structure has no edges */
     MG_FLAG_NONFINITE = 4u,     /* a NaN/Inf lattice entry or coordinate: that structure has no edges */
     MG_FLAG_IMAGES = 8u,        /* the workspace's image table was too small: the graph is incomplete;
-                                   mg_report.images_needed holds the entries required */
+                                   mg_report.images_needed holds the slots required */
     MG_FLAG_RANGE = 16u,        /* an image offset beyond |t_k| <= 511 or a KNN key space beyond 2^32
                                    would be needed: that structure (or source) has no edges */
     MG_FLAG_KNN_EXTENDED = 32u, /* informational: some KNN sources needed the extended search */
@@ -76,7 +76,7 @@ enum {
 /* Device-resident summary written by the graph calls (64 bytes). */
 typedef struct mg_report {
     int64_t num_edges;       /* edges the inputs define (cutoff: exact even if > capacity; KNN: N*k) */
-    int64_t images_needed;   /* image-table entries the batch needs (see mg_*_workspace_bytes) */
+    int64_t images_needed;   /* image slots the batch needs (see mg_*_workspace_bytes) */
     int64_t candidates;      /* (source, destination, image) candidates evaluated by the main sweep */
     int64_t knn_extended;    /* KNN sources resolved by the extended search */
     uint32_t flags;          /* MG_FLAG_* */
@@ -97,10 +97,12 @@ int32_t mg_abi_version(void);
 const char* mg_last_error(void);
 
 /* Workspace bytes for mg_cutoff_graph on B structures / N atoms with room for
- * `image_capacity` image-table entries (16 bytes each). The table holds, per
- * structure, the lattice translations whose cell can reach within the cutoff;
- * a cutoff call sets MG_FLAG_IMAGES and reports images_needed when the batch
- * needs more. Returns 0 for negative arguments. */
+ * `image_capacity` image slots (45 bytes each). Every structure takes one slot
+ * per translation of its search box (the translations its per-axis bounds
+ * allow); the table then keeps, per structure, those whose cell can reach
+ * within the cutoff. A cutoff call sets MG_FLAG_IMAGES and reports
+ * images_needed (the slots the batch needs) when the batch needs more.
+ * Returns 0 for negative arguments. */
 size_t mg_cutoff_workspace_bytes(int32_t B, int64_t N, int64_t image_capacity);
 
 /* Workspace bytes for mg_knn_graph (same meaning of image_capacity; k in 1..64). */

@@ -118,6 +118,21 @@ void carve_cl(Carver& c, int B, int64_t N, mg::Counters* ctr, mg::ClWs& w) {
     w.ctr = ctr;
 }
 
+// The image tables take the workspace after the fixed part: per slot a box
+// entry, a keep flag, a scan value and a compacted entry.
+mg::ImageTables carve_images(Carver& c, size_t bytes) {
+    mg::ImageTables t;
+    const int64_t room = (int64_t)bytes - (int64_t)c.used - mg::IMAGE_FIXED_BYTES;
+    t.cap = room > 0 ? room / mg::IMAGE_SLOT_BYTES : 0;
+    if (c.base == nullptr) t.cap = 0;
+    t.box = c.take<mg::ImageEntry>((size_t)t.cap);
+    t.table = c.take<mg::ImageEntry>((size_t)t.cap);
+    t.kscan = c.take<int64_t>((size_t)t.cap + 1);
+    t.kflag = c.take<uint32_t>((size_t)t.cap);
+    t.kbsum = c.take<int64_t>((size_t)mg::scan_block_count(t.cap) + 1);
+    return t;
+}
+
 struct CutoffWs {
     mg::Counters* ctr;
     mg::StructInfo* info;
@@ -129,8 +144,7 @@ struct CutoffWs {
     int64_t* partials;
     float* thr;
     mg::ClWs cl;
-    mg::ImageEntry* table;
-    int64_t table_cap;
+    mg::ImageTables img;
     size_t fixed;
 };
 
@@ -154,9 +168,8 @@ CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
     w.partials = c.take<int64_t>((size_t)mg::MAX_GRID_WAVES);
     w.thr = c.take<float>((size_t)N);
     carve_cl(c, B, N, w.ctr, w.cl);
-    w.table = c.take<mg::ImageEntry>(0);
     w.fixed = c.used;
-    w.table_cap = bytes > w.fixed ? (int64_t)((bytes - w.fixed) / sizeof(mg::ImageEntry)) : 0;
+    w.img = carve_images(c, bytes);
     return w;
 }
 
@@ -168,8 +181,7 @@ struct KnnWs {
     int32_t* ext_list;
     int64_t* partials;
     mg::ClWs cl;
-    mg::ImageEntry* table;
-    int64_t table_cap;
+    mg::ImageTables img;
     size_t fixed;
 };
 
@@ -183,9 +195,8 @@ KnnWs carve_knn(void* ws, size_t bytes, int B, int64_t N) {
     w.ext_list = c.take<int32_t>((size_t)N);
     w.partials = c.take<int64_t>((size_t)mg::MAX_GRID_WAVES);
     carve_cl(c, B, N, w.ctr, w.cl);
-    w.table = c.take<mg::ImageEntry>(0);
     w.fixed = c.used;
-    w.table_cap = bytes > w.fixed ? (int64_t)((bytes - w.fixed) / sizeof(mg::ImageEntry)) : 0;
+    w.img = carve_images(c, bytes);
     return w;
 }
 
@@ -312,13 +323,13 @@ const char* mg_last_error(void) { return g_err.c_str(); }
 size_t mg_cutoff_workspace_bytes(int32_t B, int64_t N, int64_t image_capacity) {
     if (B < 0 || N < 0 || image_capacity < 0) return 0;
     CutoffWs w = carve_cutoff(nullptr, 0, B, N);
-    return w.fixed + (size_t)image_capacity * sizeof(mg::ImageEntry);
+    return w.fixed + (size_t)mg::IMAGE_FIXED_BYTES + (size_t)image_capacity * (size_t)mg::IMAGE_SLOT_BYTES;
 }
 
 size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_capacity) {
     if (B < 0 || N < 0 || image_capacity < 0 || k < 1 || k > 64) return 0;
     KnnWs w = carve_knn(nullptr, 0, B, N);
-    return w.fixed + (size_t)image_capacity * sizeof(mg::ImageEntry);
+    return w.fixed + (size_t)mg::IMAGE_FIXED_BYTES + (size_t)image_capacity * (size_t)mg::IMAGE_SLOT_BYTES;
 }
 
 size_t mg_knn_ties_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_capacity) {
@@ -382,17 +393,17 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("cutoff.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.table_cap, s);
+             return mg::launch_struct_scan(B, w.info, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
          })) != hipSuccess)
         return hip_fail(e, "plan");
-    if ((e = phase("cutoff.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.table, w.table_cap, s); })) !=
+    if ((e = phase("cutoff.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.img, s); })) !=
         hipSuccess)
         return hip_fail(e, "images");
     if (cl && (e = phase("cutoff.cells", s, [&] { return mg::launch_cl_build(B, N, frac, batch_ptr, w.info, w.cl, s); })) !=
                   hipSuccess)
         return hip_fail(e, "cell lists");
     if ((e = phase("cutoff.count", s, [&] {
-             hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.table, frac, c2, thr, w.counts, offs,
+             hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.img.table, frac, c2, thr, w.counts, offs,
                                                     capacity, src, dst, image, length, w.ctr, report, w.partials,
                                                     grid, tu.cutoff_slots, s);
              if (r != hipSuccess || !sum) return r;
@@ -412,7 +423,7 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
          })) != hipSuccess)
         return hip_fail(e, "scan");
     if ((e = phase("cutoff.fill", s, [&] {
-             return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.table, frac, c2, thr, w.counts, offs,
+             return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.img.table, frac, c2, thr, w.counts, offs,
                                             capacity, src, dst, image, length, w.ctr, report, w.partials,
                                             grid, tu.cutoff_slots, s);
          })) != hipSuccess)
@@ -486,10 +497,10 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("knn.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.table_cap, s);
+             return mg::launch_struct_scan(B, w.info, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
          })) != hipSuccess)
         return hip_fail(e, "plan");
-    if ((e = phase("knn.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.table, w.table_cap, s); })) !=
+    if ((e = phase("knn.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.img, s); })) !=
         hipSuccess)
         return hip_fail(e, "images");
     if ((e = phase("knn.atoms", s, [&] { return mg::launch_atom_struct(batch_ptr, B, N, w.cl.atom_struct, s); })) !=
@@ -499,7 +510,7 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
                   hipSuccess)
         return hip_fail(e, "cell lists");
     if ((e = phase("knn.select", s, [&] {
-             hipError_t r = mg::launch_knn(B, N, k, w.info, w.item_off, w.table, frac, src, dst, image, length,
+             hipError_t r = mg::launch_knn(B, N, k, w.info, w.item_off, w.img.table, frac, src, dst, image, length,
                                            w.ext_list, w.ctr, report, w.partials, grid, s);
              if (r != hipSuccess || !sum) return r;
              return mg::launch_sum_partials(w.partials, grid * 4, report, s);

@@ -361,7 +361,8 @@ __device__ double cell_min_dist2(const double G[3][3], int t0, int t1, int t2) {
 __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __restrict__ info,
                                                      const int64_t* __restrict__ box_off,
                                                      const Counters* __restrict__ ctr,
-                                                     ImageEntry* __restrict__ table, int64_t capacity) {
+                                                     ImageEntry* __restrict__ table, uint32_t* __restrict__ kflag,
+                                                     int64_t capacity) {
     const int64_t total = min(ctr->total_box, capacity);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
@@ -372,7 +373,10 @@ __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __
             else hi = mid;
         }
         const StructInfo* si = info + lo;
-        if (si->box == 0) continue;       // skipped structure (its slot is never read)
+        if (si->box == 0) {               // skipped structure (its slot is never read)
+            kflag[idx] = 0u;
+            continue;
+        }
         const int64_t loc = idx - box_off[lo];
         const int n0 = si->nk[0], n1 = si->nk[1], n2 = si->nk[2];
         const int w1 = 2 * n1 + 1, w2 = 2 * n2 + 1;
@@ -438,62 +442,55 @@ __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __
         e.sz = (float)cz;
         e.tpk = keep ? pack_t(t0, t1, t2) : -1;
         table[idx] = e;
+        kflag[idx] = keep ? 1u : 0u;
     }
 }
 
-// One workgroup per structure: stable in-place compaction of the kept images
-// (lexicographic order is kept) and the table index of t = 0.
-__global__ __launch_bounds__(256) void k_image_compact(StructInfo* __restrict__ info,
-                                                       ImageEntry* __restrict__ table,
-                                                       int64_t capacity) {
-    __shared__ uint32_t s_cnt[4];
-    __shared__ int s_total;
-    const int b = blockIdx.x;
-    const int t = threadIdx.x, w = t >> 6;
-    const int64_t box = info[b].box;
-    const int64_t off = info[b].img_off;
+// Kept images moved to their compacted slots (kscan: exclusive scan of the keep
+// flags over the whole table, so every structure's kept images stay contiguous
+// and in lexicographic order).
+__global__ __launch_bounds__(256) void k_image_scatter(const Counters* __restrict__ ctr,
+                                                       const ImageEntry* __restrict__ table,
+                                                       const uint32_t* __restrict__ kflag,
+                                                       const int64_t* __restrict__ kscan,
+                                                       ImageEntry* __restrict__ ctable, int64_t capacity) {
+    const int64_t total = min(ctr->total_box, capacity);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride)
+        if (kflag[idx]) ctable[kscan[idx]] = table[idx];
+}
+
+// Per structure: offset of its compacted images, their number and the index
+// of t = 0 (the box centre, always kept).
+__global__ __launch_bounds__(256) void k_image_offsets(int B, StructInfo* __restrict__ info,
+                                                       const uint32_t* __restrict__ kflag,
+                                                       const int64_t* __restrict__ kscan, int64_t capacity) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    StructInfo& si = info[b];
+    const int64_t box = si.box, off = si.img_off;
     if (box == 0 || off + box > capacity) {
-        if (t == 0) {
-            info[b].images = 0;
-            info[b].zero_img = -1;
-        }
+        si.images = 0;
+        si.zero_img = -1;
         return;
     }
-    if (t == 0) s_total = 0;
-    __syncthreads();
-    ImageEntry* slot = table + off;
-    const int32_t zero_pk = pack_t(0, 0, 0);
-    for (int64_t base = 0; base < box; base += 256) {
-        const int64_t idx = base + t;
-        ImageEntry e;
-        bool keep = false;
-        if (idx < box) {
-            e = slot[idx];
-            keep = e.tpk >= 0;
-        }
-        const uint64_t m = ballot(keep);
-        if ((t & 63) == 0) s_cnt[w] = (uint32_t)__popcll(m);
-        __syncthreads();
-        int pos = s_total;
-        for (int q = 0; q < w; ++q) pos += (int)s_cnt[q];
-        pos += (int)mbcnt(m);
-        if (keep) {
-            slot[pos] = e;
-            if (e.tpk == zero_pk) info[b].zero_img = pos;
-        }
-        __syncthreads();
-        if (t == 0) s_total += (int)(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
-        __syncthreads();
-    }
-    if (t == 0) info[b].images = s_total;
+    const int64_t c = ((int64_t)si.nk[0] * (2 * si.nk[1] + 1) + si.nk[1]) * (2 * si.nk[2] + 1) + si.nk[2];
+    const int64_t first = kscan[off];
+    si.images = (int)(kscan[off + box] - first);
+    si.zero_img = kflag[off + c] ? (int)(kscan[off + c] - first) : -1;
+    si.img_off = first;
 }
 
-hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr,
-                         ImageEntry* table, int64_t image_capacity, hipStream_t s) {
+hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr, const ImageTables& t,
+                         hipStream_t s) {
     if (B == 0) return hipSuccess;
     const int grid = device_cu_count() * 8;
-    hipLaunchKernelGGL(k_image_flags, dim3(grid), dim3(256), 0, s, B, info, box_off, ctr, table, image_capacity);
-    hipLaunchKernelGGL(k_image_compact, dim3(B), dim3(256), 0, s, info, table, image_capacity);
+    hipLaunchKernelGGL(k_image_flags, dim3(grid), dim3(256), 0, s, B, info, box_off, ctr, t.box, t.kflag, t.cap);
+    // the scan covers the batch's boxes only (their total is known on the device)
+    hipError_t e = launch_scan_counts(t.kflag, t.cap, t.kscan, t.kbsum, INT64_MAX, nullptr, s, &ctr->total_box);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_image_scatter, dim3(grid), dim3(256), 0, s, ctr, t.box, t.kflag, t.kscan, t.table, t.cap);
+    hipLaunchKernelGGL(k_image_offsets, dim3((B + 255) / 256), dim3(256), 0, s, B, info, t.kflag, t.kscan, t.cap);
     return hipGetLastError();
 }
 

@@ -196,8 +196,23 @@ hipError_t launch_cl_knn(int B, int k, const StructInfo* info, const ClWs& w, co
                          int32_t* src, int32_t* dst, int32_t* image, float* length,
                          int32_t* ext_list, Counters* ctr, mg_report* report, int64_t* partials,
                          int grid, hipStream_t s);
-hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr,
-                         ImageEntry* table, int64_t image_capacity, hipStream_t s);
+// Image tables: every structure's box-sized slot (box), keep flags and their
+// exclusive scan over the whole capacity, and the compacted tables read by the
+// sweeps (table: each structure's kept images contiguous, lexicographic).
+struct ImageTables {
+    ImageEntry* box;
+    uint32_t* kflag;
+    int64_t* kscan;   // cap + 1
+    int64_t* kbsum;
+    ImageEntry* table;
+    int64_t cap;
+};
+// Workspace bytes per image slot (box entry, flag, scan value, compacted entry)
+// and a fixed allowance for scan partials and alignment.
+constexpr int64_t IMAGE_SLOT_BYTES = 45;
+constexpr int64_t IMAGE_FIXED_BYTES = 4096;
+hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr, const ImageTables& t,
+                         hipStream_t s);
 hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
                                const ImageEntry* table, const float* frac, float c2thr,
                                const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
@@ -205,9 +220,11 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
                                hipStream_t s);
 // Exclusive scan of counts[0..N) into offsets[0..N]; with a report, also
-// records the total as num_edges and flags a capacity overflow.
+// records the total as num_edges and flags a capacity overflow. With n_dev
+// (a device count), only min(N, *n_dev) counts are scanned.
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offsets, int64_t* bsum,
-                              int64_t capacity, mg_report* report, hipStream_t s);
+                              int64_t capacity, mg_report* report, hipStream_t s,
+                              const int64_t* n_dev = nullptr);
 hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const int64_t* item_off,
                       const ImageEntry* table, const float* frac, int32_t* src, int32_t* dst,
                       int32_t* image, float* length, int32_t* ext_list, Counters* ctr,

@@ -283,26 +283,42 @@ __device__ inline int64_t block_sum_256(int64_t v, int64_t* sh) {
     return t;
 }
 
+// Exclusive scan of N counts (offsets[N] = total). With n_dev set, only the
+// first min(N, *n_dev) counts are scanned and offsets[] ends there; launches
+// are sized for N so that the count may be known on the device only.
+__device__ __forceinline__ int64_t scan_length(int64_t N, const int64_t* n_dev) {
+    if (!n_dev) return N;
+    const int64_t n = *n_dev;
+    return n < 0 ? 0 : (n < N ? n : N);
+}
+
 __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ counts, int64_t N,
+                                                   const int64_t* __restrict__ n_dev,
                                                    int64_t* __restrict__ bsum) {
     __shared__ int64_t sh[4];
+    const int64_t n = scan_length(N, n_dev);
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    if (base >= n) return;            // never read by the final pass
     int64_t s = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int64_t idx = base + k * 256 + threadIdx.x;
-        if (idx < N) s += counts[idx];
+        if (idx < n) s += counts[idx];
     }
     s = block_sum_256(s, sh);
     if (threadIdx.x == 0) bsum[blockIdx.x] = s;
 }
 
 __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__ counts, int64_t N,
+                                                    const int64_t* __restrict__ n_dev,
                                                     const int64_t* __restrict__ bsum,
                                                     int64_t* __restrict__ offsets, int64_t capacity,
                                                     mg_report* __restrict__ rep) {
     __shared__ int64_t sh[4];
     __shared__ int64_t swave[4];
+    const int64_t n = scan_length(N, n_dev);
+    const int64_t last = n > 0 ? (n - 1) / SCAN_TILE : 0;   // the block that writes offsets[n]
+    if ((int64_t)blockIdx.x > last) return;
     int64_t p = 0;
     for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) p += bsum[b];
     p = block_sum_256(p, sh);
@@ -311,7 +327,7 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__
     int64_t tsum = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        v[k] = (base + k < N) ? counts[base + k] : 0u;
+        v[k] = (base + k < n) ? counts[base + k] : 0u;
         tsum += v[k];
     }
     const int64_t inc = wave_incl_scan_i64(tsum);
@@ -322,11 +338,11 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__
     for (int q = 0; q < w; ++q) excl += swave[q];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        if (base + k < N) offsets[base + k] = excl;
+        if (base + k < n) offsets[base + k] = excl;
         excl += v[k];
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) {
-        offsets[N] = excl;
+    if ((int64_t)blockIdx.x == last && threadIdx.x == 255) {
+        offsets[n] = excl;
         if (rep) {
             rep->num_edges = excl;
             if (excl > capacity) atomicOr(&rep->flags, (uint32_t)MG_FLAG_CAPACITY);
@@ -335,10 +351,10 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__
 }
 
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offsets, int64_t* bsum,
-                              int64_t capacity, mg_report* report, hipStream_t s) {
+                              int64_t capacity, mg_report* report, hipStream_t s, const int64_t* n_dev) {
     const int64_t nb = N > 0 ? (N + SCAN_TILE - 1) / SCAN_TILE : 1;
-    if (N > 0) hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, counts, N, bsum);
-    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(256), 0, s, counts, N, bsum, offsets,
+    if (N > 0) hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, counts, N, n_dev, bsum);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(256), 0, s, counts, N, n_dev, bsum, offsets,
                        capacity, report);
     return hipGetLastError();
 }
