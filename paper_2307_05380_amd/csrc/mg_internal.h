@@ -105,8 +105,11 @@ __device__ inline int wave_incl_scan_i32(int v) {
 // items w, w + W, w + 2W, ... (W waves in the grid). Consecutive items (the
 // sources of one structure) land on different waves, which balances uneven
 // structures without a shared counter; every loop is bounded by the item count.
+// The wave index is made explicitly wave-uniform so that the item loop, its
+// structure search and the per-structure loads run on the scalar unit.
 __device__ __forceinline__ int64_t grid_wave() {
-    return (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    return (int64_t)blockIdx.x * (blockDim.x / WAVE) + w;
 }
 __device__ __forceinline__ int64_t grid_waves() { return (int64_t)gridDim.x * (blockDim.x / WAVE); }
 
@@ -207,6 +210,8 @@ struct ImageTables {
     ImageEntry* table;
     int64_t cap;
 };
+// The cutoff sweep reads a structure's images in groups of IMG_GROUP entries.
+constexpr int IMG_GROUP = 4;
 // Workspace bytes per image slot (box entry, flag, scan value, compacted entry)
 // and a fixed allowance for scan partials and alignment.
 constexpr int64_t IMAGE_SLOT_BYTES = 45;

@@ -60,26 +60,35 @@ __device__ inline Pair make_pair(const float* __restrict__ frac, const double* L
 // The image loop: every lane uses the same image, so the entries are read
 // through the constant address space (scalar loads into SGPRs, waited on by
 // their own counter, never behind the fill's vector stores) and the step's
-// shift operands are scalar registers.
+// shift operands are scalar registers. Entries are read in groups of
+// IMG_GROUP (one wait per group), the last few one at a time.
 typedef const __attribute__((address_space(4))) ImageEntry* ConstTable;
 
+__device__ __forceinline__ ImageEntry image_at(ConstTable tab, int m) {
+    ImageEntry e;
+    e.sx = tab[m].sx;
+    e.sy = tab[m].sy;
+    e.sz = tab[m].sz;
+    e.tpk = tab[m].tpk;
+    return e;
+}
+
 template <class Step>
-__device__ __forceinline__ void for_images(const ImageEntry* __restrict__ table, int I, int zimg, int lane,
-                                           Step&& step) {
-    (void)lane;
+__device__ __forceinline__ void for_images(const ImageEntry* __restrict__ table, int I, Step&& step) {
     // the table address is wave-uniform; make that explicit so the loads are scalar
     const uint64_t a = (uint64_t)table;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
     ConstTable tab = (ConstTable)(((uint64_t)hi << 32) | lo);
-    for (int m = 0; m < I; ++m) {
-        ImageEntry e;
-        e.sx = tab[m].sx;
-        e.sy = tab[m].sy;
-        e.sz = tab[m].sz;
-        e.tpk = tab[m].tpk;
-        step(e, m == zimg);
+    int m = 0;
+    for (; m + IMG_GROUP <= I; m += IMG_GROUP) {
+        ImageEntry e[IMG_GROUP];
+#pragma unroll
+        for (int u = 0; u < IMG_GROUP; ++u) e[u] = image_at(tab, m + u);
+#pragma unroll
+        for (int u = 0; u < IMG_GROUP; ++u) step(e[u]);
     }
+    for (; m < I; ++m) step(image_at(tab, m));
 }
 
 __device__ inline float dist2(const Pair& P, const ImageEntry& e) {
@@ -124,7 +133,7 @@ __device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t 
 constexpr int MODE_COUNT = 0, MODE_FILL = 1;
 
 template <int MODE, int SLOTS>
-__global__ __launch_bounds__(256) void k_cutoff_sweep(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_cutoff_sweep(
     int B, const StructInfo* __restrict__ info, const int64_t* __restrict__ item_off,
     const ImageEntry* __restrict__ table, const float* __restrict__ frac, float c2thr,
     const float* __restrict__ thr, uint32_t* __restrict__ counts, const int64_t* __restrict__ offsets, int64_t capacity,
@@ -150,6 +159,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
         const int I = si->box == 0 ? 0 : si->images;
         const int zimg = si->zero_img;
         const ImageEntry* tab = table + si->img_off;
+        const int32_t zero_pk = pack_t(0, 0, 0);
         double L[9];
 #pragma unroll
         for (int r = 0; r < 9; ++r) L[r] = si->L[r];
@@ -180,20 +190,22 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
                 seg = (n == WAVE) ? ~0ull : (((1ull << n) - 1ull) << (a * n));
             }
             const int32_t sa = (int32_t)(atom0 + il), da = (int32_t)(atom0 + j);
-            auto step = [&](const ImageEntry& e, bool zero) {
+            auto step = [&](const ImageEntry& e) {
                 const float l2 = dist2(P, e);
                 bool hit = l2 < c2;
-                if (zero) hit = hit && !P.self;
                 if (MODE == MODE_COUNT) {
                     cnt += hit ? 1u : 0u;
                 } else {
+                    hit = hit && !(P.self && e.tpk == zero_pk);   // the excluded self-image (i, i, 0)
                     const uint64_t m = ballot(hit) & seg;
                     if (hit) write_edge(base + run + mbcnt(m), out, sa, da, P, e.tpk, l2);
                     run += (uint32_t)__popcll(m);
                 }
             };
-            for_images(tab, I, zimg, lane, step);
+            for_images(tab, I, step);
             if (MODE == MODE_COUNT) {
+                // the self pair at t = 0 has length exactly 0: it was counted iff 0 < c2
+                if (P.self && 0.0f < c2) cnt -= 1u;
                 const int inc = wave_incl_scan_i32(act ? (int)cnt : 0);
                 const int end = min((lane + 1) * n - 1, WAVE - 1);
                 const int beg = lane * n - 1;
@@ -205,7 +217,7 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
             // ---- one source per item, SLOTS destinations per lane, chunks of 64*SLOTS
             const int il = i_first;
             const float c2 = thr ? thr[atom0 + il] : c2thr;
-            uint32_t cnt = 0;
+            uint32_t cnt = 0;   // wave-uniform in this path
             uint32_t run = 0;
             OutRel out{};
             if (MODE == MODE_FILL) out = rebase(offsets[atom0 + il], capacity, src, dst, image, length);
@@ -217,15 +229,15 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
                     const int j = jc + r * WAVE + lane;
                     P[r] = make_pair(frac, L, atom0, il, j, j < n);
                 }
-                auto step = [&](const ImageEntry& e, bool zero) {
+                auto step = [&](const ImageEntry& e) {
 #pragma unroll
                     for (int r = 0; r < SLOTS; ++r) {
                         const float l2 = dist2(P[r], e);
                         bool hit = l2 < c2;
-                        if (zero) hit = hit && !P[r].self;
                         if (MODE == MODE_COUNT) {
-                            cnt += hit ? 1u : 0u;
+                            cnt += (uint32_t)__popcll(ballot(hit));
                         } else {
+                            hit = hit && !(P[r].self && e.tpk == zero_pk);
                             const uint64_t m = ballot(hit);
                             if (hit)
                                 write_edge(run + mbcnt(m), out, sa, (int32_t)(atom0 + jc + r * WAVE + lane), P[r],
@@ -234,11 +246,12 @@ __global__ __launch_bounds__(256) void k_cutoff_sweep(
                         }
                     }
                 };
-                for_images(tab, I, zimg, lane, step);
+                for_images(tab, I, step);
             }
             if (MODE == MODE_COUNT) {
-                const int tot = wave_incl_scan_i32((int)cnt);
-                if (lane == WAVE - 1) counts[atom0 + il] = (uint32_t)tot;
+                // the self pair at t = 0 (length exactly 0) was counted iff 0 < c2
+                if (0.0f < c2) cnt -= 1u;
+                if (lane == 0) counts[atom0 + il] = cnt;
             }
         }
     }
