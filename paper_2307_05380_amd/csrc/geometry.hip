@@ -105,19 +105,22 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_
 // Global atomics on MI355X are resolved far from the compute units and cost
 // far more than LDS traffic, so the backward pass is organised so that almost
 // no per-edge value reaches global memory through an atomic:
-// - a plan pass checks that the edges are grouped by structure (both
-//   endpoints in the structure, structures in ascending order: what the
-//   graph builders emit) and records every structure's edge range;
+// - the edges are expected grouped by structure with non-decreasing src (what
+//   the graph builders emit); every structure's edge range is found by a
+//   search of src for the structure's first atom (no pass over the edges);
 // - one workgroup per item (a structure, or a chunk of BW_CHUNK edges of a
 //   large one) accumulates the coordinate gradients of the structure's atoms
 //   in LDS and the lattice gradient in registers, then writes them with plain
 //   stores when the item covers the whole structure (atomics only for split
-//   structures). A wave whose 64 edges share the source (edges grouped by
-//   source) keeps the source's sum in registers until the run ends.
-// - Structures with more than BW_WIN atoms, and edges in any other order, take
-//   a general kernel: runs of equal dst / src / structure are merged inside the
-//   wave by a segmented scan, and the run's last lane adds the total with a
-//   global atomic.
+//   structures). A wave whose 64 edges share the source keeps the source's sum
+//   in registers until the run ends. The item kernels check what the grouping
+//   promises (both endpoints in the item's structure, src non-decreasing
+//   inside every 64-edge step) and raise a flag otherwise;
+// - structures with more than BW_WIN atoms take a general kernel: runs of equal
+//   dst / src / structure are merged inside the wave by a segmented scan and the
+//   run's last lane adds the total with a global atomic. When the flag is
+//   raised, whatever the item kernels wrote is cleared and the general kernel
+//   takes every edge in chunks of BW_CHUNK, whatever their order.
 // Both kernels are launched; each leaves the items of the other at once.
 constexpr int BW_CHUNK = 16384;   // edges per item
 constexpr int BW_WIN = 512;       // atoms of a structure held in LDS
@@ -149,78 +152,57 @@ __device__ __forceinline__ T seg_scan(T v, int rs, int lane) {
     return v;
 }
 
-// Plan of the grouped path: the edges must come with non-decreasing src (what
-// the graph builders emit: grouped by source, sources in atom order, hence by
-// structure). One streaming pass over src records every structure's edge range
-// start[s] .. start[s+1] (atom_struct is read only where src changes) and sets
-// flag bit 0 if src decreases or leaves [0, N). A dst outside its source's
-// structure is found later by the item kernels (flag bit 1).
-__global__ __launch_bounds__(256) void k_geom_plan(const int32_t* __restrict__ src,
-                                                   const int32_t* __restrict__ atom_struct, int64_t N, int B,
-                                                   int64_t E, const int64_t* __restrict__ num_edges,
-                                                   int64_t* __restrict__ start, int32_t* __restrict__ flag) {
+// Edge ranges of the grouped order: start[s] = first edge whose src is at
+// least the structure's first atom (start[0] = 0, start[B] = E). One wave per
+// structure boundary: a 65-ary search, each step probing 64 positions at once
+// (five dependent steps for 50M edges). On edges that are not grouped the
+// result is still a set of indices in [0, E]; the item kernels then find edges
+// outside their structure and raise the flag.
+__global__ __launch_bounds__(256) void k_geom_ranges(const int32_t* __restrict__ src,
+                                                     const int64_t* __restrict__ batch_ptr, int B, int64_t E,
+                                                     const int64_t* __restrict__ num_edges,
+                                                     int64_t* __restrict__ start) {
     const int64_t Ee = edge_count(E, num_edges);
     const int lane = lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (Ee == 0) {
-        for (int64_t q = t0; q <= B; q += stride) start[q] = 0;
+    const int q = (int)(blockIdx.x * (blockDim.x / WAVE)) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    if (q > B) return;
+    if (q == 0 || q == B || Ee == 0) {
+        if (lane == 0) start[q] = q == B ? Ee : 0;
         return;
     }
-    bool bad = false;
-    // whole waves step together so that lane - 1 holds edge e - 1; four
-    // wave-rows of edges per step, their loads issued together
-    constexpr int U = 4;
-    const int64_t wstride = stride * U;
-    const int64_t span = (Ee + WAVE - 1) / WAVE * WAVE;
-    const int64_t wbase = (t0 - lane) * U;            // this wave's first edge of the step
-    for (int64_t b0 = wbase; b0 < span; b0 += wstride) {
-        int32_t iv[U], ipv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t e = b0 + u * WAVE + lane;
-            const int32_t v = src[min(e, Ee - 1)];               // clamped: no branch around the load
-            const int32_t vp = src[min(max(e - 1, (int64_t)0), Ee - 1)];
-            iv[u] = e < Ee ? v : INT32_MAX;
-            ipv[u] = (e > 0 && e <= Ee) ? vp : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t e = b0 + u * WAVE + lane;
-            const int32_t i = iv[u];
-            int32_t ip = __shfl_up(i, 1, WAVE);
-            if (lane == 0) ip = ipv[u];
-            if (e >= Ee) continue;
-            if (i < 0 || i >= N || i < ip) {
-                bad = true;
-                continue;
-            }
-            if (e == 0 || i != ip) {
-                const int32_t sc = atom_struct[i];
-                const int32_t sp = (e == 0 || ip < 0) ? -1 : atom_struct[ip];
-                for (int32_t q = sp + 1; q <= sc; ++q) start[q] = e;
-            }
-            if (e == Ee - 1) {
-                for (int32_t q = atom_struct[i] + 1; q <= B; ++q) start[q] = Ee;
-            }
-        }
+    const int64_t target = batch_ptr[q];
+    int64_t lo = 0, hi = Ee;   // the answer lies in [lo, hi]
+    while (hi - lo > WAVE) {
+        const int64_t span = hi - lo;
+        const int64_t p = lo + (span * (lane + 1)) / (WAVE + 1);   // strictly increasing, in [lo, hi)
+        const uint64_t below = ballot((int64_t)src[p] < target);
+        const int c = __popcll(below);                            // probes below the target
+        const int64_t plo = lo + (span * c) / (WAVE + 1);         // probe c - 1, or lo when c = 0
+        const int64_t phi = lo + (span * (c + 1)) / (WAVE + 1);   // probe c, or hi when c = 64
+        lo = c == 0 ? lo : plo + 1;
+        hi = c == WAVE ? hi : phi;
     }
-    if (ballot(bad) != 0 && lane == 0) atomicOr(flag, 1);
+    const int64_t p = lo + lane;
+    const uint64_t below = ballot(p < hi && (int64_t)src[min(p, Ee - 1)] < target);
+    if (lane == 0) start[q] = lo + __popcll(below);
 }
 
 // Items: item_off[s] = number of items of structures < s (one item per
 // BW_CHUNK edges, at least one per structure); item_off[B] = total.
 __global__ __launch_bounds__(1024) void k_bwd_items(const int64_t* __restrict__ start, int B,
-                                                    int64_t* __restrict__ item_off) {
+                                                    int64_t* __restrict__ item_off, int32_t* __restrict__ flag) {
     __shared__ int64_t sh[1024];
     const int t = threadIdx.x;
     const int per = (B + 1023) / 1024;
     const int s0 = min(B, t * per), s1 = min(B, s0 + per);
     int64_t sum = 0;
+    bool bad = false;   // ranges that are not ordered (edges not grouped)
     for (int q = s0; q < s1; ++q) {
         const int64_t n = start[q + 1] - start[q];
+        bad |= n < 0;
         sum += n > BW_CHUNK ? (n + BW_CHUNK - 1) / BW_CHUNK : 1;
     }
+    if (bad) atomicOr(flag, 1);
     sh[t] = sum;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
@@ -260,7 +242,7 @@ __device__ __forceinline__ bool bwd_item(int64_t item, int B, const int64_t* __r
     it.st = lo;
     const int64_t k = item - item_off[lo];
     it.c0 = start[lo] + k * BW_CHUNK;
-    it.c1 = min(start[lo + 1], it.c0 + BW_CHUNK);
+    it.c1 = max(it.c0, min(start[lo + 1], it.c0 + BW_CHUNK));
     it.whole = item_off[lo + 1] - item_off[lo] == 1;
     it.atom0 = batch_ptr[lo];
     it.n = (int)(batch_ptr[lo + 1] - it.atom0);
@@ -292,7 +274,8 @@ __device__ __forceinline__ double block_lattice(const double (&la)[9], double (&
 // summed at the end and written with plain stores when the item is the whole
 // structure. Each wave walks a contiguous quarter of the item, four groups of
 // 64 edges per step with all their loads issued first. A dst outside the
-// structure sets flag bit 1 (the results are then cleared and recomputed by
+// structure sets flag bit 1, a src outside it or a src smaller than the
+// previous lane's sets bit 0 (the results are then cleared and recomputed by
 // the general kernel).
 template <bool GV, bool GL, int WIN>
 __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ lattices,
@@ -339,7 +322,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
     double la[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) la[q] = 0.0;
-    bool bad = false;
+    bool bad = false, unsorted = false;
     auto add_src_run = [&]() {   // lane 0 adds the wave's source run
         if (src_cur >= 0) {
             const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
@@ -352,7 +335,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
         }
         sa0 = sa1 = sa2 = 0.f;
     };
-    constexpr int U = 4;
+    constexpr int U = 2;
     for (int64_t b0 = w0; b0 < w1; b0 += WAVE * U) {
         int ai[U], aj[U], at[U][3];
         float ag[U][3], al[U];
@@ -376,10 +359,14 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
             const int64_t base = b0 + u * WAVE;
             if (base >= w1) break;                       // uniform
             const bool inr = base + lane < w1;
+            const bool oki = (unsigned)ai[u] < (unsigned)n;
             const bool okj = (unsigned)aj[u] < (unsigned)n;
             bad |= inr && !okj;
-            const bool act = inr && okj;
-            const int li = ai[u], lj = okj ? aj[u] : 0;
+            const bool act = inr && okj && oki;
+            const int li = oki ? ai[u] : 0, lj = okj ? aj[u] : 0;
+            // the grouping: src inside the structure and non-decreasing over the step
+            const int lprev = __shfl_up(li, 1, WAVE);
+            unsorted |= inr && (!oki || (lane > 0 && li < lprev));
             const double f0 = (double)xs[3 * lj] - (double)xs[3 * li] + (double)at[u][0];
             const double f1 = (double)xs[3 * lj + 1] - (double)xs[3 * li + 1] + (double)at[u][1];
             const double f2 = (double)xs[3 * lj + 2] - (double)xs[3 * li + 2] + (double)at[u][2];
@@ -454,6 +441,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
     }
     if (gf) add_src_run();
     if (ballot(bad) != 0 && lane == 0) atomicOr(flag, 2);
+    if (ballot(unsorted) != 0 && lane == 0) atomicOr(flag, 1);
     const double lt = block_lattice(la, red, tid);   // also orders the LDS updates before the reads below
     if (acc && tid < 9) {
         if (it.whole) acc[9 * (int64_t)it.st + tid] = lt;
@@ -469,12 +457,12 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
     }
 }
 
-// After the grouped kernels: if one of them found a dst outside its structure
-// (flag bit 1), clear what they wrote so that the general kernel, which then
-// takes every edge, starts from zero.
+// After the grouped kernels: if the edges turned out not to be grouped (flag
+// set), clear what they wrote so that the general kernel, which then takes
+// every edge, starts from zero.
 __global__ __launch_bounds__(256) void k_bwd_fix(const int32_t* __restrict__ flag, float* __restrict__ grad_frac,
                                                  int64_t n3, double* __restrict__ acc, int64_t n9) {
-    if ((*flag & 2) == 0) return;
+    if (*flag == 0) return;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n3 + n9; q += stride) {
         if (q < n3) {
@@ -487,7 +475,9 @@ __global__ __launch_bounds__(256) void k_bwd_fix(const int32_t* __restrict__ fla
 
 // General kernel: grouped order with structures of more than BW_WIN atoms
 // (one workgroup per item), or any other order (one workgroup per BW_CHUNK
-// edges). Per-edge math in FP64; merged runs go to global atomics.
+// edges). Per-edge math in FP64; merged runs go to global atomics, and every
+// edge's lattice term goes to the structure of its own source, so the result
+// does not depend on the item's range being exact.
 __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ lattices,
                                                       const float* __restrict__ frac,
                                                       const int32_t* __restrict__ atom_struct,
@@ -503,7 +493,6 @@ __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ 
                                                       const int32_t* __restrict__ flag,
                                                       float* __restrict__ grad_frac,
                                                       double* __restrict__ acc) {
-    __shared__ double red[4][9];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const bool grouped = *flag == 0;
     int64_t c0, c1;
@@ -524,7 +513,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ 
     const int64_t w0 = c0 + wv * qlen, w1 = min(c1, w0 + qlen);
     int32_t src_cur = -1;   // wave's current source run (uniform), -1: none
     float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f;
-    int32_t st_cur = it.st; // wave's current structure run, -1: none
+    int32_t st_cur = -1;    // wave's current structure run, -1: none
     double la[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) la[q] = 0.0;
@@ -564,7 +553,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ 
             if (!act) i = j = -1;
         }
         if (act) {
-            s = grouped ? it.st : atom_struct[i];
+            s = atom_struct[i];   // per edge: correct whatever the order
             const float* L = lattices + 9 * (int64_t)s;
             f0 = (double)frac[3 * (int64_t)j] - (double)frac[3 * (int64_t)i] + (double)image[3 * e];
             f1 = (double)frac[3 * (int64_t)j + 1] - (double)frac[3 * (int64_t)i + 1] + (double)image[3 * e + 1];
@@ -615,7 +604,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ 
             }
         }
         if (acc) {
-            if (!grouped) {
+            {
                 const uint64_t am = ballot(act);
                 const int fl = am ? __builtin_ctzll(am) : 0;
                 const int32_t su = am ? __builtin_amdgcn_readlane(s, fl) : -1;
@@ -645,15 +634,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ 
         }
     }
     if (grad_frac) flush_src();
-    if (!grouped) {
-        if (acc) flush_lat();
-        return;
-    }
-    const double lt = block_lattice(la, red, tid);
-    if (acc && tid < 9) {
-        if (it.whole) acc[9 * (int64_t)it.st + tid] = lt;
-        else unsafeAtomicAdd(&acc[9 * (int64_t)it.st + tid], lt);
-    }
+    if (acc) flush_lat();
 }
 
 __global__ __launch_bounds__(256) void k_finalize_lattice(const double* __restrict__ acc, int64_t n,
@@ -669,13 +650,13 @@ static int grid_for(int64_t work, int per_block, int cap) {
     return (int)g;
 }
 
-// Plan shared by both passes: flag cleared, edge ranges, items.
-static void launch_plan(const int32_t* src, const int32_t* atom_struct, int B, int64_t N, int64_t E,
-                        const int64_t* num_edges, const GeomBwdWs& w, int cu, hipStream_t s) {
+// Plan of the grouped path: flag cleared, edge ranges, items.
+static void launch_plan(const int32_t* src, const int64_t* batch_ptr, int B, int64_t E, const int64_t* num_edges,
+                        const GeomBwdWs& w, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, w.flag, 1);
-    hipLaunchKernelGGL(k_geom_plan, dim3(grid_for(E, 256 * 4, cu * 16)), dim3(256), 0, s, src, atom_struct, N, B, E,
-                       num_edges, w.start, w.flag);
-    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, B, w.item_off);
+    hipLaunchKernelGGL(k_geom_ranges, dim3((unsigned)((B + 1 + 3) / 4)), dim3(256), 0, s, src, batch_ptr, B, E,
+                       num_edges, w.start);
+    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, B, w.item_off, w.flag);
 }
 
 // Enough workgroups for either order: sum_s max(1, ceil(E_s / chunk)) <= B + ceil(E / chunk).
@@ -706,7 +687,7 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
         hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(9 * (int64_t)B, 256, cu * 4)), dim3(256), 0, s, w.acc,
                            9 * (int64_t)B);
     if (E > 0 && B > 0 && (grad_frac || grad_lattice) && (grad_vec || grad_length)) {
-        launch_plan(src, atom_struct, B, N, E, num_edges, w, cu, s);
+        launch_plan(src, batch_ptr, B, E, num_edges, w, s);
         const unsigned grid = item_grid(B, E);
         double* acc = grad_lattice ? w.acc : nullptr;
         // two LDS sizes: structures of up to 128 atoms (most), and 129..BW_WIN atoms

@@ -102,6 +102,36 @@ def test_backward_random_edge_order():
     assert _rel_err(gL.cpu().numpy(), rL) <= 1e-4
 
 
+@pytest.mark.parametrize("order", ["structures_reversed", "shuffled_in_structure", "reversed_in_structure"])
+def test_backward_partial_orders(order):
+    """Edge orders that are grouped in some ways but not others: structure
+    blocks in reverse order (each sorted by source), each structure's edges
+    shuffled, or each structure's edges reversed. The result must not depend
+    on the order."""
+    rng = np.random.default_rng(81)
+    b = inputs.random_batch(rng, 12, 3, 60, 3.0, 8.0, cutoff=5.0)
+    g, (s, d, t, ln) = _edges(b)
+    blocks = [np.flatnonzero((s >= b.batch_ptr[q]) & (s < b.batch_ptr[q + 1])) for q in range(b.B)]
+    if order == "structures_reversed":
+        perm = np.concatenate(blocks[::-1])
+    elif order == "shuffled_in_structure":
+        perm = np.concatenate([rng.permutation(x) for x in blocks])
+    else:
+        perm = np.concatenate([x[::-1] for x in blocks])
+    assert len(perm) == len(s)
+    s, d, t = s[perm], d[perm], t[perm]
+    gv = rng.normal(size=(len(s), 3)).astype(np.float32)
+    glen = rng.normal(size=len(s)).astype(np.float32)
+    L, X, P = gu.dev(b)
+    run = graph.GeometryRunner(b.B, b.N)
+    gf = torch.empty_like(X)
+    gL = torch.empty_like(L)
+    ti = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.int32))).cuda()
+    run.backward(L, X, P, ti(s), ti(d), ti(t), torch.from_numpy(gv).cuda(), torch.from_numpy(glen).cuda(), gf, gL)
+    rf, rL = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, gv, glen)
+    _per_structure_check(b, gf.cpu().numpy(), gL.cpu().numpy(), rf, rL)
+
+
 def _per_structure_check(b, gf, gL, rf, rL, tol=1e-4):
     worst_f = worst_L = 0.0
     for q in range(b.B):
