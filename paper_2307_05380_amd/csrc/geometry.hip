@@ -249,18 +249,6 @@ __device__ __forceinline__ bool bwd_item(int64_t item, int B, const int64_t* __r
     return true;
 }
 
-// Block reduction of the per-lane lattice sums; thread q < 9 gets entry q.
-__device__ __forceinline__ double block_lattice(const double (&la)[9], double (&red)[4][9], int tid) {
-    const int lane = tid & 63, wv = tid >> 6;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const double t = wave_sum_f64(la[q]);
-        if (lane == 0) red[wv][q] = t;
-    }
-    __syncthreads();
-    return tid < 9 ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
-}
-
 // Backward pass of the grouped path, structures of at most WIN atoms. The
 // structure's coordinates are staged in LDS; every wave accumulates the
 // coordinate gradients of its edges in a private LDS copy with plain
@@ -270,32 +258,28 @@ __device__ __forceinline__ double block_lattice(const double (&la)[9], double (&
 // for a later round (each round every contended atom has one owner, the last
 // lane that wrote its tag). Runs of one source are summed in registers (the
 // edges are ordered by source), or by a segmented scan when a step mixes
-// sources. The lattice gradient stays in FP64 registers. The four copies are
-// summed at the end and written with plain stores when the item is the whole
-// structure. Each wave walks a contiguous quarter of the item, four groups of
-// 64 edges per step with all their loads issued first. A dst outside the
-// structure sets flag bit 1, a src outside it or a src smaller than the
-// previous lane's sets bit 0 (the results are then cleared and recomputed by
-// the general kernel).
+// sources. The length term is evaluated with the metric tensor G = L L^T of
+// the structure: |v|^2 = f G f^T, g L^T = c G f^T and f^T g = c f^T f L, so
+// no per-edge v is formed and the lattice gradient of the length term is the
+// FP64 register sum M = sum c f^T f, multiplied by L once per item. The four
+// copies are summed at the end and written with plain stores when the item is
+// the whole structure. Each wave walks a contiguous quarter of the item, two
+// groups of 64 edges per step with all their loads issued first. A dst outside
+// the structure sets flag bit 1, a src outside it (or, where a step mixes
+// sources, a src smaller than the previous lane's) sets bit 0 (the results are
+// then cleared and recomputed by the general kernel).
 template <bool GV, bool GL, int WIN>
-__global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ lattices,
-                                                      const float* __restrict__ frac,
-                                                      const int64_t* __restrict__ batch_ptr, int B,
-                                                      const int32_t* __restrict__ src,
-                                                      const int32_t* __restrict__ dst,
-                                                      const int32_t* __restrict__ image,
-                                                      const float* __restrict__ gvec,
-                                                      const float* __restrict__ glen,
-                                                      const int64_t* __restrict__ start,
-                                                      const int64_t* __restrict__ item_off,
-                                                      int32_t* __restrict__ flag,
-                                                      float* __restrict__ grad_frac,
-                                                      double* __restrict__ acc,
-                                                      int n_lo) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict__ frac,
+                    const int64_t* __restrict__ batch_ptr, int B, const int32_t* __restrict__ src,
+                    const int32_t* __restrict__ dst, const int32_t* __restrict__ image,
+                    const float* __restrict__ gvec, const float* __restrict__ glen,
+                    const int64_t* __restrict__ start, const int64_t* __restrict__ item_off,
+                    int32_t* __restrict__ flag, float* __restrict__ grad_frac, double* __restrict__ acc, int n_lo) {
     __shared__ float xs[WIN * 3];
     __shared__ float wacc[4][WIN * 3];
     __shared__ int tag[4][WIN];
-    __shared__ double red[4][9];
+    __shared__ double red[4][15];
     if (*flag != 0) return;
     BwdItem it;
     if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it) || it.n > WIN || it.n <= n_lo) return;
@@ -313,22 +297,46 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
     float Lf[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) Lf[q] = Lp[q];
+    // metric tensor G = L L^T (rows of L are the lattice vectors), wave-uniform
+    double Gm[6];
+    {
+        const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double g = (double)Lf[3 * ia[q]] * Lf[3 * ib[q]] + (double)Lf[3 * ia[q] + 1] * Lf[3 * ib[q] + 1] +
+                             (double)Lf[3 * ia[q] + 2] * Lf[3 * ib[q] + 2];
+            const int64_t bits = __double_as_longlong(g);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)bits);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)bits >> 32));
+            Gm[q] = __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+        }
+    }
     const int32_t a0 = (int32_t)it.atom0;
-    // this wave's contiguous quarter of the item
+    // this wave's contiguous quarter of the item, as offsets from the item's first edge
     const int64_t qlen = ((it.c1 - it.c0 + 3) / 4 + WAVE - 1) / WAVE * WAVE;
     const int64_t w0 = it.c0 + wv * qlen, w1 = min(it.c1, w0 + qlen);
+    const int32_t* srcb = src + it.c0;
+    const int32_t* dstb = dst + it.c0;
+    const int32_t* imgb = image + 3 * it.c0;
+    const float* gvb = GV ? gvec + 3 * it.c0 : nullptr;
+    const float* glb = GL ? glen + it.c0 : nullptr;
+    const int r1 = (int)(w1 - it.c0);   // end of this wave's range
     int src_cur = -1;   // wave's current source run (local index), -1: none
     float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f;
-    double la[9];
+    // lattice gradient: sum f (x) g_v (upstream vector gradient) and the
+    // symmetric M = sum c f f^T of the length term (its part is M L)
+    double lv[9], M[6];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) la[q] = 0.0;
+    for (int q = 0; q < 9; ++q) lv[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) M[q] = 0.0;
     bool bad = false, unsorted = false;
     auto add_src_run = [&]() {   // lane 0 adds the wave's source run
         if (src_cur >= 0) {
-            const float r0 = wave_sum_f32(sa0), r1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
+            const float r0 = wave_sum_f32(sa0), rr1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
             if (lane == 0) {
                 my[3 * src_cur] -= r0;
-                my[3 * src_cur + 1] -= r1;
+                my[3 * src_cur + 1] -= rr1;
                 my[3 * src_cur + 2] -= r2;
             }
             wave_lds_sync();
@@ -336,59 +344,79 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
         sa0 = sa1 = sa2 = 0.f;
     };
     constexpr int U = 2;
-    for (int64_t b0 = w0; b0 < w1; b0 += WAVE * U) {
+    for (int rb = (int)(w0 - it.c0); rb < r1; rb += WAVE * U) {
         int ai[U], aj[U], at[U][3];
         float ag[U][3], al[U];
-        // loads without branches (the index is clamped into the range; lanes past
-        // the end are masked later), so all U groups stay in flight together
+        // loads without branches (the offset is clamped into the range; lanes past
+        // the end are masked later), so all U groups stay in flight together;
+        // 32-bit byte offsets from the item's (scalar) bases
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t e = min(b0 + u * WAVE + lane, w1 - 1);
-            ai[u] = src[e] - a0;
-            aj[u] = dst[e] - a0;
-            at[u][0] = image[3 * e];
-            at[u][1] = image[3 * e + 1];
-            at[u][2] = image[3 * e + 2];
-            ag[u][0] = GV ? gvec[3 * e] : 0.0f;
-            ag[u][1] = GV ? gvec[3 * e + 1] : 0.0f;
-            ag[u][2] = GV ? gvec[3 * e + 2] : 0.0f;
-            al[u] = GL ? glen[e] : 0.0f;
+            const uint32_t r = (uint32_t)min(rb + u * WAVE + lane, r1 - 1);
+            const uint32_t o4 = r * 4u, o12 = r * 12u;
+            ai[u] = *(const int32_t*)((const char*)srcb + o4) - a0;
+            aj[u] = *(const int32_t*)((const char*)dstb + o4) - a0;
+            const int32_t* ip = (const int32_t*)((const char*)imgb + o12);
+            at[u][0] = ip[0];
+            at[u][1] = ip[1];
+            at[u][2] = ip[2];
+            if (GV) {
+                const float* gp = (const float*)((const char*)gvb + o12);
+                ag[u][0] = gp[0];
+                ag[u][1] = gp[1];
+                ag[u][2] = gp[2];
+            } else {
+                ag[u][0] = ag[u][1] = ag[u][2] = 0.0f;
+            }
+            al[u] = GL ? *(const float*)((const char*)glb + o4) : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t base = b0 + u * WAVE;
-            if (base >= w1) break;                       // uniform
-            const bool inr = base + lane < w1;
+            const int base = rb + u * WAVE;
+            if (base >= r1) break;                       // uniform
+            const bool inr = base + lane < r1;
             const bool oki = (unsigned)ai[u] < (unsigned)n;
             const bool okj = (unsigned)aj[u] < (unsigned)n;
             bad |= inr && !okj;
+            unsorted |= inr && !oki;                     // src outside the item's structure
             const bool act = inr && okj && oki;
             const int li = oki ? ai[u] : 0, lj = okj ? aj[u] : 0;
-            // the grouping: src inside the structure and non-decreasing over the step
-            const int lprev = __shfl_up(li, 1, WAVE);
-            unsorted |= inr && (!oki || (lane > 0 && li < lprev));
             const double f0 = (double)xs[3 * lj] - (double)xs[3 * li] + (double)at[u][0];
             const double f1 = (double)xs[3 * lj + 1] - (double)xs[3 * li + 1] + (double)at[u][1];
             const double f2 = (double)xs[3 * lj + 2] - (double)xs[3 * li + 2] + (double)at[u][2];
-            float g0 = ag[u][0], g1 = ag[u][1], g2 = ag[u][2];
+            float x0 = 0.f, x1 = 0.f, x2 = 0.f;
             if (GL) {
-                // v in FP64 (large image offsets), the length term in FP32
-                const double v0 = f0 * (double)Lf[0] + f1 * (double)Lf[3] + f2 * (double)Lf[6];
-                const double v1 = f0 * (double)Lf[1] + f1 * (double)Lf[4] + f2 * (double)Lf[7];
-                const double v2 = f0 * (double)Lf[2] + f1 * (double)Lf[5] + f2 * (double)Lf[8];
-                const float l2 = (float)(v0 * v0 + v1 * v1 + v2 * v2);
-                const float c = l2 > 0.0f ? al[u] * __frsqrt_rn(l2) : 0.0f;
-                g0 += c * (float)v0;
-                g1 += c * (float)v1;
-                g2 += c * (float)v2;
+                // v = f L, |v|^2 = f G f^T and g = c v with c = g_l / |v|; then
+                // g L^T = c (G f) and f (x) g = c f f^T L: no per-edge v
+                const double h0 = Gm[0] * f0 + Gm[1] * f1 + Gm[2] * f2;
+                const double h1 = Gm[1] * f0 + Gm[3] * f1 + Gm[4] * f2;
+                const double h2 = Gm[2] * f0 + Gm[4] * f1 + Gm[5] * f2;
+                const float l2 = (float)(f0 * h0 + f1 * h1 + f2 * h2);
+                float c = l2 > 0.0f ? al[u] * __frsqrt_rn(l2) : 0.0f;
+                c = act ? c : 0.0f;
+                x0 = c * (float)h0;
+                x1 = c * (float)h1;
+                x2 = c * (float)h2;
+                if (acc) {
+                    const double cd = c;
+                    const double c0 = cd * f0, c1 = cd * f1, c2 = cd * f2;
+                    M[0] += c0 * f0; M[1] += c0 * f1; M[2] += c0 * f2;
+                    M[3] += c1 * f1; M[4] += c1 * f2; M[5] += c2 * f2;
+                }
             }
-            g0 = act ? g0 : 0.0f;
-            g1 = act ? g1 : 0.0f;
-            g2 = act ? g2 : 0.0f;
-            // g L^T: component k is g . (row k of L)
-            const float x0 = g0 * Lf[0] + g1 * Lf[1] + g2 * Lf[2];
-            const float x1 = g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
-            const float x2 = g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
+            if (GV) {
+                const float g0 = act ? ag[u][0] : 0.0f, g1 = act ? ag[u][1] : 0.0f, g2 = act ? ag[u][2] : 0.0f;
+                // g L^T: component k is g . (row k of L)
+                x0 += g0 * Lf[0] + g1 * Lf[1] + g2 * Lf[2];
+                x1 += g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
+                x2 += g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
+                if (acc) {
+                    const double d0 = g0, d1 = g1, d2 = g2;
+                    lv[0] += f0 * d0; lv[1] += f0 * d1; lv[2] += f0 * d2;
+                    lv[3] += f1 * d0; lv[4] += f1 * d1; lv[5] += f1 * d2;
+                    lv[6] += f2 * d0; lv[7] += f2 * d1; lv[8] += f2 * d2;
+                }
+            }
             if (gf) {
                 // destination side: rounds of owner lanes (bounded: every round
                 // retires at least the owner of each contended atom)
@@ -417,9 +445,12 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
                     sa1 += x1;
                     sa2 += x2;
                 } else {
-                    // mixed sources: sources are sorted, so each one is a run of lanes
+                    // mixed sources: with src non-decreasing over the lanes each
+                    // source is one run (checked here: the merge needs it)
                     const int key = act ? li : -1 - lane;   // inactive lanes are runs of their own
-                    const uint64_t heads = run_heads(key, lane);
+                    const int kprev = __shfl_up(key, 1, WAVE);
+                    unsorted |= act && lane > 0 && kprev >= 0 && li < kprev;
+                    const uint64_t heads = ballot(lane == 0 || kprev != key);
                     const int rs = run_start(heads, lane);
                     const float y0 = seg_scan(x0, rs, lane), y1 = seg_scan(x1, rs, lane),
                                 y2 = seg_scan(x2, rs, lane);
@@ -431,19 +462,29 @@ __global__ __launch_bounds__(256) void k_geom_bwd_lds(const float* __restrict__ 
                     wave_lds_sync();
                 }
             }
-            if (acc) {
-                const double h0 = g0, h1 = g1, h2 = g2;   // zero for inactive lanes
-                la[0] += f0 * h0; la[1] += f0 * h1; la[2] += f0 * h2;
-                la[3] += f1 * h0; la[4] += f1 * h1; la[5] += f1 * h2;
-                la[6] += f2 * h0; la[7] += f2 * h1; la[8] += f2 * h2;
-            }
         }
     }
     if (gf) add_src_run();
     if (ballot(bad) != 0 && lane == 0) atomicOr(flag, 2);
     if (ballot(unsorted) != 0 && lane == 0) atomicOr(flag, 1);
-    const double lt = block_lattice(la, red, tid);   // also orders the LDS updates before the reads below
+    // block sums of lv and M (also orders the LDS updates before the reads below)
+#pragma unroll
+    for (int q = 0; q < 15; ++q) {
+        const double t = wave_sum_f64(q < 9 ? lv[q] : M[q - 9]);
+        if (lane == 0) red[wv][q] = t;
+    }
+    __syncthreads();
     if (acc && tid < 9) {
+        const int ra = tid / 3, k = tid - 3 * (tid / 3);
+        auto tot = [&](int q) { return (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]); };
+        // (M L)[a][k] = sum_b M[a][b] L[b][k], M stored as 00 01 02 11 12 22
+        auto msym = [](int x, int y) {   // storage index of M[x][y]
+            const int p = x < y ? x : y, q = x < y ? y : x;
+            return 3 * p - (p * (p - 1)) / 2 + (q - p);
+        };
+        double lt = tot(tid);
+#pragma unroll
+        for (int bq = 0; bq < 3; ++bq) lt += tot(9 + msym(ra, bq)) * (double)Lp[3 * bq + k];
         if (it.whole) acc[9 * (int64_t)it.st + tid] = lt;
         else unsafeAtomicAdd(&acc[9 * (int64_t)it.st + tid], lt);
     }
