@@ -23,11 +23,14 @@ __device__ inline int64_t edge_count(int64_t E, const int64_t* __restrict__ num_
 
 }  // namespace
 
-// Forward pass: grid-stride over edges, four edges per thread per step with
-// every streamed load (src, dst, image) issued before the gathers that depend
-// on them (the source's structure, its lattice, both coordinates) and no
-// branch between a load and its use (indices are clamped; an edge with an
-// endpoint outside [0, N) gets NaN). FP64 arithmetic, FP32 results.
+// Forward pass: four edges per thread with every streamed load (src, dst,
+// image) issued before the gathers that depend on them (the source's
+// structure, its lattice, both coordinates) and no branch between a load and
+// its use (indices are clamped; an edge with an endpoint outside [0, N) gets
+// NaN). When a wave's 64 edges share one structure (almost always: the
+// builders emit edges grouped by structure) its lattice comes through scalar
+// loads. One thread per four edges (no grid cap): the plain streaming shape is
+// the fastest here. FP64 arithmetic, FP32 results.
 __global__ __launch_bounds__(256) void k_geom_fwd(const float* __restrict__ lattices,
                                                   const float* __restrict__ frac,
                                                   const int32_t* __restrict__ atom_struct, int64_t N,
@@ -63,16 +66,25 @@ __global__ __launch_bounds__(256) void k_geom_fwd(const float* __restrict__ latt
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = e0 + u * stride;
-            const float* L = lattices + 9 * (int64_t)st[u];
             const float* xi = frac + 3 * (int64_t)ic[u];
             const float* xj = frac + 3 * (int64_t)jc[u];
             const double f0 = (double)xj[0] - (double)xi[0] + (double)t[u][0];
             const double f1 = (double)xj[1] - (double)xi[1] + (double)t[u][1];
             const double f2 = (double)xj[2] - (double)xi[2] + (double)t[u][2];
             const double nan = __builtin_nan("");
-            const double v0 = ok[u] ? f0 * (double)L[0] + f1 * (double)L[3] + f2 * (double)L[6] : nan;
-            const double v1 = ok[u] ? f0 * (double)L[1] + f1 * (double)L[4] + f2 * (double)L[7] : nan;
-            const double v2 = ok[u] ? f0 * (double)L[2] + f1 * (double)L[5] + f2 * (double)L[8] : nan;
+            const int su = __builtin_amdgcn_readfirstlane(st[u]);
+            double v0, v1, v2;
+            if (ballot(st[u] != su) == 0) {
+                const float* L = lattices + 9 * (int64_t)su;   // one structure: scalar loads
+                v0 = ok[u] ? f0 * (double)L[0] + f1 * (double)L[3] + f2 * (double)L[6] : nan;
+                v1 = ok[u] ? f0 * (double)L[1] + f1 * (double)L[4] + f2 * (double)L[7] : nan;
+                v2 = ok[u] ? f0 * (double)L[2] + f1 * (double)L[5] + f2 * (double)L[8] : nan;
+            } else {
+                const float* L = lattices + 9 * (int64_t)st[u];
+                v0 = ok[u] ? f0 * (double)L[0] + f1 * (double)L[3] + f2 * (double)L[6] : nan;
+                v1 = ok[u] ? f0 * (double)L[1] + f1 * (double)L[4] + f2 * (double)L[7] : nan;
+                v2 = ok[u] ? f0 * (double)L[2] + f1 * (double)L[5] + f2 * (double)L[8] : nan;
+            }
             if (e < Ee) {
                 if (vec) {
                     vec[3 * e] = (float)v0;
@@ -711,7 +723,7 @@ hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const i
     (void)w;
     if (E == 0 || B == 0) return hipSuccess;
     const int cu = device_cu_count();
-    hipLaunchKernelGGL(k_geom_fwd, dim3(grid_for(E, 256 * 4, cu * 16)), dim3(256), 0, s, lattices, frac, atom_struct,
+    hipLaunchKernelGGL(k_geom_fwd, dim3(grid_for(E, 256 * 4, 1 << 30)), dim3(256), 0, s, lattices, frac, atom_struct,
                        N, src, dst, image, E, num_edges, vec, length);
     return hipGetLastError();
 }

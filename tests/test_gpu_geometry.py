@@ -27,6 +27,43 @@ def test_forward_parity_config4():
     assert np.abs(length.detach().cpu().numpy() - ln).max() <= 2e-5
 
 
+@pytest.mark.parametrize("order", ["shuffled", "structures_reversed", "cross_and_invalid"])
+def test_forward_edge_orders(order):
+    """The forward pass for edges that are not in the builders' order: fully
+    shuffled, structure blocks reversed, or the builders' order with one edge
+    whose dst lies in another structure and two edges with an endpoint outside
+    [0, N) (those give NaN). Valid edges must match the oracle (the lattice of
+    the source's structure)."""
+    rng = np.random.default_rng(91)
+    b = inputs.random_batch(rng, 10, 3, 60, 3.0, 8.0, cutoff=5.0)
+    g, (s, d, t, ln) = _edges(b)
+    s, d, t = s.astype(np.int64), d.astype(np.int64), t.copy()
+    bad = np.zeros(len(s), bool)
+    if order == "shuffled":
+        perm = rng.permutation(len(s))
+        s, d, t = s[perm], d[perm], t[perm]
+    elif order == "structures_reversed":
+        blocks = [np.flatnonzero((s >= b.batch_ptr[q]) & (s < b.batch_ptr[q + 1])) for q in range(b.B)]
+        perm = np.concatenate(blocks[::-1])
+        s, d, t = s[perm], d[perm], t[perm]
+    else:
+        q5 = int(np.searchsorted(b.batch_ptr, s[5], side="right")) - 1
+        other_q = next(q for q in range(q5 + 1, q5 + b.B) if b.batch_ptr[q % b.B + 1] > b.batch_ptr[q % b.B]) % b.B
+        d[5] = b.batch_ptr[other_q]                      # an atom of another structure
+        s[10] = -1
+        d[20] = b.N
+        bad[[10, 20]] = True
+    L, X, P = gu.dev(b)
+    ti = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.int32))).cuda()
+    vec, length = graph.edge_geometry(L, X, P, ti(s), ti(d), ti(t))
+    vec, length = vec.detach().cpu().numpy(), length.detach().cpu().numpy()
+    ok = ~bad
+    v64, l64 = oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, s[ok], d[ok], t[ok])
+    assert np.abs(vec[ok] - v64).max() <= 2e-5
+    assert np.abs(length[ok] - l64).max() <= 2e-5
+    assert np.isnan(vec[bad]).all() and np.isnan(length[bad]).all()
+
+
 def _rel_err(a, ref):
     return np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)
 
