@@ -12,8 +12,9 @@
 // The count pass writes the number of edges of every source; after the scan
 // the fill pass repeats the sweep and writes every hit at
 // offsets[src] + (rank of the hit inside the source), ranked with a wave
-// ballot and mbcnt. Both passes enumerate candidates in the same order, so
-// the edges of a source are contiguous and their order is deterministic.
+// ballot and mbcnt. The fill visits t = 0 first (the only image with an
+// excluded pair, (i, i, 0)) and then the others in table order, so the edges
+// of a source are contiguous and their order is deterministic.
 // This replaces the ordered stack's concatenate / sort / filter (Sec. 2.2,
 // Algorithm 2) for the cutoff graph: nothing is sorted, the output is grouped
 // by source as Algorithm 2's stable sort by source index would group it.
@@ -25,7 +26,7 @@ namespace {
 
 struct Pair {
     float px, py, pz;
-    int w0, w1, w2;
+    int w0, w1, w2;   // wrap of the fractional displacement, plus the packing bias
     bool self;
 };
 
@@ -51,9 +52,9 @@ __device__ inline Pair make_pair(const float* __restrict__ frac, const double* L
     P.px = (float)(d0 * L[0] + d1 * L[3] + d2 * L[6]);
     P.py = (float)(d0 * L[1] + d1 * L[4] + d2 * L[7]);
     P.pz = (float)(d0 * L[2] + d1 * L[5] + d2 * L[8]);
-    P.w0 = (int)w0;
-    P.w1 = (int)w1;
-    P.w2 = (int)w2;
+    P.w0 = (int)w0 + TBIAS;
+    P.w1 = (int)w1 + TBIAS;
+    P.w2 = (int)w2 + TBIAS;
     return P;
 }
 
@@ -103,7 +104,7 @@ struct OutRel {
     int32_t* dst;
     int32_t* image;
     float* length;
-    int64_t cap;   // capacity - base: relative edges >= cap are not written
+    uint32_t cap;   // capacity - base (clamped to 32 bits): relative edges >= cap are not written
 };
 
 __device__ __forceinline__ OutRel rebase(int64_t base, int64_t capacity, int32_t* src, int32_t* dst, int32_t* image,
@@ -111,21 +112,36 @@ __device__ __forceinline__ OutRel rebase(int64_t base, int64_t capacity, int32_t
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)base >> 32));
     const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
-    return OutRel{src + b, dst + b, image + 3 * b, length + b, capacity - b};
+    const int64_t room = capacity - b;
+    const uint32_t cap = room <= 0 ? 0u : (room >= (int64_t)UINT32_MAX ? UINT32_MAX : (uint32_t)room);
+    return OutRel{src + b, dst + b, image + 3 * b, length + b, cap};
+}
+
+// Correctly rounded square root of a finite x >= 0: the hardware root (within
+// one ulp) and one residual test on each neighbour, r*r against x with a
+// single rounding (fma). The library's sqrtf adds denormal scaling and special
+// cases that squared distances below the cutoff never need.
+__device__ __forceinline__ float sqrt_rn_finite(float x) {
+    const float r = __builtin_amdgcn_sqrtf(x);
+    const float rm = __uint_as_float(__float_as_uint(r) - 1u);
+    const float rp = __uint_as_float(__float_as_uint(r) + 1u);
+    const float lo = fmaf(-rm, r, x) <= 0.0f ? rm : r;   // x at or below the rm..r midpoint squared
+    return fmaf(-rp, r, x) > 0.0f ? rp : lo;             // x above the r..rp midpoint squared
 }
 
 __device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t src_atom, int32_t dst_atom,
                                            const Pair& P, int32_t tpk, float l2) {
-    if ((int64_t)e >= o.cap) return;
+    if (e >= o.cap) return;
     // 32-bit byte offsets from the scalar bases (an item's edges are far fewer than 2^28)
-    const uint32_t b4 = e * 4u, b12 = e * 12u;
+    const uint32_t b4 = e << 2, b12 = (e << 3) + (e << 2);
     *(int32_t*)((char*)o.src + b4) = src_atom;
     *(int32_t*)((char*)o.dst + b4) = dst_atom;
     int32_t* im = (int32_t*)((char*)o.image + b12);
-    im[0] = unpack_t0(tpk) - P.w0;
-    im[1] = unpack_t1(tpk) - P.w1;
-    im[2] = unpack_t2(tpk) - P.w2;
-    *(float*)((char*)o.length + b4) = sqrtf(l2);
+    constexpr int32_t mask = (1 << TBITS) - 1;   // t - w from the biased fields
+    im[0] = ((tpk >> (2 * TBITS)) & mask) - P.w0;
+    im[1] = ((tpk >> TBITS) & mask) - P.w1;
+    im[2] = (tpk & mask) - P.w2;
+    *(float*)((char*)o.length + b4) = sqrt_rn_finite(l2);
 }
 
 }  // namespace
@@ -159,7 +175,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         const int I = si->box == 0 ? 0 : si->images;
         const int zimg = si->zero_img;
         const ImageEntry* tab = table + si->img_off;
-        const int32_t zero_pk = pack_t(0, 0, 0);
         double L[9];
 #pragma unroll
         for (int r = 0; r < 9; ++r) L[r] = si->L[r];
@@ -190,19 +205,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 seg = (n == WAVE) ? ~0ull : (((1ull << n) - 1ull) << (a * n));
             }
             const int32_t sa = (int32_t)(atom0 + il), da = (int32_t)(atom0 + j);
-            auto step = [&](const ImageEntry& e) {
+            auto step_x = [&](const ImageEntry& e, bool zero) {
                 const float l2 = dist2(P, e);
                 bool hit = l2 < c2;
                 if (MODE == MODE_COUNT) {
                     cnt += hit ? 1u : 0u;
                 } else {
-                    hit = hit && !(P.self && e.tpk == zero_pk);   // the excluded self-image (i, i, 0)
+                    if (zero) hit = hit & !P.self;   // the excluded self-image (i, i, 0)
                     const uint64_t m = ballot(hit) & seg;
                     if (hit) write_edge(base + run + mbcnt(m), out, sa, da, P, e.tpk, l2);
                     run += (uint32_t)__popcll(m);
                 }
             };
-            for_images(tab, I, step);
+            auto step = [&](const ImageEntry& e) { step_x(e, false); };
+            if (MODE == MODE_COUNT) {
+                for_images(tab, I, step);
+            } else {
+                // t = 0 first (the only image with an excluded pair), then the others in order
+                step_x(tab[zimg], true);
+                for_images(tab, zimg, step);
+                for_images(tab + zimg + 1, I - zimg - 1, step);
+            }
             if (MODE == MODE_COUNT) {
                 // the self pair at t = 0 has length exactly 0: it was counted iff 0 < c2
                 if (P.self && 0.0f < c2) cnt -= 1u;
@@ -229,7 +252,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                     const int j = jc + r * WAVE + lane;
                     P[r] = make_pair(frac, L, atom0, il, j, j < n);
                 }
-                auto step = [&](const ImageEntry& e) {
+                auto step_x = [&](const ImageEntry& e, bool zero) {
 #pragma unroll
                     for (int r = 0; r < SLOTS; ++r) {
                         const float l2 = dist2(P[r], e);
@@ -237,7 +260,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                         if (MODE == MODE_COUNT) {
                             cnt += (uint32_t)__popcll(ballot(hit));
                         } else {
-                            hit = hit && !(P[r].self && e.tpk == zero_pk);
+                            if (zero) hit = hit & !P[r].self;
                             const uint64_t m = ballot(hit);
                             if (hit)
                                 write_edge(run + mbcnt(m), out, sa, (int32_t)(atom0 + jc + r * WAVE + lane), P[r],
@@ -246,7 +269,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                         }
                     }
                 };
-                for_images(tab, I, step);
+                auto step = [&](const ImageEntry& e) { step_x(e, false); };
+                if (MODE == MODE_COUNT) {
+                    for_images(tab, I, step);
+                } else {
+                    step_x(tab[zimg], true);
+                    for_images(tab, zimg, step);
+                    for_images(tab + zimg + 1, I - zimg - 1, step);
+                }
             }
             if (MODE == MODE_COUNT) {
                 // the self pair at t = 0 (length exactly 0) was counted iff 0 < c2
