@@ -153,6 +153,25 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
             use_cl = true;
         }
     }
+    // quantities of the image tests
+    {
+        double rh2 = 0.0;
+        for (int cnr = 0; cnr < 4; ++cnr) {
+            const double e1 = (cnr & 1) ? 0.5 : -0.5, e2 = (cnr & 2) ? 0.5 : -0.5;
+            const double dx = 0.5 * L[0] + e1 * L[3] + e2 * L[6];
+            const double dy = 0.5 * L[1] + e1 * L[4] + e2 * L[7];
+            const double dz = 0.5 * L[2] + e1 * L[5] + e2 * L[8];
+            rh2 = fmax(rh2, dx * dx + dy * dy + dz * dz);
+        }
+        const double far = (double)(float)Rb + sqrt(rh2);   // the radius the image kernel tests with
+        si.far2 = far * far;
+        for (int k = 0; k < 3; ++k)
+            si.hk[k] = fabs(det) / sqrt(c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2]);
+        const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+        for (int q = 0; q < 6; ++q)
+            si.Gm[q] = L[3 * ia[q]] * L[3 * ib[q]] + L[3 * ia[q] + 1] * L[3 * ib[q] + 1] +
+                       L[3 * ia[q] + 2] * L[3 * ib[q] + 2];
+    }
     int64_t box = 1;
     for (int k = 0; k < 3; ++k) {
         double r = sqrt(c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2]) / fabs(det);
@@ -356,8 +375,9 @@ __device__ double cell_min_dist2(const double G[3][3], int t0, int t1, int t2) {
 // Every box image of the batch, one thread each: the FP64 shift t.L and a keep
 // flag, written into the structure's box-sized slot of the table (tpk = -1 for
 // images dropped). Cheap bounds decide most images: the slab bound
-// (|t_k| - 1/2) h_k and the sphere bound |t.L| - (half cell diagonal) reject,
-// a cell centre inside the ball accepts; the exact distance decides the rest.
+// (|t_k| - 1/2) h_k and the sphere bound |t.L| - (half the longest cell
+// diagonal) reject, a cell centre inside the ball accepts; the exact distance
+// decides the rest. The structure's quantities come precomputed (bounds).
 __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __restrict__ info,
                                                      const int64_t* __restrict__ box_off,
                                                      const Counters* __restrict__ ctr,
@@ -377,62 +397,30 @@ __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __
             kflag[idx] = 0u;
             continue;
         }
-        const int64_t loc = idx - box_off[lo];
+        const int loc = (int)(idx - box_off[lo]);
         const int n0 = si->nk[0], n1 = si->nk[1], n2 = si->nk[2];
         const int w1 = 2 * n1 + 1, w2 = 2 * n2 + 1;
-        const int t2 = (int)(loc % w2) - n2;
-        const int64_t r = loc / w2;
-        const int t1 = (int)(r % w1) - n1;
-        const int t0 = (int)(r / w1) - n0;
-        double L[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) L[q] = si->L[q];
+        const int t2 = loc % w2 - n2;
+        const int r = loc / w2;
+        const int t1 = r % w1 - n1;
+        const int t0 = r / w1 - n0;
+        const double* L = si->L;
         const double R = (double)si->R;
         const double cx = t0 * L[0] + t1 * L[3] + t2 * L[6];
         const double cy = t0 * L[1] + t1 * L[4] + t2 * L[7];
         const double cz = t0 * L[2] + t1 * L[5] + t2 * L[8];
-        bool keep;
         const double c2 = cx * cx + cy * cy + cz * cz;
+        bool keep;
         if ((t0 | t1 | t2) == 0 || c2 <= R * R) {
             keep = true;
         } else {
-            // slab bound
-            double cof[3][3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double* u = L + 3 * ((a + 1) % 3);
-                const double* w = L + 3 * ((a + 2) % 3);
-                cof[a][0] = u[1] * w[2] - u[2] * w[1];
-                cof[a][1] = u[2] * w[0] - u[0] * w[2];
-                cof[a][2] = u[0] * w[1] - u[1] * w[0];
-            }
-            const double det = fabs(L[0] * cof[0][0] + L[1] * cof[0][1] + L[2] * cof[0][2]);
-            const int tt[3] = {t0, t1, t2};
-            double slab = 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double h = det / sqrt(cof[a][0] * cof[a][0] + cof[a][1] * cof[a][1] + cof[a][2] * cof[a][2]);
-                slab = fmax(slab, (fabs((double)tt[a]) - 0.5) * h);
-            }
-            // sphere bound: half the longest cell diagonal
-            double rh2 = 0.0;
-#pragma unroll
-            for (int cnr = 0; cnr < 4; ++cnr) {
-                const double s1 = (cnr & 1) ? 0.5 : -0.5, s2 = (cnr & 2) ? 0.5 : -0.5;
-                const double dx = 0.5 * L[0] + s1 * L[3] + s2 * L[6];
-                const double dy = 0.5 * L[1] + s1 * L[4] + s2 * L[7];
-                const double dz = 0.5 * L[2] + s1 * L[5] + s2 * L[8];
-                rh2 = fmax(rh2, dx * dx + dy * dy + dz * dz);
-            }
-            if (slab >= R || sqrt(c2) - sqrt(rh2) >= R) {
+            const double slab = fmax(fmax((fabs((double)t0) - 0.5) * si->hk[0], (fabs((double)t1) - 0.5) * si->hk[1]),
+                                     (fabs((double)t2) - 0.5) * si->hk[2]);
+            if (slab >= R || c2 >= si->far2) {
                 keep = false;
             } else {
-                double G[3][3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b)
-                        G[a][b] = L[3 * a] * L[3 * b] + L[3 * a + 1] * L[3 * b + 1] + L[3 * a + 2] * L[3 * b + 2];
+                const double* g = si->Gm;
+                const double G[3][3] = {{g[0], g[1], g[2]}, {g[1], g[3], g[4]}, {g[2], g[4], g[5]}};
                 keep = cell_min_dist2(G, t0, t1, t2) < R * R;
             }
         }

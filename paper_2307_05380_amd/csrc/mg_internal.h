@@ -49,6 +49,11 @@ struct alignas(16) StructInfo {
     int64_t bin_off;    // cell lists: first bin in the global bin arrays
     int32_t cl_items;   // cell lists: work items (one per source)
     float wcl;          // cell lists: radius covered by the 27-bin stencil (Angstrom)
+    // image tests (FP64): lattice-plane spacings, (R + half the longest cell
+    // diagonal)^2 and the metric tensor G = L L^T (00 01 02 11 12 22)
+    double hk[3];
+    double far2;
+    double Gm[6];
 };
 
 constexpr int CL_MIN_ATOMS = 512;   // structures smaller than this use the image sweep
