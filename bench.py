@@ -38,6 +38,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 # algorithmic work per unit: bytes per edge / flops per candidate
 BYTES_PER_EDGE_FILL = 24.0     # src, dst (4+4), image (12), length (4)
+BYTES_PER_EDGE_VEC = 12.0      # the edge vector, when the fill emits it
 BYTES_PER_EDGE_GEOM = 36.0     # forward: read src, dst, image (20) + write vec, length (16)
 BYTES_PER_EDGE_GEOM_BWD = 24.0 # backward with the length gradient only: read src, dst, image (20) + grad (4)
 FLOPS_PER_CANDIDATE = 8.0      # 3 add + 1 mul + 2 fma (= 8 flops) per (source, destination, image)
@@ -58,6 +59,9 @@ def _parse(argv=None):
                     help="also run a plain device copy of this many MiB (profiler counter calibration)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch parameters")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP graph")
+    ap.add_argument("--separate-forward", action="store_true",
+                    help="compute the edge vectors with the separate geometry kernel instead of taking them "
+                         "from the cutoff fill")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the KNN build after the cutoff build instead of on a second stream")
     ap.add_argument("--update-loop", type=int, default=0, metavar="STEPS",
@@ -176,18 +180,25 @@ def main(argv=None):
     k0 = graph.knn_graph(L, X, P, k, opts=opts)
     knn_images = k0.report.images_needed
     del g0, k0
-    cb = graph.CutoffBuilder(B, N, E, cut_images, dev)
+    # the edge vectors and lengths come out of the cutoff fill (fused), or from
+    # the separate geometry kernel
+    fused = not args.separate_forward
+    cb = graph.CutoffBuilder(B, N, E, cut_images, dev, vec=fused)
     kb = graph.KnnBuilder(B, N, k, knn_images, dev)
     geo = graph.GeometryRunner(B, N, dev)
-    vec = torch.empty((E, 3), dtype=torch.float32, device=dev)
-    length = torch.empty(E, dtype=torch.float32, device=dev)
+    if fused:
+        vec, length = cb.vec, cb.length
+    else:
+        vec = torch.empty((E, 3), dtype=torch.float32, device=dev)
+        length = torch.empty(E, dtype=torch.float32, device=dev)
     gf = torch.empty_like(X)
     gL = torch.empty_like(L)
     ne = cb.rep[:1]     # device edge count written by the cutoff call
 
     # upstream gradient of the loss at this batch (the model's part, untimed)
     cb.run(L, X, P, c, opts)
-    geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
+    if not fused:
+        geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
     w = torch.from_numpy(inputs.loss_weights(E)).to(dev)
 
     def loss_grad():
@@ -205,7 +216,8 @@ def main(argv=None):
     def step():
         cb.run(L, X, P, c, opts)
         kb.run(L, X, P, opts)
-        geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
+        if not fused:
+            geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
         geo.backward(L, X, P, cb.src, cb.dst, cb.image, None, glen, gf, gL, num_edges=ne)
 
     # ---- eager run with per-phase device events
@@ -238,7 +250,8 @@ def main(argv=None):
         with torch.cuda.stream(knn_stream):
             kb.run(L, X, P, opts)
         cb.run(L, X, P, c, opts)
-        geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
+        if not fused:
+            geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
         geo.backward(L, X, P, cb.src, cb.dst, cb.image, None, glen, gf, gL, num_edges=ne)
         main.wait_stream(knn_stream)
 
@@ -279,7 +292,7 @@ def main(argv=None):
     # ---- roofline of every phase; the dominant one goes into "roofline"
     per = {}
     work = {
-        "cutoff.fill": ("hbm", BYTES_PER_EDGE_FILL * E),
+        "cutoff.fill": ("hbm", (BYTES_PER_EDGE_FILL + (BYTES_PER_EDGE_VEC if fused else 0.0)) * E),
         "cutoff.count": ("alu", FLOPS_PER_CANDIDATE * rep_c.candidates),
         "knn.select": ("alu", FLOPS_PER_CANDIDATE * rep_k.candidates),
         "geometry.fwd": ("hbm", BYTES_PER_EDGE_GEOM * E),
@@ -324,7 +337,9 @@ def main(argv=None):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{B} structures, {N} atoms, cutoff {c} A, k {k}, one batched launch sequence "
                                "per graph type" + ("" if args.no_graph else ", captured in a HIP graph")
-                               + ("" if args.no_overlap else "; the KNN build on a second stream"),
+                               + ("" if args.no_overlap else "; the KNN build on a second stream")
+                               + ("; edge vectors and lengths emitted by the cutoff fill" if fused
+                                  else "; edge vectors and lengths by the separate geometry kernel"),
                    "structures": B, "atoms": N, "cutoff_edges": E, "knn_edges": N * k, "cutoff": c, "k": k},
         "roofline": roof,
         "phases": per,

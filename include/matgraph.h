@@ -162,6 +162,29 @@ mg_status mg_cutoff_graph_radii(const float* lattices, const float* frac, const 
                                 void* workspace, size_t workspace_bytes, int32_t opts, void* stream);
 
 /*
+ * Periodic cutoff multigraph that also returns every edge's vector, the
+ * displacement whose norm the cutoff test takes (Definition def6): the
+ * geometry of the edges comes out of the same sweep, so a model that needs
+ * (vec, length) right after building the graph does not stream the edge list
+ * again. vec_e = p_ij + s_t in FP32, where p_ij (the wrapped pair
+ * displacement times the lattice) and s_t = t L are each computed in FP64 and
+ * rounded once; length_e is the correctly rounded norm of that FP32 vector.
+ * Compared with mg_edge_geometry (FP64 throughout) the components differ by a
+ * few FP32 ulps of |p_ij| + |s_t|.
+ *
+ *  radii         float32 [N] device per-atom cutoffs as in mg_cutoff_graph_radii,
+ *                or NULL for the constant `cutoff` as in mg_cutoff_graph.
+ *  vec           float32 [capacity][3]; must be non-NULL when capacity > 0.
+ *  All other arguments, outputs, ordering and errors as for mg_cutoff_graph
+ *  (mg_cutoff_graph_radii when radii is given); same workspace size.
+ */
+mg_status mg_cutoff_graph_vec(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                              int32_t B, int64_t N, float cutoff, const float* radii, int64_t capacity,
+                              int32_t* src, int32_t* dst, int32_t* image, float* length, float* vec,
+                              int64_t* row_ptr, mg_report* report,
+                              void* workspace, size_t workspace_bytes, int32_t opts, void* stream);
+
+/*
  * Periodic k-nearest-neighbour multigraph (Sec. 1; Sec. 2.2 Algorithms 1-2).
  * Every source gets exactly k edges: the k smallest (length, dst, t0, t1, t2) keys,
  * compared on the FP32 length, then the global dst index, then t lexicographically

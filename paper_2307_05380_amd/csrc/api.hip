@@ -359,8 +359,8 @@ namespace {
 // Both cutoff entry points: one constant cutoff, or per-atom cutoffs (radii).
 mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
                        int64_t N, float cutoff, const float* radii, int64_t capacity, int32_t* src,
-                       int32_t* dst, int32_t* image, float* length, int64_t* row_ptr, mg_report* report,
-                       void* workspace, size_t workspace_bytes, int32_t opts, void* stream) {
+                       int32_t* dst, int32_t* image, float* length, float* vec, int64_t* row_ptr,
+                       mg_report* report, void* workspace, size_t workspace_bytes, int32_t opts, void* stream) {
     g_err.clear();
     mg_status st = check_common(lattices, frac, batch_ptr, B, N);
     if (st != MG_OK) return st;
@@ -404,7 +404,7 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
         return hip_fail(e, "cell lists");
     if ((e = phase("cutoff.count", s, [&] {
              hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.img.table, frac, c2, thr, w.counts, offs,
-                                                    capacity, src, dst, image, length, w.ctr, report, w.partials,
+                                                    capacity, src, dst, image, length, vec, w.ctr, report, w.partials,
                                                     grid, tu.cutoff_slots, s);
              if (r != hipSuccess || !sum) return r;
              return mg::launch_sum_partials(w.partials, grid * 4, report, s);
@@ -412,7 +412,7 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
         return hip_fail(e, "count");
     if (cl && (e = phase("cutoff.cells.count", s, [&] {
                    hipError_t r = mg::launch_cl_cutoff_sweep(0, B, w.info, w.cl, frac, c2, thr, w.counts, offs,
-                                                             capacity, src, dst, image, length, w.ctr, report,
+                                                             capacity, src, dst, image, length, vec, w.ctr, report,
                                                              w.partials, grid, s);
                    if (r != hipSuccess || !sum) return r;
                    return mg::launch_sum_partials(w.partials, grid * 4, report, s);
@@ -424,13 +424,13 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
         return hip_fail(e, "scan");
     if ((e = phase("cutoff.fill", s, [&] {
              return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.img.table, frac, c2, thr, w.counts, offs,
-                                            capacity, src, dst, image, length, w.ctr, report, w.partials,
+                                            capacity, src, dst, image, length, vec, w.ctr, report, w.partials,
                                             grid, tu.cutoff_slots, s);
          })) != hipSuccess)
         return hip_fail(e, "fill");
     if (cl && (e = phase("cutoff.cells.fill", s, [&] {
                    return mg::launch_cl_cutoff_sweep(1, B, w.info, w.cl, frac, c2, thr, w.counts, offs, capacity, src,
-                                                     dst, image, length, w.ctr, report, w.partials, grid, s);
+                                                     dst, image, length, vec, w.ctr, report, w.partials, grid, s);
                })) != hipSuccess)
         return hip_fail(e, "cell-list fill");
     return MG_OK;
@@ -446,6 +446,23 @@ mg_status mg_cutoff_graph(const float* lattices, const float* frac, const int64_
                           mg_report* report, void* workspace, size_t workspace_bytes, int32_t opts,
                           void* stream) {
     return cutoff_graph(lattices, frac, batch_ptr, B, N, cutoff, nullptr, capacity, src, dst, image, length,
+                        nullptr, row_ptr, report, workspace, workspace_bytes, opts, stream);
+}
+
+mg_status mg_cutoff_graph_vec(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
+                              int64_t N, float cutoff, const float* radii, int64_t capacity, int32_t* src,
+                              int32_t* dst, int32_t* image, float* length, float* vec, int64_t* row_ptr,
+                              mg_report* report, void* workspace, size_t workspace_bytes, int32_t opts,
+                              void* stream) {
+    if (capacity > 0 && !vec) {
+        g_err.clear();
+        return fail(MG_ERR_INVALID_ARG, "vec must be non-NULL when capacity > 0");
+    }
+    if (radii || N == 0)
+        return cutoff_graph(lattices, frac, batch_ptr, B, N, radii ? 1.0f : cutoff, N > 0 ? radii : nullptr,
+                            capacity, src, dst, image, length, vec, row_ptr, report, workspace, workspace_bytes,
+                            opts, stream);
+    return cutoff_graph(lattices, frac, batch_ptr, B, N, cutoff, nullptr, capacity, src, dst, image, length, vec,
                         row_ptr, report, workspace, workspace_bytes, opts, stream);
 }
 
@@ -460,7 +477,7 @@ mg_status mg_cutoff_graph_radii(const float* lattices, const float* frac, const 
     }
     // with no atoms there is nothing to read: any valid constant gives the same (empty) graph
     return cutoff_graph(lattices, frac, batch_ptr, B, N, 1.0f, N > 0 ? radii : nullptr, capacity, src, dst,
-                        image, length, row_ptr, report, workspace, workspace_bytes, opts, stream);
+                        image, length, nullptr, row_ptr, report, workspace, workspace_bytes, opts, stream);
 }
 
 mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,

@@ -226,6 +226,7 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                                                   const int64_t* __restrict__ offsets, int64_t capacity,
                                                   int32_t* __restrict__ src, int32_t* __restrict__ dst,
                                                   int32_t* __restrict__ image, float* __restrict__ length,
+                                                  float* __restrict__ vec,
                                                   Counters* __restrict__ ctr, mg_report* __restrict__ rep,
                                                   int64_t* __restrict__ partials) {
     const int lane = lane_id();
@@ -269,15 +270,15 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
             for (int64_t pb = p0; pb < p3; pb += WAVE) {
                 const int64_t p = pb + lane;
                 bool hit = false;
-                float l2 = 0.0f;
+                float l2 = 0.0f, dx = 0.0f, dy = 0.0f, dz = 0.0f;
                 int32_t j = -1;
                 if (p < p3) {
                     const float4 e = w.slot_pos[p];
                     j = __float_as_int(e.w);
                     const float kz = (float)((p >= p1) + (p >= p2));
-                    const float dx = e.x + fmaf(kz, stx, qx);
-                    const float dy = e.y + fmaf(kz, sty, qy);
-                    const float dz = e.z + fmaf(kz, stz, qz);
+                    dx = e.x + fmaf(kz, stx, qx);
+                    dy = e.y + fmaf(kz, sty, qy);
+                    dz = e.z + fmaf(kz, stz, qz);
                     l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     hit = l2 < c2 && (int64_t)j != i;
                 }
@@ -295,6 +296,11 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                             image[3 * e + 1] = u1 - unpack_t1(shj) + si1;
                             image[3 * e + 2] = u2 - unpack_t2(shj) + si2;
                             length[e] = sqrtf(l2);
+                            if (vec) {
+                                vec[3 * e] = dx;
+                                vec[3 * e + 1] = dy;
+                                vec[3 * e + 2] = dz;
+                            }
                         }
                     }
                     run += (uint32_t)__popcll(msk);
@@ -334,15 +340,15 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
 hipError_t launch_cl_cutoff_sweep(int mode, int B, const StructInfo* info, const ClWs& w,
                                   const float* frac, float c2thr, const float* thr, uint32_t* counts,
                                   const int64_t* offsets, int64_t capacity, int32_t* src,
-                                  int32_t* dst, int32_t* image, float* length, Counters* ctr,
+                                  int32_t* dst, int32_t* image, float* length, float* vec, Counters* ctr,
                                   mg_report* report, int64_t* partials, int grid, hipStream_t s) {
     if (B == 0) return hipSuccess;
     if (mode == 0)
         hipLaunchKernelGGL((k_cl_sweep<0>), dim3(grid), dim3(256), 0, s, B, info, w, frac, c2thr, thr, counts, offsets,
-                           capacity, src, dst, image, length, ctr, report, partials);
+                           capacity, src, dst, image, length, vec, ctr, report, partials);
     else
         hipLaunchKernelGGL((k_cl_sweep<1>), dim3(grid), dim3(256), 0, s, B, info, w, frac, c2thr, thr, counts, offsets,
-                           capacity, src, dst, image, length, ctr, report, partials);
+                           capacity, src, dst, image, length, vec, ctr, report, partials);
     return hipGetLastError();
 }
 

@@ -195,10 +195,11 @@ struct ClWs {
 };
 hipError_t launch_cl_build(int B, int64_t N, const float* frac, const int64_t* batch_ptr,
                            const StructInfo* info, const ClWs& w, hipStream_t s);
+// vec (nullable, float [capacity][3]): the fill also writes every edge's vector.
 hipError_t launch_cl_cutoff_sweep(int mode, int B, const StructInfo* info, const ClWs& w,
                                   const float* frac, float c2thr, const float* thr, uint32_t* counts,
                                   const int64_t* offsets, int64_t capacity, int32_t* src,
-                                  int32_t* dst, int32_t* image, float* length, Counters* ctr,
+                                  int32_t* dst, int32_t* image, float* length, float* vec, Counters* ctr,
                                   mg_report* report, int64_t* partials, int grid, hipStream_t s);
 hipError_t launch_cl_knn(int B, int k, const StructInfo* info, const ClWs& w, const float* frac,
                          int32_t* src, int32_t* dst, int32_t* image, float* length,
@@ -223,10 +224,11 @@ constexpr int64_t IMAGE_SLOT_BYTES = 45;
 constexpr int64_t IMAGE_FIXED_BYTES = 4096;
 hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr, const ImageTables& t,
                          hipStream_t s);
+// vec (nullable, float [capacity][3]): the fill also writes every edge's vector.
 hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
                                const ImageEntry* table, const float* frac, float c2thr,
                                const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
-                               int32_t* src, int32_t* dst, int32_t* image, float* length,
+                               int32_t* src, int32_t* dst, int32_t* image, float* length, float* vec,
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
                                hipStream_t s);
 // Exclusive scan of counts[0..N) into offsets[0..N]; with a report, also

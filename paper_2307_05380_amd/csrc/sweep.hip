@@ -104,17 +104,18 @@ struct OutRel {
     int32_t* dst;
     int32_t* image;
     float* length;
+    float* vec;     // nullable
     uint32_t cap;   // capacity - base (clamped to 32 bits): relative edges >= cap are not written
 };
 
 __device__ __forceinline__ OutRel rebase(int64_t base, int64_t capacity, int32_t* src, int32_t* dst, int32_t* image,
-                                         float* length) {
+                                         float* length, float* vec) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)base >> 32));
     const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
     const int64_t room = capacity - b;
     const uint32_t cap = room <= 0 ? 0u : (room >= (int64_t)UINT32_MAX ? UINT32_MAX : (uint32_t)room);
-    return OutRel{src + b, dst + b, image + 3 * b, length + b, cap};
+    return OutRel{src + b, dst + b, image + 3 * b, length + b, vec ? vec + 3 * b : nullptr, cap};
 }
 
 // Correctly rounded square root of a finite x >= 0: the hardware root (within
@@ -130,7 +131,8 @@ __device__ __forceinline__ float sqrt_rn_finite(float x) {
 }
 
 __device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t src_atom, int32_t dst_atom,
-                                           const Pair& P, int32_t tpk, float l2) {
+                                           const Pair& P, const ImageEntry& t, float l2) {
+    const int32_t tpk = t.tpk;
     if (e >= o.cap) return;
     // 32-bit byte offsets from the scalar bases (an item's edges are far fewer than 2^28)
     const uint32_t b4 = e << 2, b12 = (e << 3) + (e << 2);
@@ -142,6 +144,12 @@ __device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t 
     im[1] = ((tpk >> TBITS) & mask) - P.w1;
     im[2] = (tpk & mask) - P.w2;
     *(float*)((char*)o.length + b4) = sqrt_rn_finite(l2);
+    if (o.vec) {   // the edge vector p_ij + s_t, as summed for the length
+        float* v = (float*)((char*)o.vec + b12);
+        v[0] = P.px + t.sx;
+        v[1] = P.py + t.sy;
+        v[2] = P.pz + t.sz;
+    }
 }
 
 }  // namespace
@@ -154,7 +162,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const ImageEntry* __restrict__ table, const float* __restrict__ frac, float c2thr,
     const float* __restrict__ thr, uint32_t* __restrict__ counts, const int64_t* __restrict__ offsets, int64_t capacity,
     int32_t* __restrict__ src, int32_t* __restrict__ dst, int32_t* __restrict__ image,
-    float* __restrict__ length, Counters* __restrict__ ctr, mg_report* __restrict__ rep,
+    float* __restrict__ length, float* __restrict__ vec, Counters* __restrict__ ctr, mg_report* __restrict__ rep,
     int64_t* __restrict__ partials) {
     const int lane = lane_id();
     const int64_t total = item_off[B];
@@ -200,7 +208,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             OutRel out{};
             if (MODE == MODE_FILL) {
                 const int64_t ibase = offsets[atom0 + i_first];
-                out = rebase(ibase, capacity, src, dst, image, length);
+                out = rebase(ibase, capacity, src, dst, image, length, vec);
                 base = act ? (uint32_t)(offsets[atom0 + il] - ibase) : 0u;
                 seg = (n == WAVE) ? ~0ull : (((1ull << n) - 1ull) << (a * n));
             }
@@ -213,7 +221,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 } else {
                     if (zero) hit = hit & !P.self;   // the excluded self-image (i, i, 0)
                     const uint64_t m = ballot(hit) & seg;
-                    if (hit) write_edge(base + run + mbcnt(m), out, sa, da, P, e.tpk, l2);
+                    if (hit) write_edge(base + run + mbcnt(m), out, sa, da, P, e, l2);
                     run += (uint32_t)__popcll(m);
                 }
             };
@@ -243,7 +251,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             uint32_t cnt = 0;   // wave-uniform in this path
             uint32_t run = 0;
             OutRel out{};
-            if (MODE == MODE_FILL) out = rebase(offsets[atom0 + il], capacity, src, dst, image, length);
+            if (MODE == MODE_FILL) out = rebase(offsets[atom0 + il], capacity, src, dst, image, length, vec);
             const int32_t sa = (int32_t)(atom0 + il);
             for (int jc = 0; jc < n; jc += WAVE * SLOTS) {
                 Pair P[SLOTS];
@@ -264,7 +272,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                             const uint64_t m = ballot(hit);
                             if (hit)
                                 write_edge(run + mbcnt(m), out, sa, (int32_t)(atom0 + jc + r * WAVE + lane), P[r],
-                                           e.tpk, l2);
+                                           e, l2);
                             run += (uint32_t)__popcll(m);
                         }
                     }
@@ -291,13 +299,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
                                const ImageEntry* table, const float* frac, float c2thr,
                                const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
-                               int32_t* src, int32_t* dst, int32_t* image, float* length,
+                               int32_t* src, int32_t* dst, int32_t* image, float* length, float* vec,
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
                                hipStream_t s) {
     if (B == 0) return hipSuccess;
 #define MG_SWEEP(M, S)                                                                              \
     hipLaunchKernelGGL((k_cutoff_sweep<M, S>), dim3(grid), dim3(256), 0, s, B, info, item_off, table, \
-                       frac, c2thr, thr, counts, offsets, capacity, src, dst, image, length, ctr, report, \
+                       frac, c2thr, thr, counts, offsets, capacity, src, dst, image, length, vec, ctr, report, \
                        partials)
     if (mode == MODE_COUNT) {
         if (slots <= 1) MG_SWEEP(MODE_COUNT, 1);

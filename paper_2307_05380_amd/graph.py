@@ -116,7 +116,7 @@ class CutoffBuilder:
     report (synchronising)."""
 
     def __init__(self, B: int, N: int, capacity: int, image_capacity: int, device=None,
-                 row_ptr: bool = True):
+                 row_ptr: bool = True, vec: bool = False):
         self.lib = _lib.load()
         self.device = torch.device(device or "cuda")
         self.B, self.N = int(B), int(N)
@@ -127,6 +127,8 @@ class CutoffBuilder:
         self.dst = torch.empty(self.capacity, dtype=torch.int32, device=d)
         self.image = torch.empty((self.capacity, 3), dtype=torch.int32, device=d)
         self.length = torch.empty(self.capacity, dtype=torch.float32, device=d)
+        # edge vectors from the same sweep (mg_cutoff_graph_vec), when asked for
+        self.vec = torch.empty((self.capacity, 3), dtype=torch.float32, device=d) if vec else None
         self.row_ptr = torch.empty(self.N + 1, dtype=torch.int64, device=d) if row_ptr else None
         self.rep = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=d)
         nbytes = self.lib.mg_cutoff_workspace_bytes(self.B, self.N, self.image_capacity)
@@ -134,6 +136,15 @@ class CutoffBuilder:
 
     def run(self, lattices, frac, batch_ptr, cutoff, opts: int = 0):
         """``cutoff``: one distance (float) or per-atom cutoffs (float32 device tensor [N])."""
+        if self.vec is not None:
+            radii = _radii(cutoff, self.N) if isinstance(cutoff, torch.Tensor) else None
+            _lib.check(self.lib.mg_cutoff_graph_vec(
+                _ptr(lattices), _ptr(frac), _ptr(batch_ptr), self.B, self.N,
+                1.0 if radii is not None else float(cutoff), _ptr(radii),
+                self.capacity, _ptr(self.src), _ptr(self.dst), _ptr(self.image), _ptr(self.length),
+                _ptr(self.vec), _ptr(self.row_ptr), _ptr(self.rep), _ptr(self.workspace),
+                self.workspace.numel(), int(opts), _stream(self.device)), self.lib)
+            return
         if isinstance(cutoff, torch.Tensor):
             radii = _radii(cutoff, self.N)
             _lib.check(self.lib.mg_cutoff_graph_radii(

@@ -92,6 +92,13 @@ def test_host_validation_extra_entry_points(lib):
     st = lib.mg_cutoff_graph_radii(fake, fake, fake, 1, 2, None, 0, None, None, None, None, None, fake, fake,
                                    1 << 20, 0, None)
     assert st == ERR and b"radii" in lib.mg_last_error()
+    # cutoff graph with edge vectors: vec NULL with capacity, then the cutoff checks of the plain call
+    st = lib.mg_cutoff_graph_vec(fake, fake, fake, 1, 2, 5.0, None, 8, fake, fake, fake, fake, None, None, fake,
+                                 fake, 1 << 20, 0, None)
+    assert st == ERR and b"vec" in lib.mg_last_error()
+    st = lib.mg_cutoff_graph_vec(fake, fake, fake, 1, 2, -1.0, None, 0, None, None, None, None, None, None, fake,
+                                 fake, 1 << 20, 0, None)
+    assert st == ERR and b"cutoff" in lib.mg_last_error()
     # keep-ties KNN: k outside 1..63, NULL outputs with capacity, NULL workspace
     for k in (0, 64):
         st = lib.mg_knn_graph_ties(fake, fake, fake, 1, 2, k, 0, None, None, None, None, None, fake, fake,
