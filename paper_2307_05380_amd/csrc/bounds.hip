@@ -236,7 +236,11 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
 
 // One workgroup of 1024 threads: exclusive scans over structures of the box
 // sizes (image-table offsets) and of the work-item counts. Structures whose
-// box does not fit the table capacity are skipped and flagged.
+// box does not fit the table capacity are skipped and flagged. Each thread
+// takes SCAN_PER consecutive structures per chunk, so a batch of up to
+// 1024 * SCAN_PER structures is one round of loads (all in flight together).
+constexpr int SCAN_PER = 4;
+
 __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restrict__ info,
                                                       int64_t* __restrict__ item_off,
                                                       int64_t* __restrict__ cl_off,
@@ -250,46 +254,58 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
     if (t < 4) s_base[t] = 0;
     __syncthreads();
     bool overflow = false;
-    for (int base = 0; base < B; base += 1024) {
-        const int b = base + t;
+    for (int base = 0; base < B; base += 1024 * SCAN_PER) {
         // scanned quantities: image box, image items, cell-list items, bins
-        int64_t v[4] = {0, 0, 0, 0};
-        if (b < B) {
-            v[0] = info[b].box;
-            v[1] = info[b].groups;
-            v[2] = info[b].cl_items;
-            v[3] = info[b].nbins;
+        int64_t v[SCAN_PER][4];
+        int64_t tot[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < SCAN_PER; ++u) {
+            const int b = base + t * SCAN_PER + u;
+            const bool in = b < B;
+            const StructInfo* si = info + (in ? b : 0);
+            v[u][0] = in ? si->box : 0;
+            v[u][1] = in ? si->groups : 0;
+            v[u][2] = in ? si->cl_items : 0;
+            v[u][3] = in ? si->nbins : 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tot[q] += v[u][q];
         }
         int64_t inc[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            inc[q] = wave_incl_scan_i64(v[q]);
+            inc[q] = wave_incl_scan_i64(tot[q]);
             if (lane == 63) s_part[q][w] = inc[q];
         }
         __syncthreads();
         int64_t pre[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            pre[q] = s_base[q];
+            pre[q] = s_base[q] + inc[q] - tot[q];
             for (int r = 0; r < w; ++r) pre[q] += s_part[q][r];
         }
-        if (b < B) {
-            const int64_t off = pre[0] + inc[0] - v[0];
-            info[b].img_off = off;
-            box_off[b] = off;
-            if (off + v[0] > capacity && v[0] > 0) {
-                overflow = true;
-                info[b].box = 0;           // skipped: no images; its items write empty results
-                info[b].flags |= MG_FLAG_IMAGES;
+#pragma unroll
+        for (int u = 0; u < SCAN_PER; ++u) {
+            const int b = base + t * SCAN_PER + u;
+            if (b < B) {
+                const int64_t off = pre[0];
+                info[b].img_off = off;
+                box_off[b] = off;
+                if (off + v[u][0] > capacity && v[u][0] > 0) {
+                    overflow = true;
+                    info[b].box = 0;           // skipped: no images; its items write empty results
+                    info[b].flags |= MG_FLAG_IMAGES;
+                }
+                item_off[b] = pre[1];
+                if (cl_off) cl_off[b] = pre[2];
+                info[b].bin_off = pre[3];
             }
-            item_off[b] = pre[1] + inc[1] - v[1];
-            if (cl_off) cl_off[b] = pre[2] + inc[2] - v[2];
-            info[b].bin_off = pre[3] + inc[3] - v[3];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pre[q] += v[u][q];
         }
         __syncthreads();
         if (t == 1023) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s_base[q] = pre[q] + inc[q];
+            for (int q = 0; q < 4; ++q) s_base[q] = pre[q];
         }
         __syncthreads();
     }
@@ -372,6 +388,28 @@ __device__ double cell_min_dist2(const double G[3][3], int t0, int t1, int t2) {
     return best;
 }
 
+// Largest s in [0, n) with a[s] <= x, for a non-decreasing a with a[0] <= x,
+// found by the whole wave (x wave-uniform): a 65-ary search, each step probing
+// 64 positions at once, so the result needs about log65(n) dependent loads.
+__device__ __forceinline__ int wave_search_le(const int64_t* __restrict__ a, int n, int64_t x, int lane) {
+    int lo = 0, hi = n;   // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int span = hi - lo;
+        if (span <= WAVE) {
+            const int p = lo + lane;
+            const uint64_t le = ballot(lane < span && a[min(p, n - 1)] <= x);
+            return lo + __popcll(le) - 1;   // a is sorted: the lanes with a[p] <= x are a prefix
+        }
+        const int p = lo + (int)(((int64_t)span * (lane + 1)) / (WAVE + 1));   // strictly increasing, in (lo, hi)
+        const int c = __popcll(ballot(a[p] <= x));                           // probes at or below x
+        const int plo = lo + (int)(((int64_t)span * c) / (WAVE + 1));         // probe c - 1, or lo
+        const int phi = lo + (int)(((int64_t)span * (c + 1)) / (WAVE + 1));   // probe c, or hi
+        lo = c == 0 ? lo : plo;
+        hi = c == WAVE ? hi : phi;
+    }
+    return lo;
+}
+
 // Every box image of the batch, one thread each: the FP64 shift t.L and a keep
 // flag, written into the structure's box-sized slot of the table (tpk = -1 for
 // images dropped). Cheap bounds decide most images: the slab bound
@@ -384,9 +422,16 @@ __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __
                                                      ImageEntry* __restrict__ table, uint32_t* __restrict__ kflag,
                                                      int64_t capacity) {
     const int64_t total = min(ctr->total_box, capacity);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-        int lo = 0, hi = B;   // box_off[lo] <= idx < box_off[hi]
+    const int lane = lane_id();
+    // whole waves step together over consecutive slots: the wave finds the
+    // structures of its first and last slot, each lane then searches only
+    // between them
+    for (int64_t w0 = grid_wave() * WAVE; w0 < total; w0 += grid_waves() * WAVE) {
+        const int64_t idx = w0 + lane;
+        const int sa = wave_search_le(box_off, B, w0, lane);
+        const int sb = wave_search_le(box_off, B, min(w0 + WAVE, total) - 1, lane);
+        if (idx >= total) continue;
+        int lo = sa, hi = sb + 1;   // box_off[lo] <= idx < box_off[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (box_off[mid] <= idx) lo = mid;
