@@ -171,6 +171,14 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
         for (int q = 0; q < 6; ++q)
             si.Gm[q] = L[3 * ia[q]] * L[3 * ib[q]] + L[3 * ia[q] + 1] * L[3 * ib[q] + 1] +
                        L[3 * ia[q] + 2] * L[3 * ib[q] + 2];
+        const double g00 = si.Gm[0], g01 = si.Gm[1], g02 = si.Gm[2], g11 = si.Gm[3], g12 = si.Gm[4],
+                     g22 = si.Gm[5];
+        si.rGd[0] = 1.0 / g00;
+        si.rGd[1] = 1.0 / g11;
+        si.rGd[2] = 1.0 / g22;
+        si.rD2[0] = 1.0 / (g11 * g22 - g12 * g12);
+        si.rD2[1] = 1.0 / (g00 * g22 - g02 * g02);
+        si.rD2[2] = 1.0 / (g00 * g11 - g01 * g01);
     }
     int64_t box = 1;
     for (int k = 0; k < 3; ++k) {
@@ -336,54 +344,59 @@ hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, int64_
 
 // Squared distance from the origin to the cell (t + [-1/2, 1/2]^3) L, exactly:
 // the minimum of the convex quadratic q(z) = z G z^T (G = L L^T) over the box
-// z in t + [-1/2, 1/2]^3, taken over all faces of the box (vertices, edges,
-// faces, interior), each with the unconstrained minimiser of q on the face's
-// affine hull when that point lies on the face.
-__device__ double cell_min_dist2(const double G[3][3], int t0, int t1, int t2) {
+// z in t + [-1/2, 1/2]^3, taken over the faces of the box (vertices, edges,
+// 2-faces), each with the unconstrained minimiser of q on the face's affine
+// hull when that point lies on the face. The interior is never the answer
+// here (t != 0 keeps the origin outside the box). All 26 faces are unrolled;
+// the divisions use the structure's precomputed reciprocals.
+__device__ __forceinline__ double qform(const double (&G)[3][3], double z0, double z1, double z2) {
+    return z0 * (G[0][0] * z0 + 2.0 * (G[0][1] * z1 + G[0][2] * z2)) + z1 * (G[1][1] * z1 + 2.0 * G[1][2] * z2) +
+           z2 * G[2][2] * z2;
+}
+
+__device__ double cell_min_dist2(const double (&G)[3][3], const double (&rGd)[3], const double (&rD2)[3], int t0,
+                                 int t1, int t2) {
     const double t[3] = {(double)t0, (double)t1, (double)t2};
-    double best = 1e300;
     const double tol = 1e-12;
-    // pattern per coordinate: 0 = free, 1 = at -1/2, 2 = at +1/2
-    for (int p = 0; p < 27; ++p) {
-        int st[3] = {p % 3, (p / 3) % 3, p / 9};
-        double z[3];
-        int fr[3], nf = 0;
-        for (int k = 0; k < 3; ++k) {
-            if (st[k] == 0) {
-                fr[nf++] = k;
-                z[k] = 0.0;
-            } else {
-                z[k] = t[k] + (st[k] == 1 ? -0.5 : 0.5);
-            }
+    double best = 1e300;
+    // vertices
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const double z0 = t[0] + ((v & 1) ? 0.5 : -0.5);
+        const double z1 = t[1] + ((v & 2) ? 0.5 : -0.5);
+        const double z2 = t[2] + ((v & 4) ? 0.5 : -0.5);
+        best = fmin(best, qform(G, z0, z1, z2));
+    }
+    // edges: coordinate f free, the other two at a corner
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int a = (f + 1) % 3, b = (f + 2) % 3;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double z[3];
+            z[a] = t[a] + ((v & 1) ? 0.5 : -0.5);
+            z[b] = t[b] + ((v & 2) ? 0.5 : -0.5);
+            z[f] = -(G[f][a] * z[a] + G[f][b] * z[b]) * rGd[f];
+            const double u = z[f] - t[f];
+            if (u >= -0.5 - tol && u <= 0.5 + tol) best = fmin(best, qform(G, z[0], z[1], z[2]));
         }
-        bool ok = true;
-        if (nf == 3) {
-            z[0] = z[1] = z[2] = 0.0;       // minimiser of q is the origin
-        } else if (nf == 1) {
-            const int f = fr[0];
-            double rhs = 0.0;
-            for (int k = 0; k < 3; ++k)
-                if (k != f) rhs -= G[f][k] * z[k];
-            z[f] = rhs / G[f][f];
-        } else if (nf == 2) {
-            const int f = fr[0], g = fr[1];
-            const int c = 3 - f - g;
-            const double r0 = -G[f][c] * z[c], r1 = -G[g][c] * z[c];
-            const double a = G[f][f], bb = G[f][g], d = G[g][g];
-            const double det = a * d - bb * bb;
-            z[f] = (r0 * d - bb * r1) / det;
-            z[g] = (a * r1 - bb * r0) / det;
+    }
+    // 2-faces: coordinate c fixed at -1/2 or +1/2, the other two free
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int f = (c + 1) % 3, g = (c + 2) % 3;
+        const int ff = f < g ? f : g, gg = f < g ? g : f;   // the pair in index order
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            double z[3];
+            z[c] = t[c] + (v ? 0.5 : -0.5);
+            const double r0 = -G[ff][c] * z[c], r1 = -G[gg][c] * z[c];
+            z[ff] = (r0 * G[gg][gg] - G[ff][gg] * r1) * rD2[c];
+            z[gg] = (G[ff][ff] * r1 - G[ff][gg] * r0) * rD2[c];
+            const double u0 = z[ff] - t[ff], u1 = z[gg] - t[gg];
+            if (u0 >= -0.5 - tol && u0 <= 0.5 + tol && u1 >= -0.5 - tol && u1 <= 0.5 + tol)
+                best = fmin(best, qform(G, z[0], z[1], z[2]));
         }
-        for (int q = 0; q < nf; ++q) {
-            const int k = fr[q];
-            const double u = z[k] - t[k];
-            ok &= (u >= -0.5 - tol) && (u <= 0.5 + tol);
-        }
-        if (!ok) continue;
-        double v = 0.0;
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) v += z[i] * G[i][j] * z[j];
-        best = fmin(best, v);
     }
     return best;
 }
@@ -466,7 +479,9 @@ __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __
             } else {
                 const double* g = si->Gm;
                 const double G[3][3] = {{g[0], g[1], g[2]}, {g[1], g[3], g[4]}, {g[2], g[4], g[5]}};
-                keep = cell_min_dist2(G, t0, t1, t2) < R * R;
+                const double rGd[3] = {si->rGd[0], si->rGd[1], si->rGd[2]};
+                const double rD2[3] = {si->rD2[0], si->rD2[1], si->rD2[2]};
+                keep = cell_min_dist2(G, rGd, rD2, t0, t1, t2) < R * R;
             }
         }
         ImageEntry e;

@@ -54,6 +54,8 @@ struct alignas(16) StructInfo {
     double hk[3];
     double far2;
     double Gm[6];
+    double rGd[3];      // 1 / G_kk
+    double rD2[3];      // 1 / det of the 2x2 blocks of G on the index pairs (1,2), (0,2), (0,1)
 };
 
 constexpr int CL_MIN_ATOMS = 512;   // structures smaller than this use the image sweep
