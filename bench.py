@@ -322,7 +322,7 @@ def main(argv=None):
     # ---- per-structure launch form (the plain method, one launch sequence per structure)
     plain = None
     if not args.no_plain:
-        plain = plain_form(args, batch, L, X, P, cb, dev)
+        plain = plain_form(args, batch, L, X, P, cb, dev, fused)
 
     out = {
         "metric": "structures/s & edges/s, batched cutoff+KNN build fwd+bwd vs plain; % roofline",
@@ -370,10 +370,11 @@ def main(argv=None):
 def update_loop(dev, steps: int, warmup: int = 2):
     """64 supercells (8-atom base cells tiled 8..16 times per direction, ~10^6
     atoms): every step adds a Cartesian N(0, 0.02 A) move to every atom, then
-    rebuilds the cutoff graph (5 A) and the KNN graph (k = 32), both through
-    cell lists, and runs the edge geometry forward and backward (a fixed random
-    upstream gradient on the lengths). Moves are drawn beforehand; the timed
-    region holds the coordinate update and the four library calls."""
+    rebuilds the cutoff graph (5 A, edge vectors and lengths from its fill) and
+    the KNN graph (k = 32), both through cell lists, and runs the edge geometry
+    backward (a fixed random upstream gradient on the lengths). Moves are drawn
+    beforehand; the timed region holds the coordinate update and the three
+    library calls."""
     import numpy as np
     import torch
 
@@ -388,11 +389,9 @@ def update_loop(dev, steps: int, warmup: int = 2):
     g0 = graph.cutoff_graph(L, X, P, b.cutoff)
     cap = int(g0.num_edges * 1.15) + 4096
     del g0
-    cb = graph.CutoffBuilder(b.B, b.N, cap, 4096, dev)
+    cb = graph.CutoffBuilder(b.B, b.N, cap, 4096, dev, vec=True)
     kb = graph.KnnBuilder(b.B, b.N, b.k, 4096, dev)
     geo = graph.GeometryRunner(b.B, b.N, dev)
-    vec = torch.empty((cap, 3), device=dev)
-    length = torch.empty(cap, device=dev)
     gf = torch.empty_like(X)
     gL = torch.empty_like(L)
     glen = torch.from_numpy(np.random.default_rng(5).normal(size=cap).astype(np.float32)).to(dev)
@@ -404,7 +403,6 @@ def update_loop(dev, steps: int, warmup: int = 2):
         X.add_(deltas[s])
         cb.run(L, X, P, b.cutoff, 0)
         kb.run(L, X, P, 0)
-        geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
         geo.backward(L, X, P, cb.src, cb.dst, cb.image, None, glen, gf, gL, num_edges=ne)
         hist[s] = cb.rep[0]
         flags[s] = cb.rep[4] | kb.rep[4]
@@ -484,10 +482,11 @@ def batch_sweep(dev, sizes=(32, 64, 128, 256, 512), k=32, reps=10):
     return res
 
 
-def plain_form(args, batch, L, X, P, cb, dev):
+def plain_form(args, batch, L, X, P, cb, dev, fused=True):
     """The same kernels launched once per structure: every structure gets its own
-    cutoff call, KNN call, geometry forward and backward (outputs written at the
-    batched offsets). Times the first `plain_structures` structures."""
+    cutoff call (with the edge vectors when `fused`, else followed by the
+    geometry forward), KNN call and geometry backward. Times the first
+    `plain_structures` structures."""
     import numpy as np
     import torch
 
@@ -500,7 +499,7 @@ def plain_form(args, batch, L, X, P, cb, dev):
     nmax = int(np.diff(ptr).max())
     local_ptr = torch.tensor([[0, int(ptr[s + 1] - ptr[s])] for s in range(S)], dtype=torch.int64, device=dev)
     cap_max = int(max(row[ptr[s + 1]] - row[ptr[s]] for s in range(S)))
-    cbs = graph.CutoffBuilder(1, nmax, max(cap_max, 1), 1 << 16, dev)
+    cbs = graph.CutoffBuilder(1, nmax, max(cap_max, 1), 1 << 16, dev, vec=fused)
     kbs = graph.KnnBuilder(1, nmax, k, 1 << 16, dev)
     geo = graph.GeometryRunner(1, nmax, dev)
     vec = torch.empty((max(cap_max, 1), 3), device=dev)
@@ -525,7 +524,8 @@ def plain_form(args, batch, L, X, P, cb, dev):
         e = int(row[a1] - row[a0])
         if e:
             geo.N = n
-            geo.forward(Ls, Xs, ps, cbs.src[:e], cbs.dst[:e], cbs.image[:e], vec, ln)
+            if not fused:
+                geo.forward(Ls, Xs, ps, cbs.src[:e], cbs.dst[:e], cbs.image[:e], vec, ln)
             geo.backward(Ls, Xs, ps, cbs.src[:e], cbs.dst[:e], cbs.image[:e], None, glen, gf, gL)
 
     for s in range(min(8, S)):
