@@ -91,7 +91,7 @@ def measured_traffic(phase: str):
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
     device copy of known size), or None when the summary is missing or was taken
     on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_config3.json")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_4096_structures.json")
     try:
         with open(path) as f:
             t = json.load(f)
