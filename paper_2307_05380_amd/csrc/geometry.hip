@@ -245,12 +245,7 @@ __device__ __forceinline__ bool bwd_item(int64_t item, int B, const int64_t* __r
                                          const int64_t* __restrict__ item_off,
                                          const int64_t* __restrict__ batch_ptr, BwdItem& it) {
     if (item >= item_off[B]) return false;
-    int lo = 0, hi = B;   // largest s with item_off[s] <= item
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (item_off[mid] <= item) lo = mid;
-        else hi = mid;
-    }
+    const int lo = wave_search_le(item_off, B, item, lane_id());   // largest s with item_off[s] <= item
     it.st = lo;
     const int64_t k = item - item_off[lo];
     it.c0 = start[lo] + k * BW_CHUNK;
@@ -275,7 +270,7 @@ __device__ __forceinline__ bool bwd_item(int64_t item, int B, const int64_t* __r
 // no per-edge v is formed and the lattice gradient of the length term is the
 // FP64 register sum M = sum c f^T f, multiplied by L once per item. The four
 // copies are summed at the end and written with plain stores when the item is
-// the whole structure. Each wave walks a contiguous quarter of the item, two
+// the whole structure. Each wave walks a contiguous quarter of the item, four
 // groups of 64 edges per step with all their loads issued first. A dst outside
 // the structure sets flag bit 1, a src outside it (or, where a step mixes
 // sources, a src smaller than the previous lane's) sets bit 0 (the results are
@@ -355,7 +350,7 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
         }
         sa0 = sa1 = sa2 = 0.f;
     };
-    constexpr int U = 2;
+    constexpr int U = 4;
     for (int rb = (int)(w0 - it.c0); rb < r1; rb += WAVE * U) {
         int ai[U], aj[U], at[U][3];
         float ag[U][3], al[U];

@@ -120,6 +120,28 @@ __device__ __forceinline__ int64_t grid_wave() {
 }
 __device__ __forceinline__ int64_t grid_waves() { return (int64_t)gridDim.x * (blockDim.x / WAVE); }
 
+// Largest s in [0, n) with a[s] <= x, for a non-decreasing a with a[0] <= x,
+// found by the whole wave (x wave-uniform): a 65-ary search, each step probing
+// 64 positions at once, so the result needs about log65(n) dependent loads.
+__device__ __forceinline__ int wave_search_le(const int64_t* __restrict__ a, int n, int64_t x, int lane) {
+    int lo = 0, hi = n;   // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int span = hi - lo;
+        if (span <= WAVE) {
+            const int p = lo + lane;
+            const uint64_t le = ballot(lane < span && a[min(p, n - 1)] <= x);
+            return lo + __popcll(le) - 1;   // a is sorted: the lanes with a[p] <= x are a prefix
+        }
+        const int p = lo + (int)(((int64_t)span * (lane + 1)) / (WAVE + 1));   // strictly increasing, in (lo, hi)
+        const int c = __popcll(ballot(a[p] <= x));                           // probes at or below x
+        const int plo = lo + (int)(((int64_t)span * c) / (WAVE + 1));         // probe c - 1, or lo
+        const int phi = lo + (int)(((int64_t)span * (c + 1)) / (WAVE + 1));   // probe c, or hi
+        lo = c == 0 ? lo : plo;
+        hi = c == WAVE ? hi : phi;
+    }
+    return lo;
+}
+
 // Orders this wave's LDS writes before its later LDS reads (lanes exchange data
 // through LDS without a workgroup barrier).
 __device__ inline void wave_lds_sync() {
