@@ -257,16 +257,47 @@ def main(argv=None):
 
     # ---- the timed region: K replays of the captured step (or K eager steps)
     step_timed = step if args.no_overlap else step_overlap
-    run = step_timed
-    if not args.no_graph:
+
+    def capture(fn):
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            step_timed()
+            fn()
         torch.cuda.current_stream().wait_stream(side)
-        cg = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(cg):
-            step_timed()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return g
+
+    if tuning is not None and not args.no_overlap and not args.no_graph:
+        # The two streams share the GPU, so the launch shapes that are best for
+        # each build alone are not best together: time the captured step for a
+        # few grid sizes of both sweeps (the KNN search radius stays as tuned).
+        best_ms, best_cfg = None, None
+        for cw in (8, 16):
+            for kw in (2, 4, 16):
+                cfg = {**tuning, "cutoff_wgs_per_cu": cw, "knn_wgs_per_cu": kw}
+                _lib.set_tuning(**cfg)
+                g = capture(step_timed)
+                for _ in range(3):
+                    g.replay()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(10):
+                    g.replay()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / 10
+                del g
+                if best_ms is None or ms < best_ms:
+                    best_ms, best_cfg = ms, cfg
+        tuning = best_cfg
+        _lib.set_tuning(**tuning)
+        _log(args, "overlap tuning", tuning, round(best_ms, 4))
+    run = step_timed
+    if not args.no_graph:
+        cg = capture(step_timed)
         run = cg.replay
     for _ in range(args.warmup):
         run()
