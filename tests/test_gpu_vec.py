@@ -51,3 +51,43 @@ def test_vec_per_atom_cutoffs():
 def test_vec_cell_lists():
     b = inputs.random_batch(np.random.default_rng(23), 3, 40, 120, 6.0, 12.0, cutoff=5.0)
     assert _run(b, b.cutoff, _lib.MG_OPT_CELL_LIST_FORCE) > 0
+
+
+def test_vec_full_batch_sampled():
+    """The 4096-structure batch with the launch shape the benchmark settles on
+    (two cutoff slots, 16 sweep workgroups per CU): the vector call returns the
+    plain call's graph edge for edge, and the vectors of a sample of structures
+    (the most expensive ones, the thinnest cells, a random draw) agree with the
+    FP64 oracle geometry."""
+    b = inputs.make_config(3)
+    L, X, P = gu.dev(b)
+    t0 = _lib.get_tuning()
+    try:
+        _lib.set_tuning(cutoff_wgs_per_cu=16, cutoff_slots=2)
+        plain = graph.cutoff_graph(L, X, P, b.cutoff, opts=_lib.MG_OPT_CELL_LIST_OFF)
+        E = plain.num_edges
+        bld = graph.CutoffBuilder(b.B, b.N, E, plain.report.images_needed, "cuda", vec=True)
+        bld.run(L, X, P, b.cutoff, _lib.MG_OPT_CELL_LIST_OFF)
+        assert bld.report().num_edges == E
+    finally:
+        _lib.set_tuning(**t0)
+    for a, r in ((bld.src, plain.src), (bld.dst, plain.dst), (bld.image, plain.image), (bld.length, plain.length)):
+        assert torch.equal(a[:E], r)
+    n = b.counts()
+    vol = np.abs(np.linalg.det(b.lattices.astype(np.float64)))
+    heavy = np.argsort(-(n.astype(np.float64) ** 2 / vol))[:24]
+    thin = np.argsort(vol / np.prod(np.linalg.norm(b.lattices.astype(np.float64), axis=2), axis=1))[:12]
+    rnd = np.random.default_rng(3).choice(b.B, 96, replace=False)
+    sample = sorted(set(heavy.tolist()) | set(thin.tolist()) | set(rnd.tolist()))
+    row = bld.row_ptr.cpu().numpy()
+    s, d, t = (x.cpu().numpy() for x in (plain.src, plain.dst, plain.image))
+    vec = bld.vec[:E].cpu().numpy()
+    worst = 0.0
+    for q in sample:
+        e0, e1 = row[b.batch_ptr[q]], row[b.batch_ptr[q + 1]]
+        if e1 == e0:
+            continue
+        v64, _ = oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, s[e0:e1], d[e0:e1], t[e0:e1])
+        worst = max(worst, float(np.abs(vec[e0:e1] - v64).max()))
+    print("worst vector error over", len(sample), "structures:", worst)
+    assert worst <= 2e-5
