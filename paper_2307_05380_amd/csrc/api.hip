@@ -165,7 +165,7 @@ CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
     w.counts = c.take<uint32_t>((size_t)N);
     w.offsets = c.take<int64_t>((size_t)N + 1);
     w.bsum = c.take<int64_t>((size_t)mg::scan_block_count(N) + 1);
-    w.partials = c.take<int64_t>((size_t)mg::MAX_GRID_WAVES);
+    w.partials = c.take<int64_t>(2 * (size_t)mg::MAX_GRID_WAVES);   // image and cell-list sweeps
     w.thr = c.take<float>((size_t)N);
     carve_cl(c, B, N, w.ctr, w.cl);
     w.fixed = c.used;
@@ -213,7 +213,7 @@ GeomWs carve_geom(void* ws, int B, int64_t N) {
     w.bwd.acc = c.take<double>((size_t)B * 9);
     w.bwd.start = c.take<int64_t>((size_t)B + 1);
     w.bwd.item_off = c.take<int64_t>((size_t)B + 1);
-    w.bwd.flag = c.take<int32_t>(1);
+    w.bwd.flag = c.take<int32_t>(4);   // order flag, then item counts by structure size (see geometry)
     w.fixed = mg::align_up(c.used, 256);
     return w;
 }
@@ -402,24 +402,23 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
     if (cl && (e = phase("cutoff.cells", s, [&] { return mg::launch_cl_build(B, N, frac, batch_ptr, w.info, w.cl, s); })) !=
                   hipSuccess)
         return hip_fail(e, "cell lists");
+    // per-wave candidate counts: the image sweep's in partials[0, 4 grid), the
+    // cell-list sweep's after them; the scan adds them to the report
     if ((e = phase("cutoff.count", s, [&] {
-             hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.img.table, frac, c2, thr, w.counts, offs,
-                                                    capacity, src, dst, image, length, vec, w.ctr, report, w.partials,
-                                                    grid, tu.cutoff_slots, s);
-             if (r != hipSuccess || !sum) return r;
-             return mg::launch_sum_partials(w.partials, grid * 4, report, s);
+             return mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.img.table, frac, c2, thr, w.counts, offs,
+                                            capacity, src, dst, image, length, vec, w.ctr, report, w.partials,
+                                            grid, tu.cutoff_slots, s);
          })) != hipSuccess)
         return hip_fail(e, "count");
     if (cl && (e = phase("cutoff.cells.count", s, [&] {
-                   hipError_t r = mg::launch_cl_cutoff_sweep(0, B, w.info, w.cl, frac, c2, thr, w.counts, offs,
-                                                             capacity, src, dst, image, length, vec, w.ctr, report,
-                                                             w.partials, grid, s);
-                   if (r != hipSuccess || !sum) return r;
-                   return mg::launch_sum_partials(w.partials, grid * 4, report, s);
+                   return mg::launch_cl_cutoff_sweep(0, B, w.info, w.cl, frac, c2, thr, w.counts, offs, capacity,
+                                                     src, dst, image, length, vec, w.ctr, report,
+                                                     w.partials + grid * 4, grid, s);
                })) != hipSuccess)
         return hip_fail(e, "cell-list count");
     if ((e = phase("cutoff.scan", s, [&] {
-             return mg::launch_scan_counts(w.counts, N, offs, w.bsum, capacity, report, s);
+             return mg::launch_scan_counts(w.counts, N, offs, w.bsum, capacity, report, s, nullptr,
+                                           sum ? w.partials : nullptr, (cl ? 2 : 1) * grid * 4);
          })) != hipSuccess)
         return hip_fail(e, "scan");
     if ((e = phase("cutoff.fill", s, [&] {

@@ -98,18 +98,17 @@ __global__ __launch_bounds__(256) void k_geom_fwd(const float* __restrict__ latt
     }
 }
 
-__global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ p, int64_t n) {
+// Start of the backward pass: coordinate gradients, FP64 lattice sums and the
+// plan's flag and counters cleared in one launch.
+__global__ __launch_bounds__(256) void k_zero_bwd(float* __restrict__ gf, int64_t n3, double* __restrict__ acc,
+                                                  int64_t n9, int32_t* __restrict__ flag) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = 0.0f;
-}
-
-__global__ __launch_bounds__(64) void k_zero_i32(int32_t* __restrict__ p, int n) {
-    for (int q = threadIdx.x; q < n; q += 64) p[q] = 0;
-}
-
-__global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = 0.0;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 < 4) flag[t0] = 0;
+    for (int64_t q = t0; q < n3 + n9; q += stride) {
+        if (q < n3) gf[q] = 0.0f;
+        else acc[q - n3] = 0.0;
+    }
 }
 
 // Backward pass.
@@ -135,6 +134,7 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_
 //   takes every edge in chunks of BW_CHUNK, whatever their order.
 // Both kernels are launched; each leaves the items of the other at once.
 constexpr int BW_CHUNK = 16384;   // edges per item
+constexpr int BW_SMALL = 128;     // atoms of the small LDS window
 constexpr int BW_WIN = 512;       // atoms of a structure held in LDS
 
 // Lane index of the start of this lane's run (runs of equal key over lanes);
@@ -201,7 +201,11 @@ __global__ __launch_bounds__(256) void k_geom_ranges(const int32_t* __restrict__
 
 // Items: item_off[s] = number of items of structures < s (one item per
 // BW_CHUNK edges, at least one per structure); item_off[B] = total.
-__global__ __launch_bounds__(1024) void k_bwd_items(const int64_t* __restrict__ start, int B,
+// flag[1] and flag[2] count the structures of BW_SMALL < n <= BW_WIN atoms and
+// of more than BW_WIN atoms, so that the kernels for those sizes return at
+// once when there are none.
+__global__ __launch_bounds__(1024) void k_bwd_items(const int64_t* __restrict__ start,
+                                                    const int64_t* __restrict__ batch_ptr, int B,
                                                     int64_t* __restrict__ item_off, int32_t* __restrict__ flag) {
     __shared__ int64_t sh[1024];
     const int t = threadIdx.x;
@@ -209,12 +213,18 @@ __global__ __launch_bounds__(1024) void k_bwd_items(const int64_t* __restrict__ 
     const int s0 = min(B, t * per), s1 = min(B, s0 + per);
     int64_t sum = 0;
     bool bad = false;   // ranges that are not ordered (edges not grouped)
+    int mid = 0, big = 0;
     for (int q = s0; q < s1; ++q) {
         const int64_t n = start[q + 1] - start[q];
         bad |= n < 0;
         sum += n > BW_CHUNK ? (n + BW_CHUNK - 1) / BW_CHUNK : 1;
+        const int64_t na = batch_ptr[q + 1] - batch_ptr[q];
+        mid += (na > BW_SMALL && na <= BW_WIN) ? 1 : 0;
+        big += na > BW_WIN ? 1 : 0;
     }
     if (bad) atomicOr(flag, 1);
+    if (mid) atomicAdd(flag + 1, mid);
+    if (big) atomicAdd(flag + 2, big);
     sh[t] = sum;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
@@ -287,7 +297,8 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
     __shared__ float wacc[4][WIN * 3];
     __shared__ int tag[4][WIN];
     __shared__ double red[4][15];
-    if (*flag != 0) return;
+    if (flag[0] != 0) return;
+    if (n_lo > 0 && flag[1] == 0) return;   // no structure of this window's sizes
     BwdItem it;
     if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it) || it.n > WIN || it.n <= n_lo) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -542,7 +553,8 @@ __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ 
                                                       float* __restrict__ grad_frac,
                                                       double* __restrict__ acc) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const bool grouped = *flag == 0;
+    const bool grouped = flag[0] == 0;
+    if (grouped && flag[2] == 0) return;   // no structure beyond the LDS window
     int64_t c0, c1;
     BwdItem it;
     it.st = -1;
@@ -699,12 +711,12 @@ static int grid_for(int64_t work, int per_block, int cap) {
 }
 
 // Plan of the grouped path: flag cleared, edge ranges, items.
+// (the flag and counters are cleared by the caller's k_zero_bwd)
 static void launch_plan(const int32_t* src, const int64_t* batch_ptr, int B, int64_t E, const int64_t* num_edges,
                         const GeomBwdWs& w, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, w.flag, 1);
     hipLaunchKernelGGL(k_geom_ranges, dim3((unsigned)((B + 1 + 3) / 4)), dim3(256), 0, s, src, batch_ptr, B, E,
                        num_edges, w.start);
-    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, B, w.item_off, w.flag);
+    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, batch_ptr, B, w.item_off, w.flag);
 }
 
 // Enough workgroups for either order: sum_s max(1, ceil(E_s / chunk)) <= B + ceil(E / chunk).
@@ -729,11 +741,11 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
                                const int64_t* num_edges, const float* grad_vec, const float* grad_length,
                                float* grad_frac, float* grad_lattice, const GeomBwdWs& w, hipStream_t s) {
     const int cu = device_cu_count();
-    if (grad_frac && N > 0)
-        hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(3 * N, 256, cu * 4)), dim3(256), 0, s, grad_frac, 3 * N);
-    if (grad_lattice && B > 0)
-        hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(9 * (int64_t)B, 256, cu * 4)), dim3(256), 0, s, w.acc,
-                           9 * (int64_t)B);
+    {
+        const int64_t z3 = grad_frac ? 3 * N : 0, z9 = grad_lattice ? 9 * (int64_t)B : 0;
+        hipLaunchKernelGGL(k_zero_bwd, dim3(grid_for(z3 + z9 + 4, 256, cu * 4)), dim3(256), 0, s, grad_frac, z3,
+                           w.acc, z9, w.flag);
+    }
     if (E > 0 && B > 0 && (grad_frac || grad_lattice) && (grad_vec || grad_length)) {
         launch_plan(src, batch_ptr, B, E, num_edges, w, s);
         const unsigned grid = item_grid(B, E);
@@ -744,8 +756,8 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
                        src, dst, image, grad_vec, grad_length, w.start, w.item_off, w.flag, grad_frac, acc, LO)
 #define MG_BWD_LDS2(GV, GL)              \
     do {                                 \
-        MG_BWD_LDS(GV, GL, 128, 0);      \
-        MG_BWD_LDS(GV, GL, BW_WIN, 128); \
+        MG_BWD_LDS(GV, GL, BW_SMALL, 0);        \
+        MG_BWD_LDS(GV, GL, BW_WIN, BW_SMALL);   \
     } while (0)
         if (grad_vec && grad_length) MG_BWD_LDS2(true, true);
         else if (grad_vec) MG_BWD_LDS2(true, false);

@@ -256,11 +256,12 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
                                hipStream_t s);
 // Exclusive scan of counts[0..N) into offsets[0..N]; with a report, also
-// records the total as num_edges and flags a capacity overflow. With n_dev
-// (a device count), only min(N, *n_dev) counts are scanned.
+// records the total as num_edges and flags a capacity overflow, and adds the
+// np per-wave candidate counts in partials (if given) to report->candidates.
+// With n_dev (a device count), only min(N, *n_dev) counts are scanned.
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offsets, int64_t* bsum,
                               int64_t capacity, mg_report* report, hipStream_t s,
-                              const int64_t* n_dev = nullptr);
+                              const int64_t* n_dev = nullptr, const int64_t* partials = nullptr, int np = 0);
 hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const int64_t* item_off,
                       const ImageEntry* table, const float* frac, int32_t* src, int32_t* dst,
                       int32_t* image, float* length, int32_t* ext_list, Counters* ctr,
@@ -277,7 +278,7 @@ struct GeomBwdWs {
     double* acc;
     int64_t* start;
     int64_t* item_off;
-    int32_t* flag;
+    int32_t* flag;   // [4]: order flag, structures of the middle LDS window, structures beyond it, spare
 };
 hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const int32_t* atom_struct,
                                const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,

@@ -364,7 +364,8 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__
                                                     const int64_t* __restrict__ n_dev,
                                                     const int64_t* __restrict__ bsum,
                                                     int64_t* __restrict__ offsets, int64_t capacity,
-                                                    mg_report* __restrict__ rep) {
+                                                    mg_report* __restrict__ rep,
+                                                    const int64_t* __restrict__ partials, int np) {
     __shared__ int64_t sh[4];
     __shared__ int64_t swave[4];
     const int64_t n = scan_length(N, n_dev);
@@ -399,14 +400,22 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__
             if (excl > capacity) atomicOr(&rep->flags, (uint32_t)MG_FLAG_CAPACITY);
         }
     }
+    if (partials && rep && (int64_t)blockIdx.x == last) {
+        // the sweep's per-wave candidate counts, summed here instead of in a launch of their own
+        int64_t c = 0;
+        for (int q = threadIdx.x; q < np; q += 256) c += partials[q];
+        c = block_sum_256(c, sh);
+        if (threadIdx.x == 0) rep->candidates += c;
+    }
 }
 
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offsets, int64_t* bsum,
-                              int64_t capacity, mg_report* report, hipStream_t s, const int64_t* n_dev) {
+                              int64_t capacity, mg_report* report, hipStream_t s, const int64_t* n_dev,
+                              const int64_t* partials, int np) {
     const int64_t nb = N > 0 ? (N + SCAN_TILE - 1) / SCAN_TILE : 1;
     if (N > 0) hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, counts, N, n_dev, bsum);
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(256), 0, s, counts, N, n_dev, bsum, offsets,
-                       capacity, report);
+                       capacity, report, partials, np);
     return hipGetLastError();
 }
 
