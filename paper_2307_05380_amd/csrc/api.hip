@@ -596,9 +596,7 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac, co
                     workspace_bytes, w.fixed);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
-    if ((e = phase("geometry.atoms", s, [&] { return mg::launch_atom_struct(batch_ptr, B, N, w.atom_struct, s); })) !=
-        hipSuccess)
-        return hip_fail(e, "atom map");
+    // (the backward pass writes the atom -> structure map itself)
     if ((e = phase("geometry.bwd", s, [&] {
              return mg::launch_geometry_bwd(lattices, frac, w.atom_struct, batch_ptr, B, N, src, dst, image, E,
                                             num_edges, grad_vec, grad_length, grad_frac, grad_lattice, w.bwd, s);

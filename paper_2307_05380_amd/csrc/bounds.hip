@@ -474,37 +474,34 @@ __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __
 
 // Kept images moved to their compacted slots (kscan: exclusive scan of the keep
 // flags over the whole table, so every structure's kept images stay contiguous
-// and in lexicographic order).
-__global__ __launch_bounds__(256) void k_image_scatter(const Counters* __restrict__ ctr,
+// and in lexicographic order); the first B threads also set every structure's
+// offset of its compacted images, their number and the index of t = 0 (the
+// box centre, always kept).
+__global__ __launch_bounds__(256) void k_image_scatter(int B, StructInfo* __restrict__ info,
+                                                       const Counters* __restrict__ ctr,
                                                        const ImageEntry* __restrict__ table,
                                                        const uint32_t* __restrict__ kflag,
                                                        const int64_t* __restrict__ kscan,
                                                        ImageEntry* __restrict__ ctable, int64_t capacity) {
     const int64_t total = min(ctr->total_box, capacity);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride)
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t idx = t0; idx < total; idx += stride)
         if (kflag[idx]) ctable[kscan[idx]] = table[idx];
-}
-
-// Per structure: offset of its compacted images, their number and the index
-// of t = 0 (the box centre, always kept).
-__global__ __launch_bounds__(256) void k_image_offsets(int B, StructInfo* __restrict__ info,
-                                                       const uint32_t* __restrict__ kflag,
-                                                       const int64_t* __restrict__ kscan, int64_t capacity) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    StructInfo& si = info[b];
-    const int64_t box = si.box, off = si.img_off;
-    if (box == 0 || off + box > capacity) {
-        si.images = 0;
-        si.zero_img = -1;
-        return;
+    for (int64_t b = t0; b < B; b += stride) {
+        StructInfo& si = info[b];
+        const int64_t box = si.box, off = si.img_off;
+        if (box == 0 || off + box > capacity) {
+            si.images = 0;
+            si.zero_img = -1;
+            continue;
+        }
+        const int64_t c = ((int64_t)si.nk[0] * (2 * si.nk[1] + 1) + si.nk[1]) * (2 * si.nk[2] + 1) + si.nk[2];
+        const int64_t first = kscan[off];
+        si.images = (int)(kscan[off + box] - first);
+        si.zero_img = kflag[off + c] ? (int)(kscan[off + c] - first) : -1;
+        si.img_off = first;
     }
-    const int64_t c = ((int64_t)si.nk[0] * (2 * si.nk[1] + 1) + si.nk[1]) * (2 * si.nk[2] + 1) + si.nk[2];
-    const int64_t first = kscan[off];
-    si.images = (int)(kscan[off + box] - first);
-    si.zero_img = kflag[off + c] ? (int)(kscan[off + c] - first) : -1;
-    si.img_off = first;
 }
 
 hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr, const ImageTables& t,
@@ -515,8 +512,8 @@ hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const 
     // the scan covers the batch's boxes only (their total is known on the device)
     hipError_t e = launch_scan_counts(t.kflag, t.cap, t.kscan, t.kbsum, INT64_MAX, nullptr, s, &ctr->total_box);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_image_scatter, dim3(grid), dim3(256), 0, s, ctr, t.box, t.kflag, t.kscan, t.table, t.cap);
-    hipLaunchKernelGGL(k_image_offsets, dim3((B + 255) / 256), dim3(256), 0, s, B, info, t.kflag, t.kscan, t.cap);
+    hipLaunchKernelGGL(k_image_scatter, dim3(grid), dim3(256), 0, s, B, info, ctr, t.box, t.kflag, t.kscan, t.table,
+                       t.cap);
     return hipGetLastError();
 }
 

@@ -173,11 +173,16 @@ __device__ __forceinline__ T seg_scan(T v, int rs, int lane) {
 __global__ __launch_bounds__(256) void k_geom_ranges(const int32_t* __restrict__ src,
                                                      const int64_t* __restrict__ batch_ptr, int B, int64_t E,
                                                      const int64_t* __restrict__ num_edges,
-                                                     int64_t* __restrict__ start) {
+                                                     int64_t* __restrict__ start,
+                                                     int32_t* __restrict__ atom_struct) {
     const int64_t Ee = edge_count(E, num_edges);
     const int lane = lane_id();
     const int q = (int)(blockIdx.x * (blockDim.x / WAVE)) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     if (q > B) return;
+    if (q < B) {   // the atom -> structure map of the general kernel, written on the way
+        const int64_t a1 = batch_ptr[q + 1];
+        for (int64_t a = batch_ptr[q] + lane; a < a1; a += WAVE) atom_struct[a] = q;
+    }
     if (q == 0 || q == B || Ee == 0) {
         if (lane == 0) start[q] = q == B ? Ee : 0;
         return;
@@ -713,9 +718,9 @@ static int grid_for(int64_t work, int per_block, int cap) {
 // Plan of the grouped path: flag cleared, edge ranges, items.
 // (the flag and counters are cleared by the caller's k_zero_bwd)
 static void launch_plan(const int32_t* src, const int64_t* batch_ptr, int B, int64_t E, const int64_t* num_edges,
-                        const GeomBwdWs& w, hipStream_t s) {
+                        const GeomBwdWs& w, int32_t* atom_struct, hipStream_t s) {
     hipLaunchKernelGGL(k_geom_ranges, dim3((unsigned)((B + 1 + 3) / 4)), dim3(256), 0, s, src, batch_ptr, B, E,
-                       num_edges, w.start);
+                       num_edges, w.start, atom_struct);
     hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, batch_ptr, B, w.item_off, w.flag);
 }
 
@@ -735,7 +740,7 @@ hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const i
     return hipGetLastError();
 }
 
-hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const int32_t* atom_struct,
+hipError_t launch_geometry_bwd(const float* lattices, const float* frac, int32_t* atom_struct,
                                const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
                                const int32_t* dst, const int32_t* image, int64_t E,
                                const int64_t* num_edges, const float* grad_vec, const float* grad_length,
@@ -747,7 +752,7 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const i
                            w.acc, z9, w.flag);
     }
     if (E > 0 && B > 0 && (grad_frac || grad_lattice) && (grad_vec || grad_length)) {
-        launch_plan(src, batch_ptr, B, E, num_edges, w, s);
+        launch_plan(src, batch_ptr, B, E, num_edges, w, atom_struct, s);
         const unsigned grid = item_grid(B, E);
         double* acc = grad_lattice ? w.acc : nullptr;
         // two LDS sizes: structures of up to 128 atoms (most), and 129..BW_WIN atoms

@@ -284,7 +284,7 @@ hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const i
                                const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
                                const int32_t* dst, const int32_t* image, int64_t E, const int64_t* num_edges,
                                float* vec, float* length, const GeomBwdWs& w, hipStream_t s);
-hipError_t launch_geometry_bwd(const float* lattices, const float* frac, const int32_t* atom_struct,
+hipError_t launch_geometry_bwd(const float* lattices, const float* frac, int32_t* atom_struct,
                                const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
                                const int32_t* dst, const int32_t* image, int64_t E,
                                const int64_t* num_edges, const float* grad_vec, const float* grad_length,
