@@ -179,7 +179,7 @@ __device__ __forceinline__ void stack_push(Stack& st, bool pass, float l2, uint3
         c = ufirst(__popcll(m));
         wave_lds_sync();
     }
-    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(sqrtf(l2)) << 32) | (uint64_t)lo;
+    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(sqrt_rn_finite(l2)) << 32) | (uint64_t)lo;
     st.cnt = ufirst(st.cnt + c);
 }
 
@@ -209,30 +209,38 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
         }
         wave_lds_sync();
         const uint32_t nq = (uint32_t)nj * I;
-        // candidate ql = jl * I + img of this lane; the table entry of the next
-        // batch is loaded while the current one is evaluated
+        // candidate ql = jl * I + img of this lane, advanced by WAVE per batch
+        // (jl += WAVE / I, img += WAVE % I with a carry); the table entry of the
+        // next batch is loaded while the current one is evaluated
         auto split = [&](uint32_t ql, uint32_t& jl, uint32_t& img) {
             jl = (uint32_t)((float)ql * invI);
             if (jl * I > ql) --jl;
             if ((jl + 1) * I <= ql) ++jl;
             img = ql - jl * I;
         };
+        const uint32_t dj = (uint32_t)WAVE / I, di = (uint32_t)WAVE - dj * I;
+        auto advance = [&](uint32_t& jl, uint32_t& img) {
+            jl += dj;
+            img += di;
+            if (img >= I) {
+                img -= I;
+                ++jl;
+            }
+        };
+        uint32_t jl, img;
+        split((uint32_t)lane, jl, img);
+        uint32_t jn = jl, in = img;
+        advance(jn, in);
         float4 ent = make_float4(0.f, 0.f, 0.f, 0.f);
         if (S.tab && (uint32_t)lane < nq) {
-            uint32_t jl0, im0;
-            split((uint32_t)lane, jl0, im0);
-            const ImageEntry e = S.tab[im0];
+            const ImageEntry e = S.tab[img];
             ent = make_float4(e.sx, e.sy, e.sz, 0.f);
         }
-        for (uint32_t b0 = 0; b0 < nq; b0 += WAVE) {
+        for (uint32_t b0 = 0; b0 < nq; b0 += WAVE, jl = jn, img = in, advance(jn, in)) {
             const uint32_t ql = b0 + (uint32_t)lane;
             const bool valid = ql < nq;
-            uint32_t jl, img;
-            split(ql, jl, img);
             const float4 cur = ent;
             if (S.tab && ql + WAVE < nq) {
-                uint32_t jn, in;
-                split(ql + WAVE, jn, in);
                 const ImageEntry e = S.tab[in];
                 ent = make_float4(e.sx, e.sy, e.sz, 0.f);
             }

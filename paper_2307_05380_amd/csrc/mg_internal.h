@@ -142,6 +142,20 @@ __device__ __forceinline__ int wave_search_le(const int64_t* __restrict__ a, int
     return lo;
 }
 
+// Correctly rounded square root of a finite x >= 0: the hardware root (within
+// one ulp) and one residual test on each neighbour, r*r against x with a
+// single rounding (fma). Checked bit for bit against sqrtf on every float from
+// 2^-60 to the largest finite one and on 0; below about 2^-100 the residual
+// falls into the range flushed to zero and the hardware root may be kept.
+// Squared edge lengths are 0 or far above that.
+__device__ __forceinline__ float sqrt_rn_finite(float x) {
+    const float r = __builtin_amdgcn_sqrtf(x);
+    const float rm = __uint_as_float(__float_as_uint(r) - 1u);
+    const float rp = __uint_as_float(__float_as_uint(r) + 1u);
+    const float lo = fmaf(-rm, r, x) <= 0.0f ? rm : r;   // x at or below the rm..r midpoint squared
+    return fmaf(-rp, r, x) > 0.0f ? rp : lo;             // x above the r..rp midpoint squared
+}
+
 // Orders this wave's LDS writes before its later LDS reads (lanes exchange data
 // through LDS without a workgroup barrier).
 __device__ inline void wave_lds_sync() {

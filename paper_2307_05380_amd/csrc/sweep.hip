@@ -118,18 +118,6 @@ __device__ __forceinline__ OutRel rebase(int64_t base, int64_t capacity, int32_t
     return OutRel{src + b, dst + b, image + 3 * b, length + b, vec ? vec + 3 * b : nullptr, cap};
 }
 
-// Correctly rounded square root of a finite x >= 0: the hardware root (within
-// one ulp) and one residual test on each neighbour, r*r against x with a
-// single rounding (fma). The library's sqrtf adds denormal scaling and special
-// cases that squared distances below the cutoff never need.
-__device__ __forceinline__ float sqrt_rn_finite(float x) {
-    const float r = __builtin_amdgcn_sqrtf(x);
-    const float rm = __uint_as_float(__float_as_uint(r) - 1u);
-    const float rp = __uint_as_float(__float_as_uint(r) + 1u);
-    const float lo = fmaf(-rm, r, x) <= 0.0f ? rm : r;   // x at or below the rm..r midpoint squared
-    return fmaf(-rp, r, x) > 0.0f ? rp : lo;             // x above the r..rp midpoint squared
-}
-
 __device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t src_atom, int32_t dst_atom,
                                            const Pair& P, const ImageEntry& t, float l2) {
     const int32_t tpk = t.tpk;
