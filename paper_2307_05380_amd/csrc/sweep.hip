@@ -391,7 +391,16 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__
     if (partials && rep && (int64_t)blockIdx.x == last) {
         // the sweep's per-wave candidate counts, summed here instead of in a launch of their own
         int64_t c = 0;
-        for (int q = threadIdx.x; q < np; q += 256) c += partials[q];
+        for (int q0 = 0; q0 < np; q0 += 256 * 8) {   // eight independent loads per round
+            int64_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int q = q0 + k * 256 + threadIdx.x;
+                v[k] = q < np ? partials[q] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) c += v[k];
+        }
         c = block_sum_256(c, sh);
         if (threadIdx.x == 0) rep->candidates += c;
     }
@@ -417,7 +426,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(const int64_t* __restrict_
                                                       mg_report* __restrict__ rep) {
     __shared__ int64_t sh[4];
     int64_t v = 0;
-    for (int q = threadIdx.x; q < n; q += 256) v += p[q];
+    for (int q0 = 0; q0 < n; q0 += 256 * 8) {   // eight independent loads per round
+        int64_t u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = q0 + k * 256 + threadIdx.x;
+            u[k] = q < n ? p[q] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v += u[k];
+    }
     v = wave_sum_i64(v);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
