@@ -91,3 +91,33 @@ def test_vec_full_batch_sampled():
         worst = max(worst, float(np.abs(vec[e0:e1] - v64).max()))
     print("worst vector error over", len(sample), "structures:", worst)
     assert worst <= 2e-5
+
+
+def test_vec_capacity_overflow_and_empty():
+    """With too few edge slots the vector call writes the plain call's first
+    `capacity` edges and vectors (nothing past them) and flags the overflow;
+    an empty batch and a zero capacity are accepted."""
+    b = inputs.make_config(2)
+    L, X, P = gu.dev(b)
+    full = graph.cutoff_graph(L, X, P, b.cutoff)
+    E = full.num_edges
+    cap = 100
+    bld = graph.CutoffBuilder(b.B, b.N, cap + 8, full.report.images_needed, "cuda", vec=True)
+    bld.capacity = cap   # the outputs hold 8 guard slots past the capacity
+    for t in (bld.src, bld.dst, bld.image):
+        t.fill_(-7)
+    bld.length.fill_(-7.0)
+    bld.vec.fill_(-7.0)
+    bld.run(L, X, P, b.cutoff)
+    rep = bld.report()
+    assert rep.flags & _lib.MG_FLAG_CAPACITY and rep.num_edges == E
+    assert (bld.src[cap:] == -7).all() and (bld.vec[cap:] == -7.0).all() and (bld.length[cap:] == -7.0).all()
+    for a, r in ((bld.src, full.src), (bld.dst, full.dst), (bld.image, full.image), (bld.length, full.length)):
+        assert torch.equal(a[:cap], r[:cap])
+    s, d, t = (x[:cap].cpu().numpy() for x in (full.src, full.dst, full.image))
+    v64, _ = oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, s, d, t)
+    assert np.abs(bld.vec[:cap].cpu().numpy() - v64).max() <= 2e-5
+    # zero capacity: only the report
+    z = graph.CutoffBuilder(b.B, b.N, 0, full.report.images_needed, "cuda", vec=True)
+    z.run(L, X, P, b.cutoff)
+    assert z.report().num_edges == E
