@@ -432,6 +432,9 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
                                                      dst, image, length, vec, w.ctr, report, w.partials, grid, s);
                })) != hipSuccess)
         return hip_fail(e, "cell-list fill");
+    if ((e = phase("cutoff.src", s, [&] { return mg::launch_src_from_rows(offs, N, capacity, src, s); })) !=
+        hipSuccess)
+        return hip_fail(e, "src");
     return MG_OK;
 }
 

@@ -290,8 +290,7 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                         const int64_t e = base + run + mbcnt(msk);
                         if (e < capacity) {
                             const int32_t shj = w.atom_shift[j];
-                            src[e] = (int32_t)i;
-                            dst[e] = j;
+                            dst[e] = j;   // (src comes from row_ptr after the fill)
                             image[3 * e] = u0 - unpack_t0(shj) + si0;
                             image[3 * e + 1] = u1 - unpack_t1(shj) + si1;
                             image[3 * e + 2] = u2 - unpack_t2(shj) + si2;

@@ -269,6 +269,8 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
                                int32_t* src, int32_t* dst, int32_t* image, float* length, float* vec,
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
                                hipStream_t s);
+// src[e] = i for every edge e of source i (offsets = row_ptr), e < capacity.
+hipError_t launch_src_from_rows(const int64_t* offsets, int64_t N, int64_t capacity, int32_t* src, hipStream_t s);
 // Exclusive scan of counts[0..N) into offsets[0..N]; with a report, also
 // records the total as num_edges and flags a capacity overflow, and adds the
 // np per-wave candidate counts in partials (if given) to report->candidates.

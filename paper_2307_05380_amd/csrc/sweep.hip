@@ -124,7 +124,7 @@ __device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t 
     if (e >= o.cap) return;
     // 32-bit byte offsets from the scalar bases (an item's edges are far fewer than 2^28)
     const uint32_t b4 = e << 2, b12 = (e << 3) + (e << 2);
-    *(int32_t*)((char*)o.src + b4) = src_atom;
+    (void)src_atom;   // src is written densely from row_ptr after the fill (k_src_from_rows)
     *(int32_t*)((char*)o.dst + b4) = dst_atom;
     int32_t* im = (int32_t*)((char*)o.image + b12);
     constexpr int32_t mask = (1 << TBITS) - 1;   // t - w from the biased fields
@@ -305,6 +305,24 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
         else MG_SWEEP(MODE_FILL, 4);
     }
 #undef MG_SWEEP
+    return hipGetLastError();
+}
+
+// src of every cutoff edge from row_ptr, one wave per source with full-wave
+// coalesced stores: the fill writes no src (a sparse store fewer per hit step).
+__global__ __launch_bounds__(256) void k_src_from_rows(const int64_t* __restrict__ offsets, int64_t N,
+                                                       int64_t capacity, int32_t* __restrict__ src) {
+    const int lane = lane_id();
+    for (int64_t i = grid_wave(); i < N; i += grid_waves()) {
+        const int64_t e1 = min(offsets[i + 1], capacity);
+        for (int64_t e = offsets[i] + lane; e < e1; e += WAVE) src[e] = (int32_t)i;
+    }
+}
+
+hipError_t launch_src_from_rows(const int64_t* offsets, int64_t N, int64_t capacity, int32_t* src, hipStream_t s) {
+    if (N == 0 || capacity == 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>((N + 3) / 4, (int64_t)device_cu_count() * 16);
+    hipLaunchKernelGGL(k_src_from_rows, dim3((unsigned)g), dim3(256), 0, s, offsets, N, capacity, src);
     return hipGetLastError();
 }
 
