@@ -37,7 +37,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 # algorithmic work per unit: bytes per edge / flops per candidate
-BYTES_PER_EDGE_FILL = 24.0     # src, dst (4+4), image (12), length (4)
+BYTES_PER_EDGE_FILL = 20.0     # dst (4), image (12), length (4); src is stored by its own kernel
+BYTES_PER_EDGE_SRC = 4.0       # src, written from the row offsets after the fill
 BYTES_PER_EDGE_VEC = 12.0      # the edge vector, when the fill emits it
 BYTES_PER_EDGE_GEOM = 36.0     # forward: read src, dst, image (20) + write vec, length (16)
 BYTES_PER_EDGE_GEOM_BWD = 24.0 # backward with the length gradient only: read src, dst, image (20) + grad (4)
@@ -324,6 +325,7 @@ def main(argv=None):
     per = {}
     work = {
         "cutoff.fill": ("hbm", (BYTES_PER_EDGE_FILL + (BYTES_PER_EDGE_VEC if fused else 0.0)) * E),
+        "cutoff.src": ("hbm", BYTES_PER_EDGE_SRC * E),
         "cutoff.count": ("alu", FLOPS_PER_CANDIDATE * rep_c.candidates),
         "knn.select": ("alu", FLOPS_PER_CANDIDATE * rep_k.candidates),
         "geometry.fwd": ("hbm", BYTES_PER_EDGE_GEOM * E),

@@ -136,6 +136,7 @@ mg::ImageTables carve_images(Carver& c, size_t bytes) {
 struct CutoffWs {
     mg::Counters* ctr;
     mg::StructInfo* info;
+    mg::PlanRow* plan;
     int64_t* item_off;
     int64_t* box_off;
     uint32_t* counts;
@@ -160,6 +161,7 @@ CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
     CutoffWs w;
     w.ctr = c.take<mg::Counters>(1);
     w.info = c.take<mg::StructInfo>((size_t)B);
+    w.plan = c.take<mg::PlanRow>((size_t)B);
     w.item_off = c.take<int64_t>((size_t)B + 1);
     w.box_off = c.take<int64_t>((size_t)B + 1);
     w.counts = c.take<uint32_t>((size_t)N);
@@ -176,6 +178,7 @@ CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
 struct KnnWs {
     mg::Counters* ctr;
     mg::StructInfo* info;
+    mg::PlanRow* plan;
     int64_t* item_off;
     int64_t* box_off;
     int32_t* ext_list;
@@ -190,6 +193,7 @@ KnnWs carve_knn(void* ws, size_t bytes, int B, int64_t N) {
     KnnWs w;
     w.ctr = c.take<mg::Counters>(1);
     w.info = c.take<mg::StructInfo>((size_t)B);
+    w.plan = c.take<mg::PlanRow>((size_t)B);
     w.item_off = c.take<int64_t>((size_t)B + 1);
     w.box_off = c.take<int64_t>((size_t)B + 1);
     w.ext_list = c.take<int32_t>((size_t)N);
@@ -389,11 +393,11 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
     const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
     if ((e = phase("cutoff.bounds", s, [&] {
              return mg::launch_bounds(lattices, batch_ptr, frac, B, N, cutoff, radii, thr, 0, 0.f, w.info,
-                                      w.ctr, report, 0, opts, s);
+                                      w.plan, w.ctr, report, 0, opts, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("cutoff.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
+             return mg::launch_struct_scan(B, w.info, w.plan, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
          })) != hipSuccess)
         return hip_fail(e, "plan");
     if ((e = phase("cutoff.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.img, s); })) !=
@@ -512,11 +516,11 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
     const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
     if ((e = phase("knn.bounds", s, [&] {
              return mg::launch_bounds(lattices, batch_ptr, frac, B, N, 0.f, nullptr, nullptr, k, lambda,
-                                      w.info, w.ctr, report, 1, opts, s);
+                                      w.info, w.plan, w.ctr, report, 1, opts, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("knn.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
+             return mg::launch_struct_scan(B, w.info, w.plan, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
          })) != hipSuccess)
         return hip_fail(e, "plan");
     if ((e = phase("knn.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.img, s); })) !=

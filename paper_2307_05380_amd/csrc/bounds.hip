@@ -60,7 +60,7 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
                                                const float* __restrict__ frac, int B, float radius,
                                                const float* __restrict__ radii, float* __restrict__ thr,
                                                int knn_k, float knn_lambda,
-                                               StructInfo* __restrict__ info,
+                                               StructInfo* __restrict__ info, PlanRow* __restrict__ plan,
                                                mg_report* __restrict__ rep, int mode, int opts) {
     const int b = blockIdx.x;
     if (b >= B) return;
@@ -225,18 +225,19 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     si.wcl = (float)(wcl * (1.0 - 1e-6) - 1e-3);
     if (use_cl) si.groups = 0;
     info[b] = si;
+    plan[b] = PlanRow{(int32_t)si.box, si.groups, (int32_t)si.cl_items, (int32_t)si.nbins};
     if (flags) atomicOr(&rep->flags, flags);
 }
 
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
                          int64_t N, float radius, const float* radii, float* thr, int knn_k,
-                         float knn_lambda, StructInfo* info, Counters* ctr, mg_report* report, int mode,
+                         float knn_lambda, StructInfo* info, PlanRow* plan, Counters* ctr, mg_report* report, int mode,
                          int opts, hipStream_t s) {
     (void)N;
     (void)ctr;
     if (B == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bounds, dim3(B), dim3(64), 0, s, lattices, batch_ptr, frac, B, radius, radii, thr,
-                       knn_k, knn_lambda, info, report, mode, opts);
+                       knn_k, knn_lambda, info, plan, report, mode, opts);
     return hipGetLastError();
 }
 
@@ -250,6 +251,7 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
 constexpr int SCAN_PER = 4;
 
 __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restrict__ info,
+                                                      const PlanRow* __restrict__ plan,
                                                       int64_t* __restrict__ item_off,
                                                       int64_t* __restrict__ cl_off,
                                                       int64_t* __restrict__ box_off,
@@ -270,11 +272,11 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
         for (int u = 0; u < SCAN_PER; ++u) {
             const int b = base + t * SCAN_PER + u;
             const bool in = b < B;
-            const StructInfo* si = info + (in ? b : 0);
-            v[u][0] = in ? si->box : 0;
-            v[u][1] = in ? si->groups : 0;
-            v[u][2] = in ? si->cl_items : 0;
-            v[u][3] = in ? si->nbins : 0;
+            const PlanRow pr = plan[in ? b : 0];   // four consecutive rows per thread: coalesced
+            v[u][0] = in ? pr.box : 0;
+            v[u][1] = in ? pr.groups : 0;
+            v[u][2] = in ? pr.cl_items : 0;
+            v[u][3] = in ? pr.nbins : 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) tot[q] += v[u][q];
         }
@@ -296,8 +298,7 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
             const int b = base + t * SCAN_PER + u;
             if (b < B) {
                 const int64_t off = pre[0];
-                info[b].img_off = off;
-                box_off[b] = off;
+                box_off[b] = off;   // the image scatter turns it into the table offset
                 if (off + v[u][0] > capacity && v[u][0] > 0) {
                     overflow = true;
                     info[b].box = 0;           // skipped: no images; its items write empty results
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
                 }
                 item_off[b] = pre[1];
                 if (cl_off) cl_off[b] = pre[2];
-                info[b].bin_off = pre[3];
+                if (v[u][3] > 0) info[b].bin_off = pre[3];   // read by the cell-list kernels only
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) pre[q] += v[u][q];
@@ -332,10 +333,10 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
 
 // Skipped structures keep their planned item ranges, so item_off stays a plain
 // scan of the planned items.
-hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, int64_t* cl_off,
+hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t* item_off, int64_t* cl_off,
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_struct_scan, dim3(1), dim3(1024), 0, s, B, info, item_off, cl_off, box_off, ctr,
+    hipLaunchKernelGGL(k_struct_scan, dim3(1), dim3(1024), 0, s, B, info, plan, item_off, cl_off, box_off, ctr,
                        report, image_capacity);
     return hipGetLastError();
 }
@@ -478,6 +479,7 @@ __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __
 // offset of its compacted images, their number and the index of t = 0 (the
 // box centre, always kept).
 __global__ __launch_bounds__(256) void k_image_scatter(int B, StructInfo* __restrict__ info,
+                                                       const int64_t* __restrict__ box_off,
                                                        const Counters* __restrict__ ctr,
                                                        const ImageEntry* __restrict__ table,
                                                        const uint32_t* __restrict__ kflag,
@@ -490,7 +492,7 @@ __global__ __launch_bounds__(256) void k_image_scatter(int B, StructInfo* __rest
         if (kflag[idx]) ctable[kscan[idx]] = table[idx];
     for (int64_t b = t0; b < B; b += stride) {
         StructInfo& si = info[b];
-        const int64_t box = si.box, off = si.img_off;
+        const int64_t box = si.box, off = box_off[b];
         if (box == 0 || off + box > capacity) {
             si.images = 0;
             si.zero_img = -1;
@@ -512,7 +514,7 @@ hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const 
     // the scan covers the batch's boxes only (their total is known on the device)
     hipError_t e = launch_scan_counts(t.kflag, t.cap, t.kscan, t.kbsum, INT64_MAX, nullptr, s, &ctr->total_box);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_image_scatter, dim3(grid), dim3(256), 0, s, B, info, ctr, t.box, t.kflag, t.kscan, t.table,
+    hipLaunchKernelGGL(k_image_scatter, dim3(grid), dim3(256), 0, s, B, info, box_off, ctr, t.box, t.kflag, t.kscan, t.table,
                        t.cap);
     return hipGetLastError();
 }

@@ -60,6 +60,15 @@ struct alignas(16) StructInfo {
 
 constexpr int CL_MIN_ATOMS = 512;   // structures smaller than this use the image sweep
 
+// The per-structure quantities the batch plan scans, packed for coalesced
+// loads (written by the bounds kernel next to StructInfo).
+struct alignas(16) PlanRow {
+    int32_t box;        // StructInfo::box (at most 1023^3)
+    int32_t groups;
+    int32_t cl_items;
+    int32_t nbins;
+};
+
 // Scratch counters at the head of every workspace.
 struct alignas(64) Counters {
     uint32_t spare[8];
@@ -212,9 +221,9 @@ namespace mg {
 // the per-atom threshold on l^2 and the structure's radius is its largest c_a.
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
                          int64_t N, float radius, const float* radii, float* thr, int knn_k,
-                         float knn_lambda, StructInfo* info, Counters* ctr, mg_report* report, int mode,
+                         float knn_lambda, StructInfo* info, PlanRow* plan, Counters* ctr, mg_report* report, int mode,
                          int opts, hipStream_t s);
-hipError_t launch_struct_scan(int B, StructInfo* info, int64_t* item_off, int64_t* cl_off,
+hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t* item_off, int64_t* cl_off,
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
                               hipStream_t s);
 struct ClWs {

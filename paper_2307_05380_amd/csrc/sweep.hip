@@ -308,14 +308,24 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
     return hipGetLastError();
 }
 
-// src of every cutoff edge from row_ptr, one wave per source with full-wave
-// coalesced stores: the fill writes no src (a sparse store fewer per hit step).
+// src of every cutoff edge from row_ptr: the fill writes no src (a sparse store
+// fewer per hit step). One source per wave iteration, written with full-wave
+// stores; the row bounds are wave-uniform and come through scalar loads, which
+// wait on their own counter, so the next row's bounds never wait for this
+// row's stores.
+typedef const __attribute__((address_space(4))) int64_t* ConstI64;
+
 __global__ __launch_bounds__(256) void k_src_from_rows(const int64_t* __restrict__ offsets, int64_t N,
                                                        int64_t capacity, int32_t* __restrict__ src) {
     const int lane = lane_id();
+    const uint64_t a = (uint64_t)offsets;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    ConstI64 off = (ConstI64)(((uint64_t)hi << 32) | lo);
     for (int64_t i = grid_wave(); i < N; i += grid_waves()) {
-        const int64_t e1 = min(offsets[i + 1], capacity);
-        for (int64_t e = offsets[i] + lane; e < e1; e += WAVE) src[e] = (int32_t)i;
+        const int64_t e0 = off[i];
+        const int64_t e1 = min(off[i + 1], capacity);
+        for (int64_t e = e0 + lane; e < e1; e += WAVE) src[e] = (int32_t)i;
     }
 }
 
