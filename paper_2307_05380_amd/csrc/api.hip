@@ -137,9 +137,10 @@ struct CutoffWs {
     mg::Counters* ctr;
     mg::StructInfo* info;
     mg::PlanRow* plan;
-    int64_t* item_off;
+    int64_t* item_off;   // sweep items: (structure, source group, image chunk)
     int64_t* box_off;
     uint32_t* counts;
+    uint32_t* ccount;    // per-(source, image chunk) counts of chunked structures
     int64_t* offsets;
     int64_t* bsum;
     int64_t* partials;
@@ -165,6 +166,7 @@ CutoffWs carve_cutoff(void* ws, size_t bytes, int B, int64_t N) {
     w.item_off = c.take<int64_t>((size_t)B + 1);
     w.box_off = c.take<int64_t>((size_t)B + 1);
     w.counts = c.take<uint32_t>((size_t)N);
+    w.ccount = c.take<uint32_t>(4 * (size_t)N + 256);   // per-(source, image chunk) counts
     w.offsets = c.take<int64_t>((size_t)N + 1);
     w.bsum = c.take<int64_t>((size_t)mg::scan_block_count(N) + 1);
     w.partials = c.take<int64_t>(2 * (size_t)mg::MAX_GRID_WAVES);   // image and cell-list sweeps
@@ -397,7 +399,7 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("cutoff.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.plan, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
+             return mg::launch_struct_scan(B, w.info, w.plan, 4 * N + 256, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
          })) != hipSuccess)
         return hip_fail(e, "plan");
     if ((e = phase("cutoff.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.img, s); })) !=
@@ -409,9 +411,11 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
     // per-wave candidate counts: the image sweep's in partials[0, 4 grid), the
     // cell-list sweep's after them; the scan adds them to the report
     if ((e = phase("cutoff.count", s, [&] {
-             return mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.img.table, frac, c2, thr, w.counts, offs,
-                                            capacity, src, dst, image, length, vec, w.ctr, report, w.partials,
-                                            grid, tu.cutoff_slots, s);
+             const hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.ccount, w.img.table, frac, c2,
+                                                          thr, w.counts, offs, capacity, src, dst, image, length, vec,
+                                                          w.ctr, report, w.partials, grid, tu.cutoff_slots, s);
+             // row totals and in-row offsets of the image-chunked structures
+             return r != hipSuccess ? r : mg::launch_chunk_prefix(B, w.info, w.counts, w.ccount, s);
          })) != hipSuccess)
         return hip_fail(e, "count");
     if (cl && (e = phase("cutoff.cells.count", s, [&] {
@@ -426,7 +430,7 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
          })) != hipSuccess)
         return hip_fail(e, "scan");
     if ((e = phase("cutoff.fill", s, [&] {
-             return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.img.table, frac, c2, thr, w.counts, offs,
+             return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.ccount, w.img.table, frac, c2, thr, w.counts, offs,
                                             capacity, src, dst, image, length, vec, w.ctr, report, w.partials,
                                             grid, tu.cutoff_slots, s);
          })) != hipSuccess)
@@ -520,7 +524,7 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("knn.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.plan, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
+             return mg::launch_struct_scan(B, w.info, w.plan, 0, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
          })) != hipSuccess)
         return hip_fail(e, "plan");
     if ((e = phase("knn.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.img, s); })) !=

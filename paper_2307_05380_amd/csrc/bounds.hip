@@ -224,8 +224,13 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     si.cl_items = use_cl ? n : 0;
     si.wcl = (float)(wcl * (1.0 - 1e-6) - 1e-3);
     if (use_cl) si.groups = 0;
+    si.chunks = 1;
+    si.pad0 = 0;
+    si.xoff = 0;
     info[b] = si;
-    plan[b] = PlanRow{(int32_t)si.box, si.groups, (int32_t)si.cl_items, (int32_t)si.nbins};
+    const int64_t per = (n <= WAVE) ? (int64_t)min(si.G, n) : 1;   // sources of one group
+    const int64_t cost = (si.box > 0 && si.groups > 0) ? per * n * si.box : 0;
+    plan[b] = PlanRow{(int32_t)si.box, si.groups, (int32_t)si.cl_items, (int32_t)si.nbins, cost, n, 0};
     if (flags) atomicOr(&rep->flags, flags);
 }
 
@@ -248,48 +253,100 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
 // box does not fit the table capacity are skipped and flagged. Each thread
 // takes SCAN_PER consecutive structures per chunk, so a batch of up to
 // 1024 * SCAN_PER structures is one round of loads (all in flight together).
+//
+// Image chunks (chunk_cap > 0, the cutoff sweeps): the items of a batch differ
+// in cost by orders of magnitude (densities and sizes spread over decades), and
+// one source group is the smallest unit without chunks. A structure whose
+// source group costs more than target = (total cost) / CHUNK_TARGET_DIV gets
+// C = ceil(cost / target) chunks (at most MAX_CHUNKS and the box size), i.e. C
+// items per source group over consecutive ranges of its image table, and
+// n * C per-(source, chunk) count slots from a pool of chunk_cap entries; while
+// the slots would not fit, the target doubles.
 constexpr int SCAN_PER = 4;
+constexpr int SCAN_Q = 5;   // box, items, cell-list items, bins, chunk count slots
+
+__device__ inline int plan_chunks(const PlanRow& pr, int64_t target) {
+    if (target <= 0 || pr.cost <= target) return 1;
+    const double c = ceil((double)pr.cost / (double)target);   // FP64: no 64-bit integer division
+    return (int)fmax(fmin(fmin(c, (double)MAX_CHUNKS), (double)(pr.box / CHUNK_MIN_BOX)), 1.0);
+}
 
 __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restrict__ info,
-                                                      const PlanRow* __restrict__ plan,
+                                                      const PlanRow* __restrict__ plan, int64_t chunk_cap,
                                                       int64_t* __restrict__ item_off,
                                                       int64_t* __restrict__ cl_off,
                                                       int64_t* __restrict__ box_off,
                                                       Counters* __restrict__ ctr,
                                                       mg_report* __restrict__ rep,
                                                       int64_t capacity) {
-    __shared__ int64_t s_part[4][16];
-    __shared__ int64_t s_base[4];
+    __shared__ int64_t s_part[SCAN_Q][16];
+    __shared__ int64_t s_base[SCAN_Q];
+    __shared__ int64_t s_red[16];
+    __shared__ double s_redf[16];
+    __shared__ int64_t s_target;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    if (t < 4) s_base[t] = 0;
+    if (t < SCAN_Q) s_base[t] = 0;
+    // chunk target: total cost, then doubled until the count slots fit
+    int64_t target = 0;
+    if (chunk_cap > 0) {
+        double c = 0.0;   // FP64: the sum is a heuristic and must not overflow
+        for (int b = t; b < B; b += 1024) c += (double)plan[b].cost * (double)plan[b].groups;
+        c = wave_sum_f64(c);
+        if (lane == 0) s_redf[w] = c;
+        __syncthreads();
+        if (t == 0) {
+            double tot = 0.0;
+            for (int r = 0; r < 16; ++r) tot += s_redf[r];
+            s_target = (int64_t)fmin(fmax(tot / (double)CHUNK_TARGET_DIV, 1.0), 9.0e18);
+        }
+        __syncthreads();
+        target = s_target;
+        for (int it = 0; it < 64; ++it) {
+            int64_t x = 0;
+            for (int b = t; b < B; b += 1024) {
+                const int cb = plan_chunks(plan[b], target);
+                if (cb > 1) x += (int64_t)plan[b].n * cb;
+            }
+            x = wave_sum_i64(x);
+            __syncthreads();   // s_red reuse
+            if (lane == 0) s_red[w] = x;
+            __syncthreads();
+            int64_t tot = 0;
+            for (int r = 0; r < 16; ++r) tot += s_red[r];
+            if (tot <= chunk_cap) break;   // uniform over the workgroup
+            target = target > (INT64_MAX >> 1) ? INT64_MAX : target * 2;
+        }
+    }
     __syncthreads();
     bool overflow = false;
     for (int base = 0; base < B; base += 1024 * SCAN_PER) {
-        // scanned quantities: image box, image items, cell-list items, bins
-        int64_t v[SCAN_PER][4];
-        int64_t tot[4] = {0, 0, 0, 0};
+        int64_t v[SCAN_PER][SCAN_Q];
+        int ch[SCAN_PER];
+        int64_t tot[SCAN_Q] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int u = 0; u < SCAN_PER; ++u) {
             const int b = base + t * SCAN_PER + u;
             const bool in = b < B;
             const PlanRow pr = plan[in ? b : 0];   // four consecutive rows per thread: coalesced
+            ch[u] = (in && chunk_cap > 0) ? plan_chunks(pr, target) : 1;
             v[u][0] = in ? pr.box : 0;
-            v[u][1] = in ? pr.groups : 0;
+            v[u][1] = in ? (int64_t)pr.groups * ch[u] : 0;
             v[u][2] = in ? pr.cl_items : 0;
             v[u][3] = in ? pr.nbins : 0;
+            v[u][4] = ch[u] > 1 ? (int64_t)pr.n * ch[u] : 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) tot[q] += v[u][q];
+            for (int q = 0; q < SCAN_Q; ++q) tot[q] += v[u][q];
         }
-        int64_t inc[4];
+        int64_t inc[SCAN_Q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < SCAN_Q; ++q) {
             inc[q] = wave_incl_scan_i64(tot[q]);
             if (lane == 63) s_part[q][w] = inc[q];
         }
         __syncthreads();
-        int64_t pre[4];
+        int64_t pre[SCAN_Q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < SCAN_Q; ++q) {
             pre[q] = s_base[q] + inc[q] - tot[q];
             for (int r = 0; r < w; ++r) pre[q] += s_part[q][r];
         }
@@ -307,14 +364,18 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
                 item_off[b] = pre[1];
                 if (cl_off) cl_off[b] = pre[2];
                 if (v[u][3] > 0) info[b].bin_off = pre[3];   // read by the cell-list kernels only
+                if (ch[u] > 1) {
+                    info[b].chunks = ch[u];
+                    info[b].xoff = pre[4];
+                }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) pre[q] += v[u][q];
+            for (int q = 0; q < SCAN_Q; ++q) pre[q] += v[u][q];
         }
         __syncthreads();
         if (t == 1023) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s_base[q] = pre[q];
+            for (int q = 0; q < SCAN_Q; ++q) s_base[q] = pre[q];
         }
         __syncthreads();
     }
@@ -333,10 +394,11 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
 
 // Skipped structures keep their planned item ranges, so item_off stays a plain
 // scan of the planned items.
-hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t* item_off, int64_t* cl_off,
+hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t chunk_cap, int64_t* item_off,
+                              int64_t* cl_off,
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_struct_scan, dim3(1), dim3(1024), 0, s, B, info, plan, item_off, cl_off, box_off, ctr,
+    hipLaunchKernelGGL(k_struct_scan, dim3(1), dim3(1024), 0, s, B, info, plan, chunk_cap, item_off, cl_off, box_off, ctr,
                        report, image_capacity);
     return hipGetLastError();
 }

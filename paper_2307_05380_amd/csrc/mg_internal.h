@@ -39,7 +39,10 @@ struct alignas(16) StructInfo {
     int32_t images;     // entries kept in the table
     int32_t zero_img;   // table index of t = 0 (-1 if absent)
     int32_t G;          // sources per work item
-    int32_t groups;     // work items
+    int32_t groups;     // source groups (work items before image chunks)
+    int32_t chunks;     // image chunks per source group in the cutoff sweeps (1 unless the plan splits)
+    int32_t pad0;
+    int64_t xoff;       // chunks > 1: first of this structure's per-(source, chunk) counts
     float R;            // radius the table was built for, with rounding margin (Angstrom)
     float Rs;           // search radius before the margin (Angstrom)
     uint32_t flags;     // MG_FLAG_* of this structure
@@ -67,7 +70,16 @@ struct alignas(16) PlanRow {
     int32_t groups;
     int32_t cl_items;
     int32_t nbins;
+    int64_t cost;       // candidates of one source group over the whole box (0: no image sweep)
+    int32_t n;
+    int32_t pad;
 };
+
+// Image chunks: a structure whose source groups are heavy gets its image table
+// cut into up to MAX_CHUNKS consecutive ranges, each a work item of its own.
+constexpr int MAX_CHUNKS = 64;
+constexpr int64_t CHUNK_TARGET_DIV = 65536;   // target item cost = total cost / this
+constexpr int CHUNK_MIN_BOX = 64;             // at most box / this chunks (short image ranges cost setup)
 
 // Scratch counters at the head of every workspace.
 struct alignas(64) Counters {
@@ -223,7 +235,8 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
                          int64_t N, float radius, const float* radii, float* thr, int knn_k,
                          float knn_lambda, StructInfo* info, PlanRow* plan, Counters* ctr, mg_report* report, int mode,
                          int opts, hipStream_t s);
-hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t* item_off, int64_t* cl_off,
+hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t chunk_cap, int64_t* item_off,
+                              int64_t* cl_off,
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
                               hipStream_t s);
 struct ClWs {
@@ -272,7 +285,8 @@ constexpr int64_t IMAGE_FIXED_BYTES = 4096;
 hipError_t launch_images(int B, StructInfo* info, const int64_t* box_off, const Counters* ctr, const ImageTables& t,
                          hipStream_t s);
 // vec (nullable, float [capacity][3]): the fill also writes every edge's vector.
-hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
+hipError_t launch_chunk_prefix(int B, const StructInfo* info, uint32_t* counts, uint32_t* ccount, hipStream_t s);
+hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off, uint32_t* ccount,
                                const ImageEntry* table, const float* frac, float c2thr,
                                const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
                                int32_t* src, int32_t* dst, int32_t* image, float* length, float* vec,

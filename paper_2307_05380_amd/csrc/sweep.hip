@@ -144,42 +144,79 @@ __device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t 
 
 constexpr int MODE_COUNT = 0, MODE_FILL = 1;
 
+// Work item = (structure, source group, image chunk). A structure with C > 1
+// image chunks splits its table into C consecutive index ranges
+// [k I / C, (k+1) I / C); chunk 0 also takes t = 0 first, and no other chunk
+// visits t = 0, so a source's chunks, in order, visit exactly the images of the
+// unchunked sweep in the same order, and a heavy source group is spread over C
+// waves. The count pass writes one count per (source, chunk) into ccount;
+// k_chunk_prefix turns them into row totals (counts, scanned into row_ptr) and
+// offsets inside the row, and the fill starts chunk k of source i at
+// row_ptr[i] + that offset.
 template <int MODE, int SLOTS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_cutoff_sweep(
     int B, const StructInfo* __restrict__ info, const int64_t* __restrict__ item_off,
-    const ImageEntry* __restrict__ table, const float* __restrict__ frac, float c2thr,
+    uint32_t* __restrict__ ccount, const ImageEntry* __restrict__ table,
+    const float* __restrict__ frac, float c2thr,
     const float* __restrict__ thr, uint32_t* __restrict__ counts, const int64_t* __restrict__ offsets, int64_t capacity,
     int32_t* __restrict__ src, int32_t* __restrict__ dst, int32_t* __restrict__ image,
     float* __restrict__ length, float* __restrict__ vec, Counters* __restrict__ ctr, mg_report* __restrict__ rep,
     int64_t* __restrict__ partials) {
     const int lane = lane_id();
-    const int64_t total = item_off[B];
+    const int64_t* ioff = item_off;
+    const int64_t total = ioff[B];
     int64_t ncand = 0;
     for (int64_t q = grid_wave(); q < total; q += grid_waves()) {
-        int lo = 0, hi = B;   // item_off[lo] <= q < item_off[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (item_off[mid] <= q) lo = mid;
-            else hi = mid;
-        }
+        // ioff[lo] <= q < ioff[lo + 1], found by the whole wave in about
+        // log65(B) dependent loads (a binary search would chain log2(B))
+        const int lo = __builtin_amdgcn_readfirstlane(wave_search_le(ioff, B, q, lane));
         const StructInfo* si = info + lo;
         const int n = si->n;
         const int G = si->G;
-        const int i_first = (int)(q - item_off[lo]) * G;
+        const int C = si->chunks;
+        const int li = (int)(q - ioff[lo]);
+        const int grp = C == 1 ? li : li / C;
+        const int ck_beg = li - grp * C;   // this item's image chunk
+        const int ck_end = ck_beg + 1;
+        const int i_first = grp * G;
         const int nsrc = min(G, n - i_first);
         const int64_t atom0 = si->atom0;
+        const int64_t xoff = si->xoff;
         const int I = si->box == 0 ? 0 : si->images;
         const int zimg = si->zero_img;
         const ImageEntry* tab = table + si->img_off;
         double L[9];
 #pragma unroll
         for (int r = 0; r < 9; ++r) L[r] = si->L[r];
+        // (count) where the count of local source a in this item's chunk goes
+        auto cslot = [&](int a) -> uint32_t* {
+            return C == 1 ? counts + atom0 + a : ccount + xoff + (int64_t)a * C + ck_beg;
+        };
 
         if (I == 0 || zimg < 0) {
-            if (MODE == MODE_COUNT && lane < nsrc) counts[atom0 + i_first + lane] = 0u;
+            if (MODE == MODE_COUNT && lane < nsrc) *cslot(i_first + lane) = 0u;
             continue;
         }
-        ncand += (int64_t)nsrc * n * I;
+        // chunk ck's table range; t = 0 goes to chunk 0 only
+        auto visit = [&](int ck, auto& step_x, auto& step) {
+            const int k0 = (int)((int64_t)ck * I / C), k1 = (int)((int64_t)(ck + 1) * I / C);
+            if (ck == 0) step_x(tab[zimg], true);
+            if (zimg >= k0 && zimg < k1) {
+                for_images(tab + k0, zimg - k0, step);
+                for_images(tab + zimg + 1, k1 - zimg - 1, step);
+            } else {
+                for_images(tab + k0, k1 - k0, step);
+            }
+        };
+        {   // candidates of this item: images of its chunks
+            const int k0 = (int)((int64_t)ck_beg * I / C), k1 = (int)((int64_t)ck_end * I / C);
+            const bool zin = zimg >= k0 && zimg < k1;
+            ncand += (int64_t)nsrc * n * (k1 - k0 - (zin ? 1 : 0) + (ck_beg == 0 ? 1 : 0));
+        }
+        // (fill) start of this item's chunk of local source a in the output
+        auto cstart = [&](int a) -> int64_t {
+            return offsets[atom0 + a] + (C == 1 ? 0 : (int64_t)ccount[xoff + (int64_t)a * C + ck_beg]);
+        };
 
         if (n <= WAVE) {
             // ---- several sources per wave: lane = a * n + j
@@ -195,42 +232,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             uint64_t seg = 0;
             OutRel out{};
             if (MODE == MODE_FILL) {
-                const int64_t ibase = offsets[atom0 + i_first];
+                const int64_t ibase = cstart(i_first);
                 out = rebase(ibase, capacity, src, dst, image, length, vec);
-                base = act ? (uint32_t)(offsets[atom0 + il] - ibase) : 0u;
+                base = act ? (uint32_t)(cstart(il) - ibase) : 0u;
                 seg = (n == WAVE) ? ~0ull : (((1ull << n) - 1ull) << (a * n));
             }
             const int32_t sa = (int32_t)(atom0 + il), da = (int32_t)(atom0 + j);
             auto step_x = [&](const ImageEntry& e, bool zero) {
                 const float l2 = dist2(P, e);
                 bool hit = l2 < c2;
+                if (zero) hit = hit & !P.self;   // the excluded self-image (i, i, 0)
                 if (MODE == MODE_COUNT) {
                     cnt += hit ? 1u : 0u;
                 } else {
-                    if (zero) hit = hit & !P.self;   // the excluded self-image (i, i, 0)
                     const uint64_t m = ballot(hit) & seg;
                     if (hit) write_edge(base + run + mbcnt(m), out, sa, da, P, e, l2);
                     run += (uint32_t)__popcll(m);
                 }
             };
             auto step = [&](const ImageEntry& e) { step_x(e, false); };
+            visit(ck_beg, step_x, step);   // t = 0 first (the only image with an excluded pair), then table order
             if (MODE == MODE_COUNT) {
-                for_images(tab, I, step);
-            } else {
-                // t = 0 first (the only image with an excluded pair), then the others in order
-                step_x(tab[zimg], true);
-                for_images(tab, zimg, step);
-                for_images(tab + zimg + 1, I - zimg - 1, step);
-            }
-            if (MODE == MODE_COUNT) {
-                // the self pair at t = 0 has length exactly 0: it was counted iff 0 < c2
-                if (P.self && 0.0f < c2) cnt -= 1u;
                 const int inc = wave_incl_scan_i32(act ? (int)cnt : 0);
                 const int end = min((lane + 1) * n - 1, WAVE - 1);
                 const int beg = lane * n - 1;
                 const int hiv = __shfl(inc, end, WAVE);
                 const int lov = __shfl(inc, max(beg, 0), WAVE);
-                if (lane < nsrc) counts[atom0 + i_first + lane] = (uint32_t)(hiv - (beg >= 0 ? lov : 0));
+                if (lane < nsrc) *cslot(i_first + lane) = (uint32_t)(hiv - (beg >= 0 ? lov : 0));
             }
         } else {
             // ---- one source per item, SLOTS destinations per lane, chunks of 64*SLOTS
@@ -239,60 +267,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             uint32_t cnt = 0;   // wave-uniform in this path
             uint32_t run = 0;
             OutRel out{};
-            if (MODE == MODE_FILL) out = rebase(offsets[atom0 + il], capacity, src, dst, image, length, vec);
+            if (MODE == MODE_FILL) out = rebase(cstart(il), capacity, src, dst, image, length, vec);
             const int32_t sa = (int32_t)(atom0 + il);
-            for (int jc = 0; jc < n; jc += WAVE * SLOTS) {
-                Pair P[SLOTS];
-#pragma unroll
-                for (int r = 0; r < SLOTS; ++r) {
-                    const int j = jc + r * WAVE + lane;
-                    P[r] = make_pair(frac, L, atom0, il, j, j < n);
-                }
-                auto step_x = [&](const ImageEntry& e, bool zero) {
+            {
+                const int ck = ck_beg;
+                for (int jc = 0; jc < n; jc += WAVE * SLOTS) {
+                    Pair P[SLOTS];
 #pragma unroll
                     for (int r = 0; r < SLOTS; ++r) {
-                        const float l2 = dist2(P[r], e);
-                        bool hit = l2 < c2;
-                        if (MODE == MODE_COUNT) {
-                            cnt += (uint32_t)__popcll(ballot(hit));
-                        } else {
-                            if (zero) hit = hit & !P[r].self;
-                            const uint64_t m = ballot(hit);
-                            if (hit)
-                                write_edge(run + mbcnt(m), out, sa, (int32_t)(atom0 + jc + r * WAVE + lane), P[r],
-                                           e, l2);
-                            run += (uint32_t)__popcll(m);
-                        }
+                        const int j = jc + r * WAVE + lane;
+                        P[r] = make_pair(frac, L, atom0, il, j, j < n);
                     }
-                };
-                auto step = [&](const ImageEntry& e) { step_x(e, false); };
-                if (MODE == MODE_COUNT) {
-                    for_images(tab, I, step);
-                } else {
-                    step_x(tab[zimg], true);
-                    for_images(tab, zimg, step);
-                    for_images(tab + zimg + 1, I - zimg - 1, step);
+                    auto step_x = [&](const ImageEntry& e, bool zero) {
+#pragma unroll
+                        for (int r = 0; r < SLOTS; ++r) {
+                            const float l2 = dist2(P[r], e);
+                            bool hit = l2 < c2;
+                            if (zero) hit = hit & !P[r].self;
+                            if (MODE == MODE_COUNT) {
+                                cnt += (uint32_t)__popcll(ballot(hit));
+                            } else {
+                                const uint64_t m = ballot(hit);
+                                if (hit)
+                                    write_edge(run + mbcnt(m), out, sa, (int32_t)(atom0 + jc + r * WAVE + lane), P[r],
+                                               e, l2);
+                                run += (uint32_t)__popcll(m);
+                            }
+                        }
+                    };
+                    auto step = [&](const ImageEntry& e) { step_x(e, false); };
+                    visit(ck, step_x, step);
                 }
             }
-            if (MODE == MODE_COUNT) {
-                // the self pair at t = 0 (length exactly 0) was counted iff 0 < c2
-                if (0.0f < c2) cnt -= 1u;
-                if (lane == 0) counts[atom0 + il] = cnt;
-            }
+            if (MODE == MODE_COUNT && lane == 0) *cslot(il) = cnt;
         }
     }
     if (MODE == MODE_COUNT && lane == 0) partials[grid_wave()] = ncand;
 }
 
 hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const int64_t* item_off,
-                               const ImageEntry* table, const float* frac, float c2thr,
+                               uint32_t* ccount, const ImageEntry* table, const float* frac, float c2thr,
                                const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
                                int32_t* src, int32_t* dst, int32_t* image, float* length, float* vec,
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
                                hipStream_t s) {
     if (B == 0) return hipSuccess;
 #define MG_SWEEP(M, S)                                                                              \
-    hipLaunchKernelGGL((k_cutoff_sweep<M, S>), dim3(grid), dim3(256), 0, s, B, info, item_off, table, \
+    hipLaunchKernelGGL((k_cutoff_sweep<M, S>), dim3(grid), dim3(256), 0, s, B, info, item_off, ccount, table, \
                        frac, c2thr, thr, counts, offsets, capacity, src, dst, image, length, vec, ctr, report, \
                        partials)
     if (mode == MODE_COUNT) {
@@ -305,6 +326,38 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
         else MG_SWEEP(MODE_FILL, 4);
     }
 #undef MG_SWEEP
+    return hipGetLastError();
+}
+
+// Counts of the chunked structures: the row total of every source goes to
+// counts[src] (scanned into row_ptr next) and each (source, chunk) count is
+// replaced by the number of the source's edges in the chunks before it. One
+// wave per structure, one source per lane; unchunked structures return at once.
+__global__ __launch_bounds__(256) void k_chunk_prefix(int B, const StructInfo* __restrict__ info,
+                                                      uint32_t* __restrict__ counts, uint32_t* __restrict__ ccount) {
+    const int lane = lane_id();
+    for (int b = grid_wave(); b < B; b += grid_waves()) {
+        const StructInfo* si = info + b;
+        const int C = si->chunks;
+        if (C <= 1) continue;
+        const int n = si->n;
+        uint32_t* cc = ccount + si->xoff;
+        for (int a = lane; a < n; a += WAVE) {
+            uint32_t run = 0;
+            for (int k = 0; k < C; ++k) {
+                const uint32_t c = cc[(int64_t)a * C + k];
+                cc[(int64_t)a * C + k] = run;
+                run += c;
+            }
+            counts[si->atom0 + a] = run;
+        }
+    }
+}
+
+hipError_t launch_chunk_prefix(int B, const StructInfo* info, uint32_t* counts, uint32_t* ccount, hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>(((int64_t)B + 3) / 4, (int64_t)device_cu_count() * 8);
+    hipLaunchKernelGGL(k_chunk_prefix, dim3((unsigned)g), dim3(256), 0, s, B, info, counts, ccount);
     return hipGetLastError();
 }
 
