@@ -258,10 +258,11 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
 // in cost by orders of magnitude (densities and sizes spread over decades), and
 // one source group is the smallest unit without chunks. A structure whose
 // source group costs more than target = (total cost) / CHUNK_TARGET_DIV gets
-// C = ceil(cost / target) chunks (at most MAX_CHUNKS and the box size), i.e. C
-// items per source group over consecutive ranges of its image table, and
-// n * C per-(source, chunk) count slots from a pool of chunk_cap entries; while
-// the slots would not fit, the target doubles.
+// C = ceil(cost / target) chunks (at most MAX_CHUNKS and box / CHUNK_MIN_BOX),
+// i.e. C items per source group over consecutive ranges of its image table,
+// and n * C per-(source, chunk) count slots from a pool of chunk_cap entries;
+// while the slots would not fit, the target doubles. Cost = sources of a group
+// x destinations x box size (the pruned table size is not known yet).
 constexpr int SCAN_PER = 4;
 constexpr int SCAN_Q = 5;   // box, items, cell-list items, bins, chunk count slots
 

@@ -78,7 +78,7 @@ struct alignas(16) PlanRow {
 // Image chunks: a structure whose source groups are heavy gets its image table
 // cut into up to MAX_CHUNKS consecutive ranges, each a work item of its own.
 constexpr int MAX_CHUNKS = 64;
-constexpr int64_t CHUNK_TARGET_DIV = 65536;   // target item cost = total cost / this
+constexpr int64_t CHUNK_TARGET_DIV = 32768;   // target item cost = total cost / this
 constexpr int CHUNK_MIN_BOX = 64;             // at most box / this chunks (short image ranges cost setup)
 
 // Scratch counters at the head of every workspace.

@@ -49,6 +49,36 @@ def test_parity_config3_sampled():
     print(st, g.report)
 
 
+def test_chunk_plan_independence():
+    """The plan splits heavy source groups into image-chunk items, and how far
+    depends on the whole batch: a structure built alone (its groups are the
+    whole batch, so they are split into many chunks) and inside the
+    4096-structure batch must give bit-identical rows (same edges, same order
+    for up to 128 atoms, same FP32 lengths)."""
+    b = inputs.make_config(3)
+    g = gu.cutoff(b)
+    assert g.report.flags == 0, g.report.flag_names()
+    s, d, t, ln = gu.np_graph(g)
+    rp = g.row_ptr.cpu().numpy()
+    n = b.counts()
+    vol = np.abs(np.linalg.det(b.lattices.astype(np.float64)))
+    heavy = [int(i) for i in np.argsort(-(n.astype(np.float64) ** 2 / vol)) if n[i] <= 128][:6]
+    heavy += [int(np.argmax(n))]   # the largest structure (more than 64 destinations per source)
+    for sb in heavy:
+        a0, a1 = int(b.batch_ptr[sb]), int(b.batch_ptr[sb + 1])
+        print(f"structure {sb}: n={a1 - a0}", flush=True)
+        one = gu.cutoff(b.subset([sb]))
+        assert one.report.flags == 0, one.report.flag_names()
+        s1, d1, t1, l1 = gu.np_graph(one)
+        e0, e1 = int(rp[a0]), int(rp[a1])
+        assert one.num_edges == e1 - e0
+        assert np.array_equal(one.row_ptr.cpu().numpy(), rp[a0:a1 + 1] - e0)
+        assert np.array_equal(s1 + a0, s[e0:e1])
+        assert np.array_equal(d1 + a0, d[e0:e1])
+        assert np.array_equal(t1, t[e0:e1])
+        assert np.array_equal(l1.view(np.uint32), ln[e0:e1].view(np.uint32))
+
+
 def test_symmetry_bitwise_config3():
     """(i, j, t) is an edge iff (j, i, -t) is, with bit-identical FP32 length."""
     b = inputs.make_config(3)
