@@ -332,32 +332,47 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
 // Counts of the chunked structures: the row total of every source goes to
 // counts[src] (scanned into row_ptr next) and each (source, chunk) count is
 // replaced by the number of the source's edges in the chunks before it. One
-// wave per structure, one source per lane; unchunked structures return at once.
+// workgroup per structure (unchunked structures return at once); a wave takes
+// blocks of floor(64 / C) sources, lane = (source, chunk), and turns the block
+// into in-row offsets with one segmented wave scan. The four waves take every
+// fourth block, and each loads its next block before storing the current one.
 __global__ __launch_bounds__(256) void k_chunk_prefix(int B, const StructInfo* __restrict__ info,
                                                       uint32_t* __restrict__ counts, uint32_t* __restrict__ ccount) {
-    const int lane = lane_id();
-    for (int b = grid_wave(); b < B; b += grid_waves()) {
-        const StructInfo* si = info + b;
-        const int C = si->chunks;
-        if (C <= 1) continue;
-        const int n = si->n;
-        uint32_t* cc = ccount + si->xoff;
-        for (int a = lane; a < n; a += WAVE) {
-            uint32_t run = 0;
-            for (int k = 0; k < C; ++k) {
-                const uint32_t c = cc[(int64_t)a * C + k];
-                cc[(int64_t)a * C + k] = run;
-                run += c;
-            }
-            counts[si->atom0 + a] = run;
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    const StructInfo* si = info + b;
+    const int C = si->chunks;
+    if (C <= 1) return;
+    const int n = si->n;
+    const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
+    uint32_t* cc = ccount + si->xoff;
+    const int spb = WAVE / C;                 // sources per block (C <= 64)
+    const int al = lane / C, kl = lane - al * C;
+    const int nblk = (n + spb - 1) / spb;
+    auto load = [&](int blk) -> uint32_t {
+        const int a = blk * spb + al;
+        return (al < spb && a < n) ? cc[(int64_t)a * C + kl] : 0u;
+    };
+    uint32_t cn = wv < nblk ? load(wv) : 0u;
+    for (int blk = wv; blk < nblk; blk += 4) {
+        const uint32_t c = cn;
+        if (blk + 4 < nblk) cn = load(blk + 4);   // issued before this block's stores
+        const int inc = wave_incl_scan_i32((int)c);
+        const int first = al * C;                   // lane of this source's chunk 0
+        const int prev = __shfl(inc, max(first - 1, 0), WAVE);   // every lane takes part in the shuffle
+        const int before = first > 0 ? prev : 0;
+        const uint32_t excl = (uint32_t)inc - (uint32_t)before - c;   // modulo 2^32, like the counts
+        const int a = blk * spb + al;
+        if (al < spb && a < n) {
+            cc[(int64_t)a * C + kl] = excl;
+            if (kl == C - 1) counts[si->atom0 + a] = excl + c;
         }
     }
 }
 
 hipError_t launch_chunk_prefix(int B, const StructInfo* info, uint32_t* counts, uint32_t* ccount, hipStream_t s) {
     if (B == 0) return hipSuccess;
-    const int64_t g = std::min<int64_t>(((int64_t)B + 3) / 4, (int64_t)device_cu_count() * 8);
-    hipLaunchKernelGGL(k_chunk_prefix, dim3((unsigned)g), dim3(256), 0, s, B, info, counts, ccount);
+    hipLaunchKernelGGL(k_chunk_prefix, dim3((unsigned)B), dim3(256), 0, s, B, info, counts, ccount);
     return hipGetLastError();
 }
 
@@ -414,8 +429,20 @@ __device__ __forceinline__ int64_t scan_length(int64_t N, const int64_t* n_dev) 
 
 __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ counts, int64_t N,
                                                    const int64_t* __restrict__ n_dev,
-                                                   int64_t* __restrict__ bsum) {
+                                                   int64_t* __restrict__ bsum, mg_report* __restrict__ rep,
+                                                   const int64_t* __restrict__ partials, int np) {
     __shared__ int64_t sh[4];
+    if (partials && rep) {
+        // the sweep's per-wave candidate counts: every block sums a slice and
+        // adds it with one integer atomic (instead of one block looping over all)
+        const int per = (np + (int)gridDim.x - 1) / (int)gridDim.x;
+        const int q0 = (int)blockIdx.x * per, q1 = min(np, q0 + per);
+        int64_t c = 0;
+        for (int q = q0 + (int)threadIdx.x; q < q1; q += 256) c += partials[q];
+        c = block_sum_256(c, sh);
+        if (threadIdx.x == 0 && c != 0) atomicAdd((unsigned long long*)&rep->candidates, (unsigned long long)c);
+        __syncthreads();   // sh is reused below
+    }
     const int64_t n = scan_length(N, n_dev);
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     if (base >= n) return;            // never read by the final pass
@@ -491,7 +518,11 @@ hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offset
                               int64_t capacity, mg_report* report, hipStream_t s, const int64_t* n_dev,
                               const int64_t* partials, int np) {
     const int64_t nb = N > 0 ? (N + SCAN_TILE - 1) / SCAN_TILE : 1;
-    if (N > 0) hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, counts, N, n_dev, bsum);
+    if (N > 0) {   // the first pass also sums the partials
+        hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, counts, N, n_dev, bsum, report,
+                           partials, np);
+        partials = nullptr;
+    }
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(256), 0, s, counts, N, n_dev, bsum, offsets,
                        capacity, report, partials, np);
     return hipGetLastError();
