@@ -275,7 +275,7 @@ def main(argv=None):
         # each build alone are not best together: time the captured step for a
         # few grid sizes of both sweeps (the KNN search radius stays as tuned).
         best_ms, best_cfg = None, None
-        for cw in (8, 16):
+        for cw in (16, 32, 64):
             for kw in (2, 4, 16):
                 cfg = {**tuning, "cutoff_wgs_per_cu": cw, "knn_wgs_per_cu": kw}
                 _lib.set_tuning(**cfg)

@@ -309,7 +309,8 @@ mg_status mg_triplets(const int64_t* row_ptr, int64_t N, int64_t E, const float*
 
 /* Tunable launch parameters of the sweeps; 0 in a field keeps the current value. */
 typedef struct mg_tuning {
-    int32_t cutoff_wgs_per_cu;    /* persistent workgroups per CU for the cutoff sweeps */
+    int32_t cutoff_wgs_per_cu;    /* workgroups per CU for the cutoff sweeps (default 32; more than
+                                     stay resident, so the dispatcher balances the items) */
     int32_t cutoff_slots;         /* destination atoms per lane per image step (1, 2 or 4) */
     int32_t knn_wgs_per_cu;       /* persistent workgroups per CU for the KNN sweep */
     int32_t knn_lambda_x4;        /* KNN first-search radius targets (lambda_x4/4)*k + 6 candidates */

@@ -32,7 +32,7 @@ mg_status hip_fail(hipError_t e, const char* what) {
 }
 
 std::mutex g_mu;
-mg_tuning g_tune = {8, 2, 8, 6, {0, 0, 0, 0}};
+mg_tuning g_tune = {32, 2, 8, 6, {0, 0, 0, 0}};
 
 mg_tuning tuning() {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -27,7 +27,7 @@ from . import _lib, graph
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "matgraph", "tune.json")
 
-CUTOFF_SPACE = {"cutoff_wgs_per_cu": [2, 4, 8, 16], "cutoff_slots": [1, 2, 4]}
+CUTOFF_SPACE = {"cutoff_wgs_per_cu": [8, 16, 32, 64], "cutoff_slots": [1, 2, 4]}
 KNN_SPACE = {"knn_wgs_per_cu": [2, 4, 8, 16], "knn_lambda_x4": [4, 6, 8, 12]}
 
 

@@ -219,7 +219,7 @@ def test_grid_independence():
     saved = _lib.get_tuning()
     res = []
     try:
-        for cw in (4, 16):
+        for cw in (4, 64):
             _lib.set_tuning(**dict(saved, cutoff_wgs_per_cu=cw))
             g = gu.cutoff(b)
             assert g.report.flags == 0, g.report.flag_names()
