@@ -470,9 +470,41 @@ def pin_knn_ties_generic(O, seed=11):
     assert np.array_equal(d, kd) and np.array_equal(t, kt) and np.allclose(ln, kl)
 
 
+# ------------------------------------------------------ differentiation loss
+
+
+def pin_gaussian_loss(O):
+    """The differentiation workload's loss sum_e w_e exp(-(l_e - mu)^2) and its
+    length gradient: closed values at l = mu (loss sum w, gradient 0), at
+    l = mu + 1 (w / e) and at the gradient's extrema l = mu -+ 1/sqrt(2)
+    (gradient -+ sqrt(2) w e^{-1/2}), and an FP64 central difference of the
+    loss against the gradient at random lengths."""
+    mu = 3.0
+    w = np.array([0.7, -1.3, 2.0])
+    at = np.full(3, mu)
+    assert abs(O.gaussian_loss64(at, w, mu) - w.sum()) <= 1e-15 * 4
+    assert np.abs(O.gaussian_loss_grad_len64(at, w, mu)).max() == 0.0
+    assert abs(O.gaussian_loss64(at + 1.0, w, mu) - w.sum() / math.e) <= 1e-14
+    s = 1.0 / math.sqrt(2.0)
+    peak = math.sqrt(2.0) * math.exp(-0.5)
+    assert np.allclose(O.gaussian_loss_grad_len64(at - s, w, mu), peak * w, rtol=1e-14, atol=0)
+    assert np.allclose(O.gaussian_loss_grad_len64(at + s, w, mu), -peak * w, rtol=1e-14, atol=0)
+    rng = np.random.default_rng(12)
+    ln = rng.uniform(0.5, 6.0, size=40)
+    wr = rng.standard_normal(40)
+    g = O.gaussian_loss_grad_len64(ln, wr, mu)
+    h = 1e-6
+    for e in range(len(ln)):
+        up, dn = ln.copy(), ln.copy()
+        up[e] += h
+        dn[e] -= h
+        fd = (O.gaussian_loss64(up, wr, mu) - O.gaussian_loss64(dn, wr, mu)) / (2 * h)
+        assert abs(fd - g[e]) <= 1e-7 * max(1.0, abs(g[e])), (e, fd, g[e])
+
+
 ALL_PINS = [pin_cubic_shells, pin_sc_sum_of_three_squares, pin_strict_cutoff, pin_row_convention,
             pin_figure1, pin_knn_tie_break, pin_knn_single_atom_and_cluster, pin_symmetry,
             pin_supercell, pin_unimodular, pin_translation, pin_enormous_range, pin_knn_vs_cutoff,
             pin_gradients, pin_radii_closed_form, pin_radii_restriction, pin_triplets_closed_form,
             pin_triplets_brute_force, pin_symmetrize_chain, pin_symmetrize_properties,
-            pin_knn_ties_shells, pin_knn_ties_generic]
+            pin_knn_ties_shells, pin_knn_ties_generic, pin_gaussian_loss]

@@ -56,6 +56,12 @@ MUTATIONS = [
     ("geometry64", "f[:, :, None] * g[:, None, :]", "g[:, :, None] * f[:, None, :]",
      "transposed lattice gradient"),
     ("geometry64", "gl / safe, 0.0)", "gl, 0.0)", "length gradient not divided by the length"),
+    ("geometry64", "return -2.0 * w * (length - mu)", "return 2.0 * w * (length - mu)",
+     "wrong sign of the loss gradient"),
+    ("geometry64", "return -2.0 * w * (length - mu)", "return -1.0 * w * (length - mu)",
+     "factor 2 of the loss gradient dropped"),
+    ("geometry64", "np.exp(-(length - mu) ** 2)).sum()", "np.exp(-(length - mu))).sum()",
+     "square dropped from the loss exponent"),
 ]
 
 
