@@ -68,6 +68,8 @@ def _parse(argv=None):
     ap.add_argument("--update-loop", type=int, default=0, metavar="STEPS",
                     help="also time STEPS steps of the 64-supercell update loop (cell lists): move the "
                          "atoms, rebuild cutoff and KNN graphs, geometry forward and backward")
+    ap.add_argument("--update-loop-only", action="store_true",
+                    help="time only the 64-supercell update loop (STEPS from --update-loop, default 10)")
     ap.add_argument("--batch-sweep", action="store_true",
                     help="also time KNN k = 32 with ties kept on batches of 32..512 structures "
                          "(n ~ U{4..64}), with peak device memory")
@@ -109,17 +111,37 @@ def _log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(batch, seconds: float):
-    """The FP64 oracle on a bounded prefix of the batch (cutoff + KNN + geometry
-    + its VJP), in a process pool on the host's cores. Returns the dict for the
-    JSON line."""
-    import multiprocessing as mp
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), else the machine type."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
+
+def usable_cores() -> int:
+    """CPUs this process may run on (its affinity set), which on a shared host
+    is the share it was given, not every CPU the machine has."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(batch, seconds: float):
+    """The FP64 oracle on a bounded sample of the batch (cutoff + KNN + geometry
+    + its VJP), in a process pool over every core this process may use, plus
+    the same work on one core for a smaller sample. Returns the dict for the
+    JSON line."""
     import numpy as np
 
     import oracle
 
-    cores = min(os.cpu_count() or 1, 16)
+    cores = usable_cores()
     # size the sample from a quick single-structure timing
     def run(structs, procs):
         t0 = time.perf_counter()
@@ -139,10 +161,17 @@ def cpu_baseline(batch, seconds: float):
     rng = np.random.default_rng(0)
     sample = sorted(rng.choice(batch.B, S, replace=False).tolist()) if S < batch.B else list(range(batch.B))
     dt, E = run(sample, cores)
+    # one core: a smaller sample of the same draw, about a quarter of the time budget
+    S1 = int(min(len(sample), max(8, 0.25 * seconds * len(sample) / max(dt * cores, 1e-6))))
+    sample1 = sample[::max(1, len(sample) // S1)][:S1]
+    dt1, E1 = run(sample1, 1)
     return {"value": len(sample) / dt, "unit": "structures/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(sample)} of {batch.B} structures drawn uniformly (seed 0), FP64 numpy "
                       f"cutoff+KNN+geometry+VJP, {E} cutoff edges, {dt:.1f} s wall on {cores} processes",
-            "cpu": platform.processor() or platform.machine()}
+            "cpu": cpu_model(), "cpu_count_os": os.cpu_count(),
+            "single_core": {"value": round(len(sample1) / dt1, 3), "unit": "structures/s",
+                            "sample": f"every {max(1, len(sample) // S1)}-th of the sample above, "
+                                      f"{len(sample1)} structures, {E1} cutoff edges, {dt1:.1f} s wall"}}
 
 
 def main(argv=None):
@@ -159,6 +188,10 @@ def main(argv=None):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.update_loop_only:
+        res = update_loop(dev, args.update_loop or 10, cpu_sample=not args.no_cpu_baseline)
+        print(json.dumps({"update_loop": res, "source_digest": source_digest()}))
+        return 0
     batch = inputs.make_config(args.config)
     B, N, k, c = batch.B, batch.N, batch.k, batch.cutoff
     L = torch.from_numpy(batch.lattices).to(dev)
@@ -228,6 +261,8 @@ def main(argv=None):
     rep_c = cb.report()
     rep_k = kb.report()
     assert rep_c.num_edges == E and not (rep_c.flags & ~_lib.MG_FLAG_KNN_EXTENDED), rep_c
+    # a KNN source with a RANGE / IMAGES / ... flag gets invalid rows: none may be timed
+    assert not (rep_k.flags & ~_lib.MG_FLAG_KNN_EXTENDED), rep_k
     ref = [t.clone() for t in (cb.src, cb.dst, cb.image, kb.dst, kb.image, length, gf, gL)]
     _lib.profile_enable(True)
     _lib.profile_read()
@@ -380,7 +415,8 @@ def main(argv=None):
         "vs_plain": round((B / (ms_step / 1e3)) / plain["value"], 2) if plain else None,
         "report": {"cutoff_candidates": rep_c.candidates, "cutoff_images": rep_c.images_needed,
                    "knn_candidates": rep_k.candidates, "knn_images": rep_k.images_needed,
-                   "knn_extended_sources": rep_k.knn_extended},
+                   "knn_extended_sources": rep_k.knn_extended, "cutoff_flags": rep_c.flags,
+                   "knn_flags": rep_k.flags},
     }
     if args.copy_calibration_mb > 0:
         n = args.copy_calibration_mb * (1 << 20) // 4
@@ -400,7 +436,7 @@ def main(argv=None):
     return 0
 
 
-def update_loop(dev, steps: int, warmup: int = 2):
+def update_loop(dev, steps: int, warmup: int = 2, cpu_sample: bool = False):
     """64 supercells (8-atom base cells tiled 8..16 times per direction, ~10^6
     atoms): every step adds a Cartesian N(0, 0.02 A) move to every atom, then
     rebuilds the cutoff graph (5 A, edge vectors and lengths from its fill) and
@@ -456,10 +492,44 @@ def update_loop(dev, steps: int, warmup: int = 2):
     bad = f & ~_lib.MG_FLAG_KNN_EXTENDED
     assert not bad, f"update loop flags 0x{f:x}"
     E = float(h.mean())
-    return {"supercells": b.B, "atoms": b.N, "steps": steps, "ms_per_step": round(ms, 4),
-            "cutoff_edges_mean": int(E), "knn_edges": b.N * b.k, "cutoff": b.cutoff, "k": b.k,
-            "edges_per_s": round((E + b.N * b.k) / (ms / 1e3), 1),
-            "structures_per_s": round(b.B / (ms / 1e3), 1)}
+    out = {"supercells": b.B, "atoms": b.N, "steps": steps, "ms_per_step": round(ms, 4),
+           "cutoff_edges_mean": int(E), "knn_edges": b.N * b.k, "cutoff": b.cutoff, "k": b.k,
+           "edges_per_s": round((E + b.N * b.k) / (ms / 1e3), 1),
+           "structures_per_s": round(b.B / (ms / 1e3), 1)}
+    if cpu_sample:
+        out["cpu_oracle_extrapolated"] = update_loop_cpu(b)
+    return out
+
+
+def update_loop_cpu(b, sources: int = 24):
+    """The FP64 oracle on a few sources of one supercell (cutoff against every
+    atom and image, KNN, geometry and its VJP on those sources' edges), on one
+    core, extrapolated per atom to a whole update step of the 64 supercells.
+    A whole step cannot be brute-forced (a 32768-atom supercell alone has about
+    2.9e10 candidates); the figure is labelled extrapolated."""
+    import numpy as np
+
+    import oracle
+
+    q = int(np.argmax(np.diff(b.batch_ptr)))   # the largest supercell: the per-source cost grows with n
+    L, x = b.structure(q)
+    n = x.shape[0]
+    srcs = sorted(np.random.default_rng(0).choice(n, sources, replace=False).tolist())
+    t0 = time.perf_counter()
+    s, d, t, ln = oracle.cutoff_sources64(L, x, b.cutoff, srcs)
+    oracle.knn_structure64(L, x, b.k, sources=srcs)
+    ptr = np.array([0, n], np.int64)
+    v, l64 = oracle.edge_geometry64(L[None], x, ptr, s, d, t)
+    oracle.edge_geometry_vjp64(L[None], x, ptr, s, d, t, None, np.ones_like(l64))
+    dt = time.perf_counter() - t0
+    per_atom = dt / len(srcs)
+    # the per-source cost is about linear in the supercell's atom count
+    step_s = per_atom * float((np.diff(b.batch_ptr).astype(np.float64) ** 2).sum()) / n
+    return {"value": round(b.B / step_s, 6), "unit": "structures/s", "cores": 1, "kind": "oracle",
+            "extrapolated": True,
+            "sample": f"{len(srcs)} sources of the {n}-atom supercell, {dt:.1f} s; per-source time scaled "
+                      f"by n_s / {n} for every supercell s (the oracle compares a source with all n_s atoms)",
+            "seconds_per_step": round(step_s, 1)}
 
 
 def batch_sweep(dev, sizes=(32, 64, 128, 256, 512), k=32, reps=10):

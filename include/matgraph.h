@@ -121,10 +121,32 @@ size_t mg_knn_ties_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t imag
 size_t mg_symmetrize_workspace_bytes(int64_t N, int64_t E);
 
 /*
+ * Image-table sizing without building a graph: runs only the per-structure
+ * FP64 bounds and the batch plan of a cutoff call (k == 0: constant `cutoff`,
+ * or per-atom `radii` as in mg_cutoff_graph_radii) or of a KNN call (k in
+ * 1..64; the first search radius comes from the current tuning, see
+ * mg_set_tuning) and writes report->images_needed: the image_capacity with
+ * which the same call on the same inputs and tuning sets no MG_FLAG_IMAGES.
+ * report->flags gets the flags of skipped structures (SINGULAR, NONFINITE,
+ * RANGE); every other report field is 0. Together with a cutoff call of
+ * capacity 0 (which skips the fill and returns the exact num_edges) it sizes
+ * every buffer of a step before that step is captured into a HIP graph.
+ *  workspace     mg_cutoff_workspace_bytes(B, N, 0) (k == 0) or
+ *                mg_knn_workspace_bytes(B, N, k, 0) bytes suffice.
+ * Errors: as mg_cutoff_graph / mg_knn_graph; MG_ERR_INVALID_ARG for k outside 0..64.
+ */
+mg_status mg_images_needed(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                           int32_t B, int64_t N, float cutoff, const float* radii, int32_t k,
+                           mg_report* report, void* workspace, size_t workspace_bytes,
+                           int32_t opts, void* stream);
+
+/*
  * Periodic cutoff multigraph (Definition def6 with a constant cutoff c_i = cutoff).
  *
  *  cutoff        > 0 and finite, Angstrom; the test is strict (length < cutoff).
- *  capacity      number of edge slots in src/dst/image/length (>= 0).
+ *  capacity      number of edge slots in src/dst/image/length (>= 0). With capacity 0
+ *                the call only counts (no fill): report->num_edges is the exact edge
+ *                count, and row_ptr (if given) is filled, which sizes the outputs.
  *  src, dst      int32 [capacity]; image int32 [capacity][3]; length float32 [capacity].
  *  row_ptr       int64 [N+1] or NULL: edges of source i are row_ptr[i] .. row_ptr[i+1]-1
  *                (edges are grouped by ascending src; the order inside a source is

@@ -66,6 +66,7 @@ SIGNATURES = {
                                      _SZ, _I32, _P]),
     "mg_cutoff_graph_vec": (_I32, [_P, _P, _P, _I32, _I64, _F, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P,
                                    _SZ, _I32, _P]),
+    "mg_images_needed": (_I32, [_P, _P, _P, _I32, _I64, _F, _P, _I32, _P, _P, _SZ, _I32, _P]),
     "mg_knn_graph": (_I32, [_P, _P, _P, _I32, _I64, _I32, _P, _P, _P, _P, _P, _P, _SZ, _I32, _P]),
     "mg_edge_geometry": (_I32, [_P, _P, _P, _I32, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "mg_edge_geometry_backward": (_I32, [_P, _P, _P, _I32, _I64, _P, _P, _P, _I64, _P, _P, _P, _P,

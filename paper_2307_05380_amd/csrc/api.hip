@@ -31,6 +31,13 @@ mg_status hip_fail(hipError_t e, const char* what) {
     return fail(MG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+}  // namespace
+
+// The thread's last error message, for entry points outside this file.
+mg_status mg::api_fail(mg_status st, const char* msg) { return fail(st, "%s", msg); }
+
+namespace {
+
 std::mutex g_mu;
 mg_tuning g_tune = {32, 2, 8, 6, {0, 0, 0, 0}};
 
@@ -429,6 +436,7 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
                                            sum ? w.partials : nullptr, (cl ? 2 : 1) * grid * 4);
          })) != hipSuccess)
         return hip_fail(e, "scan");
+    if (capacity == 0) return MG_OK;   // a sizing call: the counts and num_edges are all it needs
     if ((e = phase("cutoff.fill", s, [&] {
              return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.ccount, w.img.table, frac, c2, thr, w.counts, offs,
                                             capacity, src, dst, image, length, vec, w.ctr, report, w.partials,
@@ -555,6 +563,54 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
                                             w.ext_list, w.ctr, report, mg::device_cu_count() * 2, s);
          })) != hipSuccess)
         return hip_fail(e, "knn extended");
+    return MG_OK;
+}
+
+mg_status mg_images_needed(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
+                           int64_t N, float cutoff, const float* radii, int32_t k, mg_report* report,
+                           void* workspace, size_t workspace_bytes, int32_t opts, void* stream) {
+    g_err.clear();
+    mg_status st = check_common(lattices, frac, batch_ptr, B, N);
+    if (st != MG_OK) return st;
+    if (k < 0 || k > 64) return fail(MG_ERR_INVALID_ARG, "k must be 0 (cutoff graph) or in 1..64 (got %d)", k);
+    if (k == 0 && !radii && (!(cutoff > 0.0f) || !std::isfinite(cutoff)))
+        return fail(MG_ERR_INVALID_ARG, "cutoff must be finite and > 0 (got %g)", (double)cutoff);
+    if (!report) return fail(MG_ERR_INVALID_ARG, "report is NULL");
+    if (opts & ~(MG_OPT_CELL_LIST_OFF | MG_OPT_CELL_LIST_FORCE))
+        return fail(MG_ERR_INVALID_ARG, "unknown opts bits 0x%x", opts);
+    if (!workspace) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const mg_tuning tu = tuning();
+    hipError_t e;
+    mg::Counters* ctr;
+    mg::StructInfo* info;
+    mg::PlanRow* plan;
+    int64_t *item_off, *cl_off, *box_off;
+    float* thr = nullptr;
+    if (k == 0) {
+        CutoffWs w = carve_cutoff(workspace, workspace_bytes, B, N);
+        if (workspace_bytes < w.fixed)
+            return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                        workspace_bytes, w.fixed);
+        ctr = w.ctr, info = w.info, plan = w.plan, item_off = w.item_off, cl_off = w.cl.cl_off, box_off = w.box_off;
+        thr = radii ? w.thr : nullptr;
+    } else {
+        KnnWs w = carve_knn(workspace, workspace_bytes, B, N);
+        if (workspace_bytes < w.fixed)
+            return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                        workspace_bytes, w.fixed);
+        ctr = w.ctr, info = w.info, plan = w.plan, item_off = w.item_off, cl_off = w.cl.cl_off, box_off = w.box_off;
+    }
+    const float lambda = (tu.knn_lambda_x4 > 0 ? tu.knn_lambda_x4 : 6) / 4.0f;
+    if ((e = mg::launch_zero_report(report, ctr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
+    if ((e = mg::launch_bounds(lattices, batch_ptr, frac, B, N, k == 0 ? (radii ? 1.0f : cutoff) : 0.f,
+                               k == 0 ? radii : nullptr, thr, k, lambda, info, plan, ctr, report, k == 0 ? 0 : 1,
+                               opts, s)) != hipSuccess)
+        return hip_fail(e, "bounds");
+    // the plan with an unbounded table: images_needed is the batch's total, no structure skipped
+    if ((e = mg::launch_struct_scan(B, info, plan, 0, item_off, cl_off, box_off, ctr, report, INT64_MAX, s)) !=
+        hipSuccess)
+        return hip_fail(e, "plan");
     return MG_OK;
 }
 

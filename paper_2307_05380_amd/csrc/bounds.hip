@@ -67,10 +67,13 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     const int lane = threadIdx.x;
     const int64_t a0 = ptr[b], a1 = ptr[b + 1];
     bool bad = false;
+    bool far = false;   // a coordinate whose cell floor(x) does not fit the cell lists' packed shift
     float rmax = 0.0f;
     for (int64_t a = a0 + lane; a < a1; a += WAVE) {
         float x = frac[3 * a], y = frac[3 * a + 1], z = frac[3 * a + 2];
         bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+        auto out = [](float v) { return !(v >= -(float)TMAX && v < (float)(TMAX + 1)); };
+        far |= out(x) || out(y) || out(z);
         if (radii) {
             const float r = radii[a];
             const bool ok = isfinite(r) && r > 0.0f;
@@ -80,6 +83,7 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
         }
     }
     const bool any_bad = ballot(bad) != 0;
+    const bool any_far = ballot(far) != 0;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, d, WAVE));
     if (lane != 0) return;
@@ -127,10 +131,14 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     // (h_k = |det| / |a_{k+1} x a_{k+2}| is the spacing of the lattice planes),
     // so every neighbour within Rb lies in the 27 bins around the source's bin;
     // m_k >= 3 keeps those 27 bins distinct. Bins are capped at 2n + 64.
+    // Cell lists store every atom's cell floor(x) packed in 10-bit fields; a
+    // structure with a coordinate outside [-511, 512) takes the image sweep,
+    // which has no such limit.
     int cm[3] = {0, 0, 0};
     double wcl = 0.0;
     bool use_cl = false;
-    if (valid && !(opts & MG_OPT_CELL_LIST_OFF) && (n >= CL_MIN_ATOMS || (opts & MG_OPT_CELL_LIST_FORCE))) {
+    if (valid && !any_far && !(opts & MG_OPT_CELL_LIST_OFF) &&
+        (n >= CL_MIN_ATOMS || (opts & MG_OPT_CELL_LIST_FORCE))) {
         double h[3];
         bool ok = true;
         for (int k = 0; k < 3; ++k) {

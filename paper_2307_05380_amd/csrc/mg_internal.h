@@ -95,7 +95,7 @@ struct alignas(64) Counters {
 // Capacity of the cell-list bin arrays: bins are capped at 2n + 64 per structure.
 inline int64_t cl_bin_capacity(int B, int64_t N) { return 2 * N + 64 * (int64_t)B + 1; }
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ------------------------------------------------------------ device helpers
 
@@ -361,5 +361,8 @@ hipError_t launch_zero_report(mg_report* report, Counters* ctr, int64_t num_edge
 int64_t scan_block_count(int64_t N);
 
 int device_cu_count();
+
+// Sets the calling thread's mg_last_error() message and returns st.
+mg_status api_fail(mg_status st, const char* msg);
 
 }  // namespace mg

@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 
 import torch
 
@@ -21,7 +22,7 @@ from . import _lib
 
 __all__ = ["Graph", "Report", "cutoff_graph", "knn_graph", "edge_geometry", "EdgeGeometry",
            "CutoffBuilder", "KnnBuilder", "GeometryRunner", "auto_opts", "Triplets", "triplets", "symmetrize",
-           "knn_graph_ties"]
+           "knn_graph_ties", "images_needed", "cutoff_sizes", "CapturedStep"]
 
 
 @dataclasses.dataclass
@@ -167,6 +168,28 @@ class CutoffBuilder:
         E = min(rep.num_edges, self.capacity)
         return Graph(self.src[:E], self.dst[:E], self.image[:E], self.length[:E], self.row_ptr, rep)
 
+    def overflowed(self, rep: Report | None = None) -> bool:
+        """The last run left edges or image slots out (MG_FLAG_CAPACITY / MG_FLAG_IMAGES)."""
+        rep = rep or self.report()
+        return bool(rep.flags & (_lib.MG_FLAG_CAPACITY | _lib.MG_FLAG_IMAGES))
+
+    def grow(self, rep: Report | None = None, headroom: float = 1.15) -> bool:
+        """Reallocate the outputs and the workspace for what the last run
+        reported it needs, times ``headroom``. Returns True when anything was
+        reallocated (buffers then have new addresses: a captured graph that
+        uses them must be captured again)."""
+        rep = rep or self.report()
+        cap, icap = self.capacity, self.image_capacity
+        if rep.flags & _lib.MG_FLAG_CAPACITY:
+            cap = max(cap, int(math.ceil(rep.num_edges * headroom)))
+        if rep.flags & _lib.MG_FLAG_IMAGES:
+            icap = max(icap, int(math.ceil(rep.images_needed * headroom)))
+        if cap == self.capacity and icap == self.image_capacity:
+            return False
+        self.__init__(self.B, self.N, cap, icap, self.device, row_ptr=self.row_ptr is not None,
+                      vec=self.vec is not None)
+        return True
+
 
 def cutoff_graph(lattices, frac, batch_ptr, cutoff, capacity: int | None = None,
                  image_capacity: int | None = None, strict: bool = False,
@@ -232,6 +255,24 @@ class KnnBuilder:
     def graph(self, rep: Report | None = None) -> Graph:
         return Graph(self.src, self.dst, self.image, self.length, None, rep or self.report())
 
+    def overflowed(self, rep: Report | None = None) -> bool:
+        """The last run left image slots out (MG_FLAG_IMAGES): some sources are invalid."""
+        rep = rep or self.report()
+        return bool(rep.flags & _lib.MG_FLAG_IMAGES)
+
+    def grow(self, rep: Report | None = None, headroom: float = 1.15) -> bool:
+        """Reallocate the workspace for the image slots the last run needed,
+        times ``headroom`` (the output size N*k never changes). Returns True
+        when the workspace moved."""
+        rep = rep or self.report()
+        if not (rep.flags & _lib.MG_FLAG_IMAGES):
+            return False
+        icap = max(self.image_capacity, int(math.ceil(rep.images_needed * headroom)))
+        if icap == self.image_capacity:
+            return False
+        self.__init__(self.B, self.N, self.k, icap, self.device)
+        return True
+
 
 def knn_graph(lattices, frac, batch_ptr, k: int, image_capacity: int | None = None,
               strict: bool = False, opts: int | None = None) -> Graph:
@@ -250,6 +291,96 @@ def knn_graph(lattices, frac, batch_ptr, k: int, image_capacity: int | None = No
     if strict:
         _strict_check(rep)
     return b.graph(rep)
+
+
+def images_needed(lattices, frac, batch_ptr, cutoff=None, k: int = 0, opts: int | None = None) -> Report:
+    """Image-table slots a cutoff call (``cutoff``: a distance or per-atom
+    float32 device tensor [N]) or a KNN call (``k`` > 0) needs on this batch,
+    from the bounds and the batch plan alone (mg_images_needed; synchronises)."""
+    lattices, frac, batch_ptr, B, N = _check_inputs(lattices, frac, batch_ptr)
+    opts = auto_opts(batch_ptr, opts)
+    lib = _lib.load()
+    d = frac.device
+    radii = None
+    if k == 0:
+        radii = _radii(cutoff, N) if isinstance(cutoff, torch.Tensor) else None
+        nbytes = lib.mg_cutoff_workspace_bytes(B, N, 0)
+    else:
+        nbytes = lib.mg_knn_workspace_bytes(B, N, int(k), 0)
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=d)
+    rep = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=d)
+    _lib.check(lib.mg_images_needed(_ptr(lattices), _ptr(frac), _ptr(batch_ptr), B, N,
+                                    1.0 if (radii is not None or k) else float(cutoff), _ptr(radii), int(k),
+                                    _ptr(rep), _ptr(ws), ws.numel(), int(opts), _stream(d)), lib)
+    return Report.from_tensor(rep)
+
+
+def cutoff_sizes(lattices, frac, batch_ptr, cutoff, opts: int | None = None) -> tuple[int, int]:
+    """(edges, image slots) of the cutoff graph of this batch: the image slots
+    from mg_images_needed, then the exact edge count from a cutoff call of
+    capacity 0 (count only, no fill). Synchronises; meant for sizing builders
+    before a step is captured."""
+    lattices, frac, batch_ptr, B, N = _check_inputs(lattices, frac, batch_ptr)
+    opts = auto_opts(batch_ptr, opts)
+    icap = max(images_needed(lattices, frac, batch_ptr, cutoff, 0, opts).images_needed, 1)
+    b = CutoffBuilder(B, N, 0, icap, frac.device)
+    b.run(lattices, frac, batch_ptr, cutoff, opts)
+    rep = b.report()
+    _strict_check(rep)
+    return int(rep.num_edges), int(icap)
+
+
+class CapturedStep:
+    """A step of builder calls captured once into a HIP graph and replayed,
+    with the overflow protocol a captured call needs: the library never
+    allocates, so a replay whose batch needs more edges or image slots than
+    the builders hold only sets MG_FLAG_CAPACITY / MG_FLAG_IMAGES (nothing is
+    written past a buffer). ``replay(check=True)`` reads the builders' reports
+    after the replay (one synchronisation); on an overflow it grows the
+    builders that overflowed (``headroom`` times what their report asks for),
+    captures the step again and replays it, so the results are complete when
+    it returns. ``step`` must enqueue its work on the current stream through
+    the builders' ``run`` methods (it is re-run at capture)."""
+
+    def __init__(self, step, builders, headroom: float = 1.15, max_recaptures: int = 4):
+        self.step = step
+        self.builders = list(builders)
+        self.headroom = float(headroom)
+        self.max_recaptures = int(max_recaptures)
+        self.recaptures = 0
+        self.graph = None
+        self._capture()
+
+    def _capture(self):
+        self.graph = None
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):   # warm-up launch outside the capture
+            self.step()
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+
+    def replay(self, check: bool = True) -> bool:
+        """Replay the captured step. With ``check``: synchronise, and if a
+        builder overflowed, grow it, capture again and replay (up to
+        ``max_recaptures`` times). Returns True when the step was captured again."""
+        self.graph.replay()
+        if not check:
+            return False
+        again = False
+        for _ in range(self.max_recaptures):
+            reps = [b.report() for b in self.builders]
+            grown = [b.grow(r, self.headroom) for b, r in zip(self.builders, reps) if b.overflowed(r)]
+            if not any(grown):
+                return again
+            self.recaptures += 1
+            again = True
+            self._capture()
+            self.graph.replay()
+        raise _lib.MatgraphError(-1, "step still overflows after %d recaptures" % self.max_recaptures)
 
 
 class GeometryRunner:

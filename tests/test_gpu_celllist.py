@@ -75,6 +75,22 @@ def test_cell_lists_wrapped_coordinates():
     compare.knn_check(b, b.k, *gu.np_graph(k))
 
 
+def test_cell_lists_far_coordinates():
+    """Coordinates hundreds of cells away from [0, 1) (beyond what the cell
+    lists' packed cell index holds): the structure goes through the image sweep
+    and its edges still match the oracle, with t relative to the coordinates
+    as given."""
+    b = _large_cells(5, B=3)
+    rng = np.random.default_rng(1)
+    shift = rng.choice([-600.0, 0.0, 600.0], size=b.frac.shape).astype(np.float32)
+    b.frac[:] = b.frac + shift
+    g = gu.cutoff(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    assert g.report.flags == 0, g.report.flag_names()
+    compare.cutoff_check(b, *gu.np_graph(g))
+    k = gu.knn(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    compare.knn_check(b, b.k, *gu.np_graph(k))
+
+
 def test_cell_list_knn_extended():
     """Clustered atoms: the k-th neighbour lies beyond the stencil, the source
     falls back to the extended search."""

@@ -131,6 +131,26 @@ def test_host_validation_extra_entry_points(lib):
     assert lib.mg_triplets_workspace_bytes(-1) == 0 and lib.mg_triplets_workspace_bytes(10) > 0
 
 
+def test_host_validation_images_needed(lib):
+    """The image-table sizing query rejects bad k, bad cutoffs and a missing
+    report or workspace on the host."""
+    from paper_2307_05380_amd import _lib
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    ERR, WS = _lib.MG_ERR_INVALID_ARG, _lib.MG_ERR_WORKSPACE
+    for k in (-1, 65):
+        st = lib.mg_images_needed(fake, fake, fake, 1, 2, 5.0, None, k, fake, fake, 1 << 20, 0, None)
+        assert st == ERR and b"k must be" in lib.mg_last_error()
+    st = lib.mg_images_needed(fake, fake, fake, 1, 2, 0.0, None, 0, fake, fake, 1 << 20, 0, None)
+    assert st == ERR and b"cutoff" in lib.mg_last_error()
+    st = lib.mg_images_needed(fake, fake, fake, 1, 2, 5.0, None, 0, None, fake, 1 << 20, 0, None)
+    assert st == ERR and b"report" in lib.mg_last_error()
+    st = lib.mg_images_needed(fake, fake, fake, 1, 2, 5.0, None, 4, fake, None, 0, 0, None)
+    assert st == WS
+    st = lib.mg_images_needed(fake, fake, fake, 1, 2, 5.0, None, 4, fake, fake, 16, 0, None)
+    assert st == WS
+
+
 def test_tuning_roundtrip(lib):
     from paper_2307_05380_amd import _lib
     t0 = _lib.get_tuning()
