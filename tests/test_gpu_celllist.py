@@ -79,16 +79,31 @@ def test_cell_lists_far_coordinates():
     """Coordinates hundreds of cells away from [0, 1) (beyond what the cell
     lists' packed cell index holds): the structure goes through the image sweep
     and its edges still match the oracle, with t relative to the coordinates
-    as given."""
+    as given. Def. def6 is invariant under x_a -> x_a + s_a (s_a integer):
+    edge (i, j, t) of the shifted coordinates is edge (i, j, t + s_j - s_i) of
+    the unshifted ones, so the oracle runs on the unshifted batch (its union
+    of per-pair image ranges would span the whole 1200-cell shift) and the GPU
+    edges are mapped back. Both batches hold the same FP32 values up to the
+    exact integer shift."""
     b = _large_cells(5, B=3)
     rng = np.random.default_rng(1)
     shift = rng.choice([-600.0, 0.0, 600.0], size=b.frac.shape).astype(np.float32)
-    b.frac[:] = b.frac + shift
-    g = gu.cutoff(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    far = inputs.Batch(b.lattices.copy(), (b.frac + shift).astype(np.float32), b.batch_ptr.copy(),
+                       b.cutoff, b.k, "far")
+    near = inputs.Batch(b.lattices, (far.frac - shift).astype(np.float32), b.batch_ptr, b.cutoff, b.k, "near")
+    assert np.array_equal(far.frac.astype(np.float64) - shift, near.frac.astype(np.float64))   # exact
+    s_int = shift.astype(np.int64)
+
+    def back(g):
+        s, d, t, ln = gu.np_graph(g)
+        return s, d, t + s_int[d] - s_int[s], ln
+
+    g = gu.cutoff(far, opts=_lib.MG_OPT_CELL_LIST_FORCE)
     assert g.report.flags == 0, g.report.flag_names()
-    compare.cutoff_check(b, *gu.np_graph(g))
-    k = gu.knn(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
-    compare.knn_check(b, b.k, *gu.np_graph(k))
+    compare.cutoff_check(near, *back(g))
+    k = gu.knn(far, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    assert k.report.flags & ~_lib.MG_FLAG_KNN_EXTENDED == 0, k.report.flag_names()
+    compare.knn_check(near, near.k, *back(k))
 
 
 def test_cell_list_knn_extended():
