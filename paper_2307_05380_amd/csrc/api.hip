@@ -39,7 +39,7 @@ mg_status mg::api_fail(mg_status st, const char* msg) { return fail(st, "%s", ms
 namespace {
 
 std::mutex g_mu;
-mg_tuning g_tune = {32, 2, 8, 6, {0, 0, 0, 0}};
+mg_tuning g_tune = {32, 2, 8, 6, 10, {0, 0, 0}};
 
 mg_tuning tuning() {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -114,13 +114,13 @@ void carve_cl(Carver& c, int B, int64_t N, mg::Counters* ctr, mg::ClWs& w) {
     w.cap = mg::cl_bin_capacity(B, N);
     w.cl_off = c.take<int64_t>((size_t)B + 1);
     w.bin_count = c.take<uint32_t>((size_t)w.cap);
-    w.bin_fill = c.take<uint32_t>((size_t)w.cap);
     w.bin_start = c.take<int64_t>((size_t)w.cap + 1);
     w.bsum = c.take<int64_t>((size_t)((w.cap + 2047) / 2048) + 1);
     w.atom_bin = c.take<int32_t>((size_t)N);
-    w.atom_shift = c.take<int32_t>((size_t)N);
+    w.atom_rank = c.take<int32_t>((size_t)N);
     w.slot_atom = c.take<int32_t>((size_t)N);
-    w.slot_pos = c.take<float4>((size_t)N);
+    w.slot_x = c.take<float4>((size_t)N);
+    w.slot_shift = c.take<int32_t>((size_t)N);
     w.atom_struct = c.take<int32_t>((size_t)N);
     w.ctr = ctr;
 }
@@ -553,7 +553,7 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
         return hip_fail(e, "knn");
     if (cl && (e = phase("knn.cells.select", s, [&] {
                    hipError_t r = mg::launch_cl_knn(B, k, w.info, w.cl, frac, src, dst, image, length, w.ext_list,
-                                                    w.ctr, report, w.partials, grid, s);
+                                                    w.ctr, report, w.partials, grid, tu.knn_cl_tau_x8 / 8.0f, s);
                    if (r != hipSuccess || !sum) return r;
                    return mg::launch_sum_partials(w.partials, grid * 4, report, s);
                })) != hipSuccess)
@@ -772,11 +772,14 @@ mg_status mg_set_tuning(const mg_tuning* in) {
         return fail(MG_ERR_INVALID_ARG, "workgroups per CU must be in 0..64");
     if (in->knn_lambda_x4 < 0 || in->knn_lambda_x4 > 64)
         return fail(MG_ERR_INVALID_ARG, "knn_lambda_x4 must be in 0..64");
+    if (in->knn_cl_tau_x8 < 0 || in->knn_cl_tau_x8 > 64)
+        return fail(MG_ERR_INVALID_ARG, "knn_cl_tau_x8 must be in 0..64");
     std::lock_guard<std::mutex> lk(g_mu);
     if (in->cutoff_wgs_per_cu) g_tune.cutoff_wgs_per_cu = in->cutoff_wgs_per_cu;
     if (in->cutoff_slots) g_tune.cutoff_slots = in->cutoff_slots;
     if (in->knn_wgs_per_cu) g_tune.knn_wgs_per_cu = in->knn_wgs_per_cu;
     if (in->knn_lambda_x4) g_tune.knn_lambda_x4 = in->knn_lambda_x4;
+    if (in->knn_cl_tau_x8) g_tune.knn_cl_tau_x8 = in->knn_cl_tau_x8;
     return MG_OK;
 }
 

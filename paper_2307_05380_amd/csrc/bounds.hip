@@ -53,40 +53,65 @@ __device__ inline float cutoff_threshold_dev(float c) {
 
 // mode 0: cutoff, radius = cutoff (or the largest per-atom cutoff of the
 // structure); mode 1: KNN first search, radius from density.
-// One wave per structure: every lane scans coordinates for non-finite values,
-// lane 0 does the FP64 lattice work.
-__global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattices,
-                                               const int64_t* __restrict__ ptr,
-                                               const float* __restrict__ frac, int B, float radius,
-                                               const float* __restrict__ radii, float* __restrict__ thr,
-                                               int knn_k, float knn_lambda,
-                                               StructInfo* __restrict__ info, PlanRow* __restrict__ plan,
-                                               mg_report* __restrict__ rep, int mode, int opts) {
+// One workgroup per structure: every thread scans coordinates for non-finite
+// values (and per-atom cutoffs), four atoms per round, thread 0 does the FP64
+// lattice work.
+__global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattices,
+                                                const int64_t* __restrict__ ptr,
+                                                const float* __restrict__ frac, int B, float radius,
+                                                const float* __restrict__ radii, float* __restrict__ thr,
+                                                int knn_k, float knn_lambda,
+                                                StructInfo* __restrict__ info, PlanRow* __restrict__ plan,
+                                                mg_report* __restrict__ rep, int mode, int opts) {
+    __shared__ int s_bad[4], s_far[4];
+    __shared__ float s_rmax[4];
     const int b = blockIdx.x;
     if (b >= B) return;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
     const int64_t a0 = ptr[b], a1 = ptr[b + 1];
     bool bad = false;
     bool far = false;   // a coordinate whose cell floor(x) does not fit the cell lists' packed shift
     float rmax = 0.0f;
-    for (int64_t a = a0 + lane; a < a1; a += WAVE) {
-        float x = frac[3 * a], y = frac[3 * a + 1], z = frac[3 * a + 2];
-        bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
-        auto out = [](float v) { return !(v >= -(float)TMAX && v < (float)(TMAX + 1)); };
-        far |= out(x) || out(y) || out(z);
+    auto out = [](float v) { return !(v >= -(float)CL_SHIFT_MAX && v < (float)(CL_SHIFT_MAX + 1)); };
+    constexpr int U = 4;
+    for (int64_t a = a0 + tid; a < a1; a += U * 256) {
+        float x[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {   // all loads of the round first
+            const int64_t q = a + u * 256 < a1 ? a + u * 256 : a;
+            x[u][0] = frac[3 * q];
+            x[u][1] = frac[3 * q + 1];
+            x[u][2] = frac[3 * q + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bad |= !(isfinite(x[u][0]) && isfinite(x[u][1]) && isfinite(x[u][2]));
+            far |= out(x[u][0]) || out(x[u][1]) || out(x[u][2]);
+        }
         if (radii) {
-            const float r = radii[a];
-            const bool ok = isfinite(r) && r > 0.0f;
-            bad |= !ok;
-            rmax = ok ? fmaxf(rmax, r) : rmax;
-            thr[a] = ok ? cutoff_threshold_dev(r) : 0.0f;
+            for (int u = 0; u < U && a + u * 256 < a1; ++u) {
+                const int64_t q = a + u * 256;
+                const float r = radii[q];
+                const bool ok = isfinite(r) && r > 0.0f;
+                bad |= !ok;
+                rmax = ok ? fmaxf(rmax, r) : rmax;
+                thr[q] = ok ? cutoff_threshold_dev(r) : 0.0f;
+            }
         }
     }
-    const bool any_bad = ballot(bad) != 0;
-    const bool any_far = ballot(far) != 0;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, d, WAVE));
-    if (lane != 0) return;
+    const bool wbad = ballot(bad) != 0, wfar = ballot(far) != 0;
+    if (lane == 0) {
+        s_bad[wv] = wbad;
+        s_far[wv] = wfar;
+        s_rmax[wv] = rmax;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const bool any_bad = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
+    const bool any_far = s_far[0] | s_far[1] | s_far[2] | s_far[3];
+    rmax = fmaxf(fmaxf(s_rmax[0], s_rmax[1]), fmaxf(s_rmax[2], s_rmax[3]));
 
     StructInfo si;
     uint32_t flags = any_bad ? (uint32_t)MG_FLAG_NONFINITE : 0u;
@@ -131,9 +156,9 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     // (h_k = |det| / |a_{k+1} x a_{k+2}| is the spacing of the lattice planes),
     // so every neighbour within Rb lies in the 27 bins around the source's bin;
     // m_k >= 3 keeps those 27 bins distinct. Bins are capped at 2n + 64.
-    // Cell lists store every atom's cell floor(x) packed in 10-bit fields; a
-    // structure with a coordinate outside [-511, 512) takes the image sweep,
-    // which has no such limit.
+    // Cell lists store every atom's cell floor(x) (and u - floor(x)) packed in
+    // 10-bit fields; a structure with a coordinate outside [-510, 511) takes the
+    // image sweep, which has no such limit.
     int cm[3] = {0, 0, 0};
     double wcl = 0.0;
     bool use_cl = false;
@@ -229,7 +254,7 @@ __global__ __launch_bounds__(64) void k_bounds(const float* __restrict__ lattice
     si.m[2] = cm[2];
     si.nbins = use_cl ? cm[0] * cm[1] * cm[2] : 0;
     si.bin_off = 0;
-    si.cl_items = use_cl ? n : 0;
+    si.cl_items = use_cl ? si.nbins : 0;   // one work item per bin
     si.wcl = (float)(wcl * (1.0 - 1e-6) - 1e-3);
     if (use_cl) si.groups = 0;
     si.chunks = 1;
@@ -249,7 +274,7 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
     (void)N;
     (void)ctr;
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bounds, dim3(B), dim3(64), 0, s, lattices, batch_ptr, frac, B, radius, radii, thr,
+    hipLaunchKernelGGL(k_bounds, dim3(B), dim3(256), 0, s, lattices, batch_ptr, frac, B, radius, radii, thr,
                        knn_k, knn_lambda, info, plan, report, mode, opts);
     return hipGetLastError();
 }

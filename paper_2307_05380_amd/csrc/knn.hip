@@ -26,7 +26,7 @@
 // handed out cyclically over the grid's waves (loops bounded by the item
 // count) and the extended search is capped at
 // KNN_MAX_ATTEMPTS radius doublings: every wave reaches its exit.
-#include "mg_internal.h"
+#include "cl_tile.h"
 
 namespace mg {
 
@@ -159,16 +159,18 @@ struct Stack {
     float tau2;
 };
 
-// Push this lane's candidate (pass, l2, ordinal lo) onto the stack; when the
-// stack would overflow, keep the k smallest keys and lower the threshold first.
+// Push this lane's candidate (pass, l2, ordinal lo) onto the stack of CAP
+// keys; when the stack would overflow, keep the k smallest keys and lower the
+// threshold first.
+template <int CAP = KNN_CAP>
 __device__ __forceinline__ void stack_push(Stack& st, bool pass, float l2, uint32_t lo, int k, uint64_t* buf,
                                            int lane) {
     uint64_t m = ballot(pass);
     int c = ufirst(__popcll(m));
     if (c == 0) return;
-    if (st.cnt + c > KNN_CAP) {
+    if (st.cnt + c > CAP) {
         wave_lds_sync();
-        const uint64_t v0 = sorted_rank<KNN_CAP / WAVE>(buf, st.cnt, lane);
+        const uint64_t v0 = sorted_rank<CAP / WAVE>(buf, st.cnt, lane);
         wave_lds_sync();
         if (lane < k) buf[lane] = v0;
         const uint64_t kth = readlane_u64(v0, k - 1);
@@ -365,112 +367,110 @@ __global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInf
     if (lane == 0) partials[grid_wave()] = wave_cand;
 }
 
-// Cell-list pass: the sources of cell-list structures, candidates from the 27
-// bins around the source's bin (see celllist.hip for the layout). Key ordinal:
-// local dst * 32768 + (t0+16, t1+16, t2+16) in 5 bits each, which is the
-// (dst, t) order. The stencil covers every candidate within wcl, so a stack of
-// >= k keys under the threshold wcl^2 is exact; otherwise (or if an image
-// component falls outside [-16, 15]) the source goes to the extended pass.
+// Cell-list pass: one workgroup per home bin of a cell-list structure, the 27
+// stencil bins staged in LDS (cl_tile.h), one wave per source of the home
+// bin. Key ordinal: local dst * 32768 + (t0+16, t1+16, t2+16) in 5 bits each,
+// which is the (dst, t) order. The stencil covers every candidate within wcl,
+// so a stack that holds >= k keys under a threshold at most wcl^2 is exact.
+// The first sweep uses a tighter threshold, tau_scale times the k-th
+// neighbour distance of a uniform density (fewer keys to sort); a source with
+// fewer than k keys under it is swept again at wcl^2, and one with fewer than
+// k under wcl^2 (or an image component outside [-16, 15]) goes to the
+// extended pass.
+constexpr int KNN_CL_CAP = 128;
+
 __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* __restrict__ info, ClWs w,
-                                                const float* __restrict__ frac,
                                                 int32_t* __restrict__ src, int32_t* __restrict__ dst,
                                                 int32_t* __restrict__ image, float* __restrict__ length,
                                                 int32_t* __restrict__ ext_list, Counters* __restrict__ ctr,
-                                                mg_report* __restrict__ rep, int64_t* __restrict__ partials) {
-    __shared__ KnnShared sh;
+                                                mg_report* __restrict__ rep, int64_t* __restrict__ partials,
+                                                float tau_scale) {
+    __shared__ ClTile tile;
+    __shared__ uint64_t sbuf[4][KNN_CL_CAP];
     const int lane = lane_id();
-    const int wv = threadIdx.x >> 6;
-    uint64_t* buf = sh.buf[wv];
+    const int wv = ufirst((int)(threadIdx.x >> 6));
+    uint64_t* buf = sbuf[wv];
     const int64_t total = w.cl_off[B];
     int64_t wave_cand = 0;
-    for (int64_t q = grid_wave(); q < total; q += grid_waves()) {
-        int lo = 0, hi = B;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (w.cl_off[mid] <= q) lo = mid;
-            else hi = mid;
-        }
-        const StructInfo* si = info + lo;
+    for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
+        ClItem it;
+        cl_stage(q, B, info, w, tile, it);
+        const StructInfo* si = it.si;
         const int64_t atom0 = si->atom0;
-        const int64_t i = atom0 + (q - w.cl_off[lo]);
-        const int m[3] = {si->m[0], si->m[1], si->m[2]};
-        double L[9];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) L[r] = si->L[r];
-        const int lb = ufirst(w.atom_bin[i]);
-        const int b2 = lb % m[2], b1 = (lb / m[2]) % m[1], b0 = lb / (m[2] * m[1]);
-        const int32_t shi = ufirst(w.atom_shift[i]);
-        const int si0 = unpack_t0(shi), si1 = unpack_t1(shi), si2 = unpack_t2(shi);
-        const double x0 = frac[3 * i], x1 = frac[3 * i + 1], x2 = frac[3 * i + 2];
-        const double xw0 = x0 - floor(x0), xw1 = x1 - floor(x1), xw2 = x2 - floor(x2);
-        const int64_t* bst = w.bin_start + si->bin_off;
+        const int n = si->n;
         const float wc = si->wcl;
-        Stack st{0, wc * wc};
-        int overflow = si->n >= 131072 ? 1 : 0;   // local dst index must fit 17 bits
-        int64_t ncand = 0;
-        for (int d = 0; d < 27; ++d) {
-            int nb0 = b0 + d / 9 - 1, nb1 = b1 + (d / 3) % 3 - 1, nb2 = b2 + d % 3 - 1;
-            const int u0 = nb0 < 0 ? -1 : (nb0 >= m[0] ? 1 : 0);
-            const int u1 = nb1 < 0 ? -1 : (nb1 >= m[1] ? 1 : 0);
-            const int u2 = nb2 < 0 ? -1 : (nb2 >= m[2] ? 1 : 0);
-            nb0 -= u0 * m[0];
-            nb1 -= u1 * m[1];
-            nb2 -= u2 * m[2];
-            const int nb = (nb0 * m[1] + nb1) * m[2] + nb2;
-            const double f0 = (double)nb0 / m[0] + u0 - xw0;
-            const double f1 = (double)nb1 / m[1] + u1 - xw1;
-            const double f2 = (double)nb2 / m[2] + u2 - xw2;
-            const float qx = (float)(f0 * L[0] + f1 * L[3] + f2 * L[6]);
-            const float qy = (float)(f0 * L[1] + f1 * L[4] + f2 * L[7]);
-            const float qz = (float)(f0 * L[2] + f1 * L[5] + f2 * L[8]);
-            const int64_t p0 = bst[nb], p1 = bst[nb + 1];
-            ncand += p1 - p0;
-            for (int64_t pb = p0; pb < p1; pb += WAVE) {
-                const int64_t p = pb + lane;
-                bool pass = false;
-                float l2 = 0.0f;
-                uint32_t ord = 0;
-                if (p < p1) {
-                    const float4 e = w.slot_pos[p];
-                    const int32_t j = __float_as_int(e.w);
-                    const float dx = e.x + qx, dy = e.y + qy, dz = e.z + qz;
-                    l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    pass = l2 < st.tau2 && (int64_t)j != i;
-                    if (pass) {
-                        const int32_t shj = w.atom_shift[j];
-                        const int t0 = u0 - unpack_t0(shj) + si0, t1 = u1 - unpack_t1(shj) + si1,
-                                  t2 = u2 - unpack_t2(shj) + si2;
-                        const bool fits = t0 >= -16 && t0 <= 15 && t1 >= -16 && t1 <= 15 && t2 >= -16 && t2 <= 15;
-                        overflow |= fits ? 0 : 1;
-                        ord = (uint32_t)(j - atom0) * 32768u + (uint32_t)(((t0 + 16) * 32 + (t1 + 16)) * 32 + (t2 + 16));
-                        pass = fits;
+        const float full = wc * wc;
+        float first = full;
+        {   // k-th neighbour distance of a uniform density n / V: (4/3) pi r^3 n / V = k
+            const double* L = it.L;
+            const double det = L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
+                               L[2] * (L[3] * L[7] - L[4] * L[6]);
+            const double rk = cbrt(3.0 * (double)k * fabs(det) / (4.0 * 3.14159265358979323846 * (double)n));
+            const double r = (double)tau_scale * rk;
+            if (tau_scale > 0.0f && r * r < (double)full) first = ufirstf((float)(r * r));
+        }
+        const int T = it.total;
+        for (int64_t r = it.hs + wv; r < it.he; r += 4) {
+            const ClSource S = cl_source(it, w, r);
+            const int s0 = unpack_t0(S.sh), s1 = unpack_t1(S.sh), s2 = unpack_t2(S.sh);
+            float tau = first;
+            bool done = false;
+            int overflow = n >= 131072 ? 1 : 0;   // local dst index must fit 17 bits
+            for (int attempt = 0; attempt < 2; ++attempt) {
+                Stack st{0, tau};
+                for (int cb = 0; cb < T; cb += WAVE) {
+                    const int c = cb + lane;
+                    bool pass = false;
+                    float l2 = 0.0f;
+                    uint32_t ord = 0;
+                    if (c < T) {
+                        int32_t ct;
+                        const float4 e = cl_candidate(tile, it, w, c, ct);
+                        const int32_t j = __float_as_int(e.w);
+                        const float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
+                        l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        pass = l2 < st.tau2 && (int64_t)j != S.i;
+                        if (pass) {
+                            const int t0 = unpack_t0(ct) + s0, t1 = unpack_t1(ct) + s1, t2 = unpack_t2(ct) + s2;
+                            const bool fits = t0 >= -16 && t0 <= 15 && t1 >= -16 && t1 <= 15 && t2 >= -16 && t2 <= 15;
+                            overflow |= fits ? 0 : 1;
+                            ord = (uint32_t)(j - atom0) * 32768u +
+                                  (uint32_t)(((t0 + 16) * 32 + (t1 + 16)) * 32 + (t2 + 16));
+                            pass = fits;
+                        }
                     }
+                    stack_push<KNN_CL_CAP>(st, pass, l2, ord, k, buf, lane);
                 }
-                stack_push(st, pass, l2, ord, k, buf, lane);
+                wave_lds_sync();
+                wave_cand += T;
+                const int any_overflow = ufirst(ballot(overflow != 0) != 0 ? 1 : 0);
+                if (st.cnt >= k && !any_overflow) {
+                    const uint64_t key = sorted_head(buf, st.cnt, lane);
+                    if (lane < k) {
+                        const uint32_t qv = (uint32_t)key;
+                        const uint32_t jl = qv >> 15, tc = qv & 32767u;
+                        const int64_t e = S.i * k + lane;
+                        src[e] = (int32_t)S.i;
+                        dst[e] = (int32_t)(atom0 + jl);
+                        image[3 * e] = (int)(tc >> 10) - 16;
+                        image[3 * e + 1] = (int)((tc >> 5) & 31u) - 16;
+                        image[3 * e + 2] = (int)(tc & 31u) - 16;
+                        length[e] = key_len(key);
+                    }
+                    done = true;
+                }
+                wave_lds_sync();   // buf is reused by the next attempt or source
+                if (done || any_overflow || !(tau < full)) break;
+                tau = full;
+            }
+            if (!done && lane == 0) {
+                const uint32_t pos = atomicAdd(&ctr->knn2_count, 1u);
+                ext_list[pos] = (int32_t)S.i;
+                atomicAdd((unsigned long long*)&rep->knn_extended, 1ull);
+                atomicOr(&rep->flags, (uint32_t)MG_FLAG_KNN_EXTENDED);
             }
         }
-        wave_lds_sync();
-        wave_cand += ncand;
-        const int any_overflow = ufirst(ballot(overflow != 0) != 0 ? 1 : 0);
-        if (st.cnt >= k && !any_overflow) {
-            const uint64_t key = sorted_head(buf, st.cnt, lane);
-            if (lane < k) {
-                const uint32_t qv = (uint32_t)key;
-                const uint32_t jl = qv >> 15, tc = qv & 32767u;
-                const int64_t e = i * k + lane;
-                src[e] = (int32_t)i;
-                dst[e] = (int32_t)(atom0 + jl);
-                image[3 * e] = (int)(tc >> 10) - 16;
-                image[3 * e + 1] = (int)((tc >> 5) & 31u) - 16;
-                image[3 * e + 2] = (int)(tc & 31u) - 16;
-                length[e] = key_len(key);
-            }
-        } else if (lane == 0) {
-            const uint32_t pos = atomicAdd(&ctr->knn2_count, 1u);
-            ext_list[pos] = (int32_t)i;
-            atomicAdd((unsigned long long*)&rep->knn_extended, 1ull);
-            atomicOr(&rep->flags, (uint32_t)MG_FLAG_KNN_EXTENDED);
-        }
+        __syncthreads();   // the next item overwrites the tile
     }
     if (lane == 0) partials[grid_wave()] = wave_cand;
 }
@@ -561,10 +561,11 @@ hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const int
 hipError_t launch_cl_knn(int B, int k, const StructInfo* info, const ClWs& w, const float* frac,
                          int32_t* src, int32_t* dst, int32_t* image, float* length,
                          int32_t* ext_list, Counters* ctr, mg_report* report, int64_t* partials,
-                         int grid, hipStream_t s) {
+                         int grid, float tau_scale, hipStream_t s) {
+    (void)frac;
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_knn_cl, dim3(grid), dim3(256), 0, s, B, k, info, w, frac, src, dst, image, length,
-                       ext_list, ctr, report, partials);
+    hipLaunchKernelGGL(k_knn_cl, dim3(grid), dim3(256), 0, s, B, k, info, w, src, dst, image, length,
+                       ext_list, ctr, report, partials, tau_scale);
     return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ struct alignas(16) StructInfo {
     int32_t m[3];       // cell lists: bins per lattice direction
     int32_t nbins;      // cell lists: m0 * m1 * m2
     int64_t bin_off;    // cell lists: first bin in the global bin arrays
-    int32_t cl_items;   // cell lists: work items (one per source)
+    int32_t cl_items;   // cell lists: work items (one per bin)
     float wcl;          // cell lists: radius covered by the 27-bin stencil (Angstrom)
     // image tests (FP64): lattice-plane spacings, (R + half the longest cell
     // diagonal)^2 and the metric tensor G = L L^T (00 01 02 11 12 22)
@@ -240,19 +240,23 @@ hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int6
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
                               hipStream_t s);
 struct ClWs {
-    int64_t* cl_off;        // [B+1] scan of cell-list items
+    int64_t* cl_off;        // [B+1] scan of cell-list items (one item per bin)
     uint32_t* bin_count;    // [cap] atoms per bin
-    uint32_t* bin_fill;     // [cap] scatter cursors
     int64_t* bin_start;     // [cap+1] first slot of every bin
     int64_t* bsum;          // scan partials
     int32_t* atom_bin;      // [N] bin of every atom (local to its structure)
-    int32_t* atom_shift;    // [N] packed floor(x) of every atom
-    int32_t* slot_atom;     // [N] atoms in bin order
-    float4* slot_pos;       // [N] position relative to the bin origin (xyz) and atom (w)
+    int32_t* atom_rank;     // [N] arrival order of every atom in its bin (from the histogram)
+    int32_t* slot_atom;     // [N] atoms in bin order, unsorted inside a bin
+    float4* slot_x;         // [N] raw coordinates (xyz) and atom index (w) in bin order, ascending atoms inside a bin
+    int32_t* slot_shift;    // [N] packed floor(x) in the same order
     int32_t* atom_struct;   // [N] structure of every atom
     Counters* ctr;          // workspace counters (bin totals)
     int64_t cap;            // bin capacity
 };
+// Cell lists pack floor(x) of every atom (and u - floor(x)) in 10-bit fields:
+// a structure with a coordinate outside [-CL_SHIFT_MAX, CL_SHIFT_MAX + 1)
+// takes the image sweep.
+constexpr int CL_SHIFT_MAX = TMAX - 1;
 hipError_t launch_cl_build(int B, int64_t N, const float* frac, const int64_t* batch_ptr,
                            const StructInfo* info, const ClWs& w, hipStream_t s);
 // vec (nullable, float [capacity][3]): the fill also writes every edge's vector.
@@ -261,10 +265,12 @@ hipError_t launch_cl_cutoff_sweep(int mode, int B, const StructInfo* info, const
                                   const int64_t* offsets, int64_t capacity, int32_t* src,
                                   int32_t* dst, int32_t* image, float* length, float* vec, Counters* ctr,
                                   mg_report* report, int64_t* partials, int grid, hipStream_t s);
+// tau_scale: the first sweep's threshold is tau_scale times the k-th
+// neighbour distance of a uniform density (0: the stencil's covered radius).
 hipError_t launch_cl_knn(int B, int k, const StructInfo* info, const ClWs& w, const float* frac,
                          int32_t* src, int32_t* dst, int32_t* image, float* length,
                          int32_t* ext_list, Counters* ctr, mg_report* report, int64_t* partials,
-                         int grid, hipStream_t s);
+                         int grid, float tau_scale, hipStream_t s);
 // Image tables: every structure's box-sized slot (box), keep flags and their
 // exclusive scan over the whole capacity, and the compacted tables read by the
 // sweeps (table: each structure's kept images contiguous, lexicographic).

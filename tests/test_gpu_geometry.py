@@ -241,3 +241,44 @@ def test_backward_empty_structures_and_no_edges():
     run.backward(L, X, P, z, z, torch.zeros((0, 3), dtype=torch.int32, device="cuda"),
                  torch.zeros((0, 3), device="cuda"), None, gf, gL)
     assert float(gf.abs().max()) == 0.0 and float(gL.abs().max()) == 0.0
+
+
+def test_backward_config4_sampled_finite_differences():
+    """The 1024-structure differentiation workload: the GPU gradient of
+    loss = sum_e w_e exp(-(l_e - 3)^2) (through the autograd function) against
+    FP64 central differences (h = 1e-6) of sum_e (dloss/dl_e) l_e, on the fixed
+    edge set, for 64 sampled atoms and 16 sampled lattices; error per entry at
+    most 1e-4 of the largest oracle gradient entry of the structure."""
+    b = inputs.make_config(4)
+    g, (s, d, t, ln) = _edges(b)
+    order = np.lexsort((t[:, 2], t[:, 1], t[:, 0], d, s))
+    w = np.empty(len(s), np.float32)
+    w[order] = inputs.loss_weights(len(s))
+    L, X, P = gu.dev(b)
+    L.requires_grad_(True)
+    X.requires_grad_(True)
+    vec, length = graph.edge_geometry(L, X, P, g.src, g.dst, g.image)
+    loss = (torch.from_numpy(w).cuda() * torch.exp(-(length - 3.0) ** 2)).sum()
+    loss.backward()
+    gf, gL = X.grad.cpu().numpy(), L.grad.cpu().numpy()
+    l64 = oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, s, d, t)[1]
+    gl64 = oracle.gaussian_loss_grad_len64(l64, w)
+    gf64, gL64 = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, None, gl64)
+    rng = np.random.default_rng(44)
+    atoms = np.sort(rng.choice(b.N, 64, replace=False))
+    structs = np.sort(rng.choice(b.B, 16, replace=False))
+    # only the edges that touch a sampled atom or structure are needed by the differences
+    s_of = np.searchsorted(b.batch_ptr, s, side="right") - 1
+    keep = np.isin(s, atoms) | np.isin(d, atoms) | np.isin(s_of, structs)
+    ff, fL = oracle.fd_vjp64(b.lattices, b.frac, b.batch_ptr, s[keep], d[keep], t[keep], None, gl64[keep],
+                             h=1e-6, atoms=atoms.tolist(), structures=structs.tolist())
+    worst = 0.0
+    for a in atoms:
+        q = int(np.searchsorted(b.batch_ptr, a, side="right")) - 1
+        scale = max(np.abs(gf64[b.batch_ptr[q]:b.batch_ptr[q + 1]]).max(), 1e-300)
+        worst = max(worst, np.abs(gf[a] - ff[a]).max() / scale)
+    for q in structs:
+        scale = max(np.abs(gL64[q]).max(), 1e-300)
+        worst = max(worst, np.abs(gL[q] - fL[q]).max() / scale)
+    print("worst relative error against finite differences", worst)
+    assert worst <= 1e-4
