@@ -42,6 +42,7 @@ BYTES_PER_EDGE_SRC = 4.0       # src, written from the row offsets after the fil
 BYTES_PER_EDGE_VEC = 12.0      # the edge vector, when the fill emits it
 BYTES_PER_EDGE_GEOM = 36.0     # forward: read src, dst, image (20) + write vec, length (16)
 BYTES_PER_EDGE_GEOM_BWD = 24.0 # backward with the length gradient only: read src, dst, image (20) + grad (4)
+BYTES_PER_EDGE_KNN = 24.0      # KNN rows: src, dst, image, length
 FLOPS_PER_CANDIDATE = 8.0      # 3 add + 1 mul + 2 fma (= 8 flops) per (source, destination, image)
 
 
@@ -387,6 +388,15 @@ def main(argv=None):
         roof = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
                 "unit": d["unit"], "frac": d["frac"], "traffic": measured_traffic(dom)}
 
+    # ---- the whole step against the same roof: the algorithmic bytes of all its
+    # HBM-bound phases (cutoff rows with vectors, src, KNN rows, backward) over the
+    # measured time of the step
+    step_bytes = ((BYTES_PER_EDGE_FILL + BYTES_PER_EDGE_SRC + BYTES_PER_EDGE_GEOM_BWD
+                   + (BYTES_PER_EDGE_VEC if fused else BYTES_PER_EDGE_GEOM)) * E + BYTES_PER_EDGE_KNN * N * k)
+    step_ach = step_bytes / (ms_step * 1e-3) / 1e9
+    roof_step = {"bound": "hbm", "algorithmic_bytes": int(step_bytes), "achieved": round(step_ach, 1),
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_ach / HBM_PEAK_GBS, 4)}
+
     # ---- per-structure launch form (the plain method, one launch sequence per structure)
     plain = None
     if not args.no_plain:
@@ -410,6 +420,7 @@ def main(argv=None):
                                   else "; edge vectors and lengths by the separate geometry kernel"),
                    "structures": B, "atoms": N, "cutoff_edges": E, "knn_edges": N * k, "cutoff": c, "k": k},
         "roofline": roof,
+        "roofline_step": roof_step,
         "phases": per,
         "plain": plain,
         "vs_plain": round((B / (ms_step / 1e3)) / plain["value"], 2) if plain else None,

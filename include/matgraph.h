@@ -111,6 +111,14 @@ size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_cap
 /* Workspace bytes for mg_edge_geometry / mg_edge_geometry_backward. */
 size_t mg_geometry_workspace_bytes(int32_t B, int64_t N);
 
+/* Workspace bytes with which mg_edge_geometry_backward on E edges takes its
+ * faster path for structures of more than 512 (and at most 131072) atoms: the
+ * destination side of those structures is transposed through per-block buckets
+ * (16 bytes per edge and a small counts table) instead of global atomics.
+ * Any workspace of at least mg_geometry_workspace_bytes(B, N) stays valid;
+ * the call takes the bucket path only when the workspace is this large. */
+size_t mg_geometry_backward_workspace_bytes(int32_t B, int64_t N, int64_t E);
+
 /* Workspace bytes for mg_triplets on a graph of N source atoms (0 if N < 0). */
 size_t mg_triplets_workspace_bytes(int64_t N);
 
@@ -340,7 +348,9 @@ typedef struct mg_tuning {
                                      times the k-th neighbour distance of a uniform density (sources
                                      with fewer than k there are swept again at the full stencil
                                      radius); default 10 */
-    int32_t reserved[3];
+    int32_t cutoff_img_group;     /* image-table entries the cutoff sweep reads per scalar load group
+                                     (2, 4 or 8; default 4) */
+    int32_t reserved[2];
 } mg_tuning;
 
 /* [host] Read / replace the tuning parameters used by later calls. */

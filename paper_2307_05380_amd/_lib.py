@@ -38,7 +38,8 @@ REPORT_BYTES = 64
 class MgTuning(ctypes.Structure):
     _fields_ = [("cutoff_wgs_per_cu", ctypes.c_int32), ("cutoff_slots", ctypes.c_int32),
                 ("knn_wgs_per_cu", ctypes.c_int32), ("knn_lambda_x4", ctypes.c_int32),
-                ("knn_cl_tau_x8", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("knn_cl_tau_x8", ctypes.c_int32), ("cutoff_img_group", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class MatgraphError(RuntimeError):
@@ -60,6 +61,7 @@ SIGNATURES = {
     "mg_cutoff_workspace_bytes": (_SZ, [_I32, _I64, _I64]),
     "mg_knn_workspace_bytes": (_SZ, [_I32, _I64, _I32, _I64]),
     "mg_geometry_workspace_bytes": (_SZ, [_I32, _I64]),
+    "mg_geometry_backward_workspace_bytes": (_SZ, [_I32, _I64, _I64]),
     "mg_cutoff_graph": (_I32, [_P, _P, _P, _I32, _I64, _F, _I64, _P, _P, _P, _P, _P, _P, _P, _SZ,
                                _I32, _P]),
     "mg_cutoff_graph_radii": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P,

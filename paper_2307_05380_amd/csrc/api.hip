@@ -39,7 +39,7 @@ mg_status mg::api_fail(mg_status st, const char* msg) { return fail(st, "%s", ms
 namespace {
 
 std::mutex g_mu;
-mg_tuning g_tune = {32, 2, 8, 6, 10, {0, 0, 0}};
+mg_tuning g_tune = {32, 2, 8, 6, 10, 4, {0, 0}};
 
 mg_tuning tuning() {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -219,14 +219,33 @@ struct GeomWs {
     size_t fixed;
 };
 
-GeomWs carve_geom(void* ws, int B, int64_t N) {
+// The backward pass's workspace: the fixed part, and with E > 0 the bucket
+// path's counts, scan and E edge records after it (same fixed part first, so a
+// workspace of either size carves the same fixed layout).
+GeomWs carve_geom(void* ws, int B, int64_t N, int64_t E = 0) {
     Carver c{static_cast<char*>(ws)};
     GeomWs w;
     w.atom_struct = c.take<int32_t>((size_t)N);
     w.bwd.acc = c.take<double>((size_t)B * 9);
     w.bwd.start = c.take<int64_t>((size_t)B + 1);
     w.bwd.item_off = c.take<int64_t>((size_t)B + 1);
-    w.bwd.flag = c.take<int32_t>(4);   // order flag, then item counts by structure size (see geometry)
+    w.bwd.flag = c.take<int32_t>(4);   // order flag, item counts by structure size, bucket path (see geometry)
+    w.bwd.cm_off = w.bwd.p3_off = nullptr;
+    w.bwd.bcount = nullptr;
+    w.bwd.boff = w.bwd.bsum = nullptr;
+    w.bwd.rec = nullptr;
+    w.bwd.m_cap = w.bwd.e_cap = 0;
+    if (E > 0) {
+        const int64_t m = mg::bk_count_capacity(B, E);
+        w.bwd.cm_off = c.take<int64_t>((size_t)B + 1);
+        w.bwd.p3_off = c.take<int64_t>((size_t)B + 1);
+        w.bwd.bcount = c.take<uint32_t>((size_t)m);
+        w.bwd.boff = c.take<int64_t>((size_t)m + 1);
+        w.bwd.bsum = c.take<int64_t>((size_t)mg::scan_block_count(m) + 1);
+        w.bwd.rec = c.take<float4>((size_t)E);
+        w.bwd.m_cap = m;
+        w.bwd.e_cap = E;
+    }
     w.fixed = mg::align_up(c.used, 256);
     return w;
 }
@@ -365,6 +384,11 @@ size_t mg_geometry_workspace_bytes(int32_t B, int64_t N) {
     return carve_geom(nullptr, B, N).fixed;
 }
 
+size_t mg_geometry_backward_workspace_bytes(int32_t B, int64_t N, int64_t E) {
+    if (B < 0 || N < 0 || E < 0) return 0;
+    return carve_geom(nullptr, B, N, E).fixed;
+}
+
 }  // extern "C"
 
 namespace {
@@ -420,7 +444,8 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
     if ((e = phase("cutoff.count", s, [&] {
              const hipError_t r = mg::launch_cutoff_sweep(0, B, w.info, w.item_off, w.ccount, w.img.table, frac, c2,
                                                           thr, w.counts, offs, capacity, src, dst, image, length, vec,
-                                                          w.ctr, report, w.partials, grid, tu.cutoff_slots, s);
+                                                          w.ctr, report, w.partials, grid, tu.cutoff_slots,
+                                                          tu.cutoff_img_group, s);
              // row totals and in-row offsets of the image-chunked structures
              return r != hipSuccess ? r : mg::launch_chunk_prefix(B, w.info, w.counts, w.ccount, s);
          })) != hipSuccess)
@@ -440,7 +465,7 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
     if ((e = phase("cutoff.fill", s, [&] {
              return mg::launch_cutoff_sweep(1, B, w.info, w.item_off, w.ccount, w.img.table, frac, c2, thr, w.counts, offs,
                                             capacity, src, dst, image, length, vec, w.ctr, report, w.partials,
-                                            grid, tu.cutoff_slots, s);
+                                            grid, tu.cutoff_slots, tu.cutoff_img_group, s);
          })) != hipSuccess)
         return hip_fail(e, "fill");
     if (cl && (e = phase("cutoff.cells.fill", s, [&] {
@@ -661,6 +686,10 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac, co
     if (workspace_bytes < w.fixed)
         return fail(MG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
                     workspace_bytes, w.fixed);
+    if (E > 0) {   // room for the bucket path of large structures
+        const GeomWs wb = carve_geom(workspace, B, N, E);
+        if (workspace_bytes >= wb.fixed) w = wb;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
     // (the backward pass writes the atom -> structure map itself)
@@ -774,12 +803,16 @@ mg_status mg_set_tuning(const mg_tuning* in) {
         return fail(MG_ERR_INVALID_ARG, "knn_lambda_x4 must be in 0..64");
     if (in->knn_cl_tau_x8 < 0 || in->knn_cl_tau_x8 > 64)
         return fail(MG_ERR_INVALID_ARG, "knn_cl_tau_x8 must be in 0..64");
+    if (in->cutoff_img_group != 0 && in->cutoff_img_group != 2 && in->cutoff_img_group != 4 &&
+        in->cutoff_img_group != 8)
+        return fail(MG_ERR_INVALID_ARG, "cutoff_img_group must be 2, 4 or 8");
     std::lock_guard<std::mutex> lk(g_mu);
     if (in->cutoff_wgs_per_cu) g_tune.cutoff_wgs_per_cu = in->cutoff_wgs_per_cu;
     if (in->cutoff_slots) g_tune.cutoff_slots = in->cutoff_slots;
     if (in->knn_wgs_per_cu) g_tune.knn_wgs_per_cu = in->knn_wgs_per_cu;
     if (in->knn_lambda_x4) g_tune.knn_lambda_x4 = in->knn_lambda_x4;
     if (in->knn_cl_tau_x8) g_tune.knn_cl_tau_x8 = in->knn_cl_tau_x8;
+    if (in->cutoff_img_group) g_tune.cutoff_img_group = in->cutoff_img_group;
     return MG_OK;
 }
 

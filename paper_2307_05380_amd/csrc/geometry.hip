@@ -133,7 +133,6 @@ __global__ __launch_bounds__(256) void k_zero_bwd(float* __restrict__ gf, int64_
 //   raised, whatever the item kernels wrote is cleared and the general kernel
 //   takes every edge in chunks of BW_CHUNK, whatever their order.
 // Both kernels are launched; each leaves the items of the other at once.
-constexpr int BW_CHUNK = 16384;   // edges per item
 constexpr int BW_SMALL = 128;     // atoms of the small LDS window
 constexpr int BW_WIN = 512;       // atoms of a structure held in LDS
 
@@ -208,21 +207,39 @@ __global__ __launch_bounds__(256) void k_geom_ranges(const int32_t* __restrict__
 // BW_CHUNK edges, at least one per structure); item_off[B] = total.
 // flag[1] and flag[2] count the structures of BW_SMALL < n <= BW_WIN atoms and
 // of more than BW_WIN atoms, so that the kernels for those sizes return at
-// once when there are none.
+// once when there are none. With the bucket path's workspace (cm_off set), the
+// structures of BW_WIN < n <= BK_MAX_BLOCKS * BK_BLOCK atoms get
+// nblk = ceil(n / BK_BLOCK) destination blocks: cm_off scans nblk x items
+// (their per-(block, chunk) counts) and p3_off scans nblk (their gather
+// items); flag[3] = 1 when the counts and the records fit the workspace.
 __global__ __launch_bounds__(1024) void k_bwd_items(const int64_t* __restrict__ start,
                                                     const int64_t* __restrict__ batch_ptr, int B,
-                                                    int64_t* __restrict__ item_off, int32_t* __restrict__ flag) {
-    __shared__ int64_t sh[1024];
+                                                    int64_t* __restrict__ item_off, int32_t* __restrict__ flag,
+                                                    int64_t* __restrict__ cm_off, int64_t* __restrict__ p3_off,
+                                                    int64_t m_cap, int64_t e_cap) {
+    __shared__ int64_t sh[3][1024];
     const int t = threadIdx.x;
     const int per = (B + 1023) / 1024;
     const int s0 = min(B, t * per), s1 = min(B, s0 + per);
-    int64_t sum = 0;
+    int64_t sum[3] = {0, 0, 0};
     bool bad = false;   // ranges that are not ordered (edges not grouped)
     int mid = 0, big = 0;
+    auto sizes = [&](int q, int64_t& items, int64_t& cm, int64_t& p3) {
+        const int64_t n = start[q + 1] - start[q];
+        const int64_t na = batch_ptr[q + 1] - batch_ptr[q];
+        items = n > BW_CHUNK ? (n + BW_CHUNK - 1) / BW_CHUNK : 1;
+        const bool bk = cm_off && na > BW_WIN && na <= (int64_t)BK_MAX_BLOCKS * BK_BLOCK;
+        p3 = bk ? (na + BK_BLOCK - 1) / BK_BLOCK : 0;
+        cm = p3 * items;
+    };
     for (int q = s0; q < s1; ++q) {
         const int64_t n = start[q + 1] - start[q];
         bad |= n < 0;
-        sum += n > BW_CHUNK ? (n + BW_CHUNK - 1) / BW_CHUNK : 1;
+        int64_t it, cm, p3;
+        sizes(q, it, cm, p3);
+        sum[0] += it;
+        sum[1] += cm;
+        sum[2] += p3;
         const int64_t na = batch_ptr[q + 1] - batch_ptr[q];
         mid += (na > BW_SMALL && na <= BW_WIN) ? 1 : 0;
         big += na > BW_WIN ? 1 : 0;
@@ -230,21 +247,42 @@ __global__ __launch_bounds__(1024) void k_bwd_items(const int64_t* __restrict__ 
     if (bad) atomicOr(flag, 1);
     if (mid) atomicAdd(flag + 1, mid);
     if (big) atomicAdd(flag + 2, big);
-    sh[t] = sum;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) sh[r][t] = sum[r];
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
-        const int64_t y = t >= d ? sh[t - d] : 0;
+        int64_t y[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) y[r] = t >= d ? sh[r][t - d] : 0;
         __syncthreads();
-        sh[t] += y;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) sh[r][t] += y[r];
         __syncthreads();
     }
-    int64_t run = sh[t] - sum;
+    int64_t run[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) run[r] = sh[r][t] - sum[r];
     for (int q = s0; q < s1; ++q) {
-        item_off[q] = run;
-        const int64_t n = start[q + 1] - start[q];
-        run += n > BW_CHUNK ? (n + BW_CHUNK - 1) / BW_CHUNK : 1;
+        item_off[q] = run[0];
+        int64_t it, cm, p3;
+        sizes(q, it, cm, p3);
+        if (cm_off) {
+            cm_off[q] = run[1];
+            p3_off[q] = run[2];
+        }
+        run[0] += it;
+        run[1] += cm;
+        run[2] += p3;
     }
-    if (t == 1023) item_off[B] = sh[1023];
+    if (t == 1023) {
+        item_off[B] = sh[0][1023];
+        if (cm_off) {
+            cm_off[B] = sh[1][1023];
+            p3_off[B] = sh[2][1023];
+            // every edge of a bucketed structure gets one record; at most start[B] of them
+            if (!bad && sh[2][1023] > 0 && sh[1][1023] <= m_cap && start[B] <= e_cap) flag[3] = 1;
+        }
+    }
 }
 
 // Item `item` of the grouped order: its structure, edge range and whether it
@@ -521,6 +559,304 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
     }
 }
 
+// Bucket path for structures of BW_WIN < n <= BK_MAX_BLOCKS * BK_BLOCK atoms.
+// Global float atomics cost about as much per update as a whole edge's
+// streaming, and one per destination would dominate the pass, so the
+// destination side is transposed instead: every edge's coordinate-gradient
+// term is written as a record into the bucket of its destination block
+// (BK_BLOCK atoms), and one workgroup per block sums its bucket in LDS and
+// adds the block to grad_frac once. Three passes over the items of the
+// grouped order: count edges per (block, chunk) in an LDS histogram, a scan of
+// the counts in (structure, block, chunk) order gives every bucket's start,
+// then the scatter pass computes the terms, places each record at its
+// bucket's start plus an LDS cursor, sums the source side per source run (a
+// few global atomics per source) and the lattice gradient in registers (nine
+// FP64 atomics per item). Edges outside the item's structure set the order
+// flag, as in the LDS kernels, and the general kernel then redoes everything.
+__device__ __forceinline__ bool bk_layout(const BwdItem& it, int64_t item, const int64_t* __restrict__ item_off,
+                                          const int64_t* __restrict__ cm_off, int64_t& k, int64_t& chunks,
+                                          int& nblk, int64_t& cmb) {
+    k = item - item_off[it.st];
+    chunks = item_off[it.st + 1] - item_off[it.st];
+    cmb = cm_off[it.st];
+    nblk = (int)((cm_off[it.st + 1] - cmb) / chunks);
+    return nblk > 0;
+}
+
+__global__ __launch_bounds__(256) void k_bk_count(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                                  const int64_t* __restrict__ batch_ptr, int B,
+                                                  const int64_t* __restrict__ start,
+                                                  const int64_t* __restrict__ item_off,
+                                                  const int64_t* __restrict__ cm_off, int32_t* __restrict__ flag,
+                                                  uint32_t* __restrict__ bcount) {
+    __shared__ uint32_t hist[BK_MAX_BLOCKS];
+    if (flag[3] == 0 || flag[0] != 0) return;
+    BwdItem it;
+    if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it)) return;
+    int64_t k, chunks, cmb;
+    int nblk;
+    if (!bk_layout(it, blockIdx.x, item_off, cm_off, k, chunks, nblk, cmb)) return;
+    const int tid = threadIdx.x;
+    for (int d = tid; d < nblk; d += 256) hist[d] = 0u;
+    __syncthreads();
+    const int32_t a0 = (int32_t)it.atom0;
+    bool bad = false;
+    for (int64_t e = it.c0 + tid; e < it.c1; e += 256) {
+        const int i = src[e] - a0, j = dst[e] - a0;
+        const bool ok = (unsigned)i < (unsigned)it.n && (unsigned)j < (unsigned)it.n;
+        bad |= !ok;
+        if (ok) atomicAdd(&hist[j / BK_BLOCK], 1u);
+    }
+    if (ballot(bad) != 0 && (tid & 63) == 0) atomicOr(flag, 2);
+    __syncthreads();
+    for (int d = tid; d < nblk; d += 256) bcount[cmb + (int64_t)d * chunks + k] = hist[d];
+}
+
+template <bool GV, bool GL>
+__global__ __launch_bounds__(256) void k_bk_scatter(const float* __restrict__ lattices, const float* __restrict__ frac,
+                                                    const int64_t* __restrict__ batch_ptr, int B,
+                                                    const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                                    const int32_t* __restrict__ image,
+                                                    const float* __restrict__ gvec, const float* __restrict__ glen,
+                                                    const int64_t* __restrict__ start,
+                                                    const int64_t* __restrict__ item_off,
+                                                    const int64_t* __restrict__ cm_off,
+                                                    const int64_t* __restrict__ boff, int32_t* __restrict__ flag,
+                                                    float* __restrict__ grad_frac, double* __restrict__ acc,
+                                                    float4* __restrict__ rec) {
+    __shared__ int64_t base[BK_MAX_BLOCKS];
+    __shared__ uint32_t cur[BK_MAX_BLOCKS];
+    __shared__ double red[4][15];
+    if (flag[3] == 0 || flag[0] != 0) return;
+    BwdItem it;
+    if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it)) return;
+    int64_t k, chunks, cmb;
+    int nblk;
+    if (!bk_layout(it, blockIdx.x, item_off, cm_off, k, chunks, nblk, cmb)) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int d = tid; d < nblk; d += 256) {
+        base[d] = boff[cmb + (int64_t)d * chunks + k];
+        cur[d] = 0u;
+    }
+    __syncthreads();
+    const int n = it.n;
+    const float* Lp = lattices + 9 * (int64_t)it.st;
+    float Lf[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Lf[q] = Lp[q];
+    double Gm[6];   // metric tensor G = L L^T, wave-uniform
+    {
+        const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double g = (double)Lf[3 * ia[q]] * Lf[3 * ib[q]] + (double)Lf[3 * ia[q] + 1] * Lf[3 * ib[q] + 1] +
+                             (double)Lf[3 * ia[q] + 2] * Lf[3 * ib[q] + 2];
+            const int64_t bits = __double_as_longlong(g);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)bits);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)bits >> 32));
+            Gm[q] = __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+        }
+    }
+    const int32_t a0 = (int32_t)it.atom0;
+    const float* xb = frac + 3 * it.atom0;
+    float* gfb = grad_frac + 3 * it.atom0;
+    // this wave's contiguous quarter of the item
+    const int64_t qlen = ((it.c1 - it.c0 + 3) / 4 + WAVE - 1) / WAVE * WAVE;
+    const int64_t w0 = it.c0 + wv * qlen, w1 = min(it.c1, w0 + qlen);
+    const int r1 = (int)(w1 - it.c0);
+    const int32_t* srcb = src + it.c0;
+    const int32_t* dstb = dst + it.c0;
+    const int32_t* imgb = image + 3 * it.c0;
+    const float* gvb = GV ? gvec + 3 * it.c0 : nullptr;
+    const float* glb = GL ? glen + it.c0 : nullptr;
+    int src_cur = -1;
+    float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f;
+    double lv[9], M[6];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lv[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) M[q] = 0.0;
+    bool bad = false, unsorted = false;
+    auto add_src_run = [&]() {   // lane 0 adds the wave's source run
+        if (src_cur >= 0) {
+            const float r0 = wave_sum_f32(sa0), rr1 = wave_sum_f32(sa1), r2 = wave_sum_f32(sa2);
+            if (lane == 0) {
+                unsafeAtomicAdd(&gfb[3 * src_cur], -r0);
+                unsafeAtomicAdd(&gfb[3 * src_cur + 1], -rr1);
+                unsafeAtomicAdd(&gfb[3 * src_cur + 2], -r2);
+            }
+        }
+        sa0 = sa1 = sa2 = 0.f;
+    };
+    constexpr int U = 4;
+    for (int rb = (int)(w0 - it.c0); rb < r1; rb += WAVE * U) {
+        int ai[U], aj[U], at[U][3];
+        float ag[U][3], al[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t r = (uint32_t)min(rb + u * WAVE + lane, r1 - 1);
+            const uint32_t o4 = r * 4u, o12 = r * 12u;
+            ai[u] = *(const int32_t*)((const char*)srcb + o4) - a0;
+            aj[u] = *(const int32_t*)((const char*)dstb + o4) - a0;
+            const int32_t* ip = (const int32_t*)((const char*)imgb + o12);
+            at[u][0] = ip[0];
+            at[u][1] = ip[1];
+            at[u][2] = ip[2];
+            if (GV) {
+                const float* gp = (const float*)((const char*)gvb + o12);
+                ag[u][0] = gp[0];
+                ag[u][1] = gp[1];
+                ag[u][2] = gp[2];
+            } else {
+                ag[u][0] = ag[u][1] = ag[u][2] = 0.0f;
+            }
+            al[u] = GL ? *(const float*)((const char*)glb + o4) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int base_r = rb + u * WAVE;
+            if (base_r >= r1) break;   // uniform
+            const bool inr = base_r + lane < r1;
+            const bool oki = (unsigned)ai[u] < (unsigned)n;
+            const bool okj = (unsigned)aj[u] < (unsigned)n;
+            bad |= inr && !okj;
+            unsorted |= inr && !oki;
+            const bool act = inr && okj && oki;
+            const int li = oki ? ai[u] : 0, lj = okj ? aj[u] : 0;
+            const double f0 = (double)xb[3 * lj] - (double)xb[3 * li] + (double)at[u][0];
+            const double f1 = (double)xb[3 * lj + 1] - (double)xb[3 * li + 1] + (double)at[u][1];
+            const double f2 = (double)xb[3 * lj + 2] - (double)xb[3 * li + 2] + (double)at[u][2];
+            float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+            if (GL) {   // g = c v, c = g_l / |v|: g L^T = c (G f), f (x) g = c f f^T L
+                const double h0 = Gm[0] * f0 + Gm[1] * f1 + Gm[2] * f2;
+                const double h1 = Gm[1] * f0 + Gm[3] * f1 + Gm[4] * f2;
+                const double h2 = Gm[2] * f0 + Gm[4] * f1 + Gm[5] * f2;
+                const float l2 = (float)(f0 * h0 + f1 * h1 + f2 * h2);
+                float c = l2 > 0.0f ? al[u] * __frsqrt_rn(l2) : 0.0f;
+                c = act ? c : 0.0f;
+                x0 = c * (float)h0;
+                x1 = c * (float)h1;
+                x2 = c * (float)h2;
+                if (acc) {
+                    const double cd = c;
+                    const double c0 = cd * f0, c1 = cd * f1, c2 = cd * f2;
+                    M[0] += c0 * f0; M[1] += c0 * f1; M[2] += c0 * f2;
+                    M[3] += c1 * f1; M[4] += c1 * f2; M[5] += c2 * f2;
+                }
+            }
+            if (GV) {
+                const float g0 = act ? ag[u][0] : 0.0f, g1 = act ? ag[u][1] : 0.0f, g2 = act ? ag[u][2] : 0.0f;
+                x0 += g0 * Lf[0] + g1 * Lf[1] + g2 * Lf[2];
+                x1 += g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
+                x2 += g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
+                if (acc) {
+                    const double d0 = g0, d1 = g1, d2 = g2;
+                    lv[0] += f0 * d0; lv[1] += f0 * d1; lv[2] += f0 * d2;
+                    lv[3] += f1 * d0; lv[4] += f1 * d1; lv[5] += f1 * d2;
+                    lv[6] += f2 * d0; lv[7] += f2 * d1; lv[8] += f2 * d2;
+                }
+            }
+            if (grad_frac) {
+                if (act) {   // destination side: a record in the destination block's bucket
+                    const int d = lj / BK_BLOCK;
+                    const int64_t pos = base[d] + (int64_t)atomicAdd(&cur[d], 1u);
+                    rec[pos] = make_float4(x0, x1, x2, __int_as_float(lj - d * BK_BLOCK));
+                }
+                // source side: runs of one source summed in the wave
+                const int iu = __builtin_amdgcn_readfirstlane(li);
+                const bool uni = ballot(act && li != iu) == 0;
+                if (!(uni && iu == src_cur)) {
+                    add_src_run();
+                    src_cur = uni ? iu : -1;
+                }
+                if (src_cur >= 0) {
+                    sa0 += x0;
+                    sa1 += x1;
+                    sa2 += x2;
+                } else {
+                    const int key = act ? li : -1 - lane;
+                    const int kprev = __shfl_up(key, 1, WAVE);
+                    unsorted |= act && lane > 0 && kprev >= 0 && li < kprev;
+                    const uint64_t heads = ballot(lane == 0 || kprev != key);
+                    const int rs = run_start(heads, lane);
+                    const float y0 = seg_scan(x0, rs, lane), y1 = seg_scan(x1, rs, lane), y2 = seg_scan(x2, rs, lane);
+                    if (act && run_tail(heads, lane)) {
+                        unsafeAtomicAdd(&gfb[3 * li], -y0);
+                        unsafeAtomicAdd(&gfb[3 * li + 1], -y1);
+                        unsafeAtomicAdd(&gfb[3 * li + 2], -y2);
+                    }
+                }
+            }
+        }
+    }
+    if (grad_frac) add_src_run();
+    if (ballot(bad) != 0 && lane == 0) atomicOr(flag, 2);
+    if (ballot(unsorted) != 0 && lane == 0) atomicOr(flag, 1);
+    if (acc) {
+#pragma unroll
+        for (int q = 0; q < 15; ++q) {
+            const double t = wave_sum_f64(q < 9 ? lv[q] : M[q - 9]);
+            if (lane == 0) red[wv][q] = t;
+        }
+        __syncthreads();
+        if (tid < 9) {
+            const int ra = tid / 3, kk = tid - 3 * (tid / 3);
+            auto tot = [&](int q) { return (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]); };
+            auto msym = [](int x, int y) {
+                const int p = x < y ? x : y, q = x < y ? y : x;
+                return 3 * p - (p * (p - 1)) / 2 + (q - p);
+            };
+            double lt = tot(tid);
+#pragma unroll
+            for (int bq = 0; bq < 3; ++bq) lt += tot(9 + msym(ra, bq)) * (double)Lp[3 * bq + kk];
+            unsafeAtomicAdd(&acc[9 * (int64_t)it.st + tid], lt);
+        }
+    }
+}
+
+// Gather: one workgroup per destination block of a bucketed structure sums
+// its bucket's records in LDS and adds them to the block's rows of grad_frac
+// (which then hold only the source-side sums of the scatter pass).
+__global__ __launch_bounds__(512) void k_bk_gather(const int64_t* __restrict__ batch_ptr, int B,
+                                                   const int64_t* __restrict__ item_off,
+                                                   const int64_t* __restrict__ cm_off,
+                                                   const int64_t* __restrict__ p3_off,
+                                                   const int64_t* __restrict__ boff, const int32_t* __restrict__ flag,
+                                                   const float4* __restrict__ rec, float* __restrict__ grad_frac) {
+    __shared__ float accl[BK_BLOCK * 3];
+    if (flag[3] == 0 || flag[0] != 0) return;
+    const int64_t q = blockIdx.x;
+    if (q >= p3_off[B]) return;
+    const int tid = threadIdx.x;
+    const int st = __builtin_amdgcn_readfirstlane(wave_search_le(p3_off, B, q, lane_id()));
+    const int d = (int)(q - p3_off[st]);
+    const int64_t chunks = item_off[st + 1] - item_off[st];
+    const int64_t cmb = cm_off[st];
+    const int64_t r0 = boff[cmb + (int64_t)d * chunks], r1 = boff[cmb + (int64_t)(d + 1) * chunks];
+    for (int x = tid; x < 3 * BK_BLOCK; x += 512) accl[x] = 0.0f;
+    __syncthreads();
+    constexpr int U = 4;
+    for (int64_t r = r0 + tid; r < r1; r += U * 512) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = r + u * 512 < r1 ? rec[r + u * 512] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (r + u * 512 < r1) {
+                const int li = __float_as_int(v[u].w);
+                atomicAdd(&accl[3 * li], v[u].x);
+                atomicAdd(&accl[3 * li + 1], v[u].y);
+                atomicAdd(&accl[3 * li + 2], v[u].z);
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t a0 = batch_ptr[st] + (int64_t)d * BK_BLOCK;
+    const int cnt = (int)min((int64_t)BK_BLOCK, batch_ptr[st + 1] - a0);
+    float* out = grad_frac + 3 * a0;
+    for (int x = tid; x < 3 * cnt; x += 512) out[x] += accl[x];
+}
+
 // After the grouped kernels: if the edges turned out not to be grouped (flag
 // set), clear what they wrote so that the general kernel, which then takes
 // every edge, starts from zero.
@@ -555,6 +891,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ 
                                                       const int64_t* __restrict__ start,
                                                       const int64_t* __restrict__ item_off,
                                                       const int32_t* __restrict__ flag,
+                                                      const int64_t* __restrict__ cm_off,
                                                       float* __restrict__ grad_frac,
                                                       double* __restrict__ acc) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -566,6 +903,7 @@ __global__ __launch_bounds__(256) void k_geom_bwd_any(const float* __restrict__ 
     it.whole = false;
     if (grouped) {
         if (!bwd_item(blockIdx.x, B, start, item_off, batch_ptr, it) || it.n <= BW_WIN) return;
+        if (flag[3] != 0 && cm_off[it.st + 1] > cm_off[it.st]) return;   // taken by the bucket path
         c0 = it.c0;
         c1 = it.c1;
     } else {
@@ -721,7 +1059,8 @@ static void launch_plan(const int32_t* src, const int64_t* batch_ptr, int B, int
                         const GeomBwdWs& w, int32_t* atom_struct, hipStream_t s) {
     hipLaunchKernelGGL(k_geom_ranges, dim3((unsigned)((B + 1 + 3) / 4)), dim3(256), 0, s, src, batch_ptr, B, E,
                        num_edges, w.start, atom_struct);
-    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, batch_ptr, B, w.item_off, w.flag);
+    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s, w.start, batch_ptr, B, w.item_off, w.flag, w.cm_off,
+                       w.p3_off, w.m_cap, w.e_cap);
 }
 
 // Enough workgroups for either order: sum_s max(1, ceil(E_s / chunk)) <= B + ceil(E / chunk).
@@ -752,7 +1091,9 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, int32_t
                            w.acc, z9, w.flag);
     }
     if (E > 0 && B > 0 && (grad_frac || grad_lattice) && (grad_vec || grad_length)) {
-        launch_plan(src, batch_ptr, B, E, num_edges, w, atom_struct, s);
+        GeomBwdWs wb = w;
+        if (!grad_frac) wb.cm_off = nullptr;   // the bucket path is for the coordinate gradients
+        launch_plan(src, batch_ptr, B, E, num_edges, wb, atom_struct, s);
         const unsigned grid = item_grid(B, E);
         double* acc = grad_lattice ? w.acc : nullptr;
         // two LDS sizes: structures of up to 128 atoms (most), and 129..BW_WIN atoms
@@ -769,12 +1110,29 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, int32_t
         else MG_BWD_LDS2(false, true);
 #undef MG_BWD_LDS2
 #undef MG_BWD_LDS
+        if (wb.cm_off) {   // bucket path for the structures of more than BW_WIN atoms
+            hipLaunchKernelGGL(k_bk_count, dim3(grid), dim3(256), 0, s, src, dst, batch_ptr, B, w.start, w.item_off,
+                               w.cm_off, w.flag, w.bcount);
+            hipError_t e = launch_scan_counts(w.bcount, w.m_cap, w.boff, w.bsum, INT64_MAX, nullptr, s, w.cm_off + B);
+            if (e != hipSuccess) return e;
+#define MG_BK(GV, GL)                                                                                          \
+    hipLaunchKernelGGL((k_bk_scatter<GV, GL>), dim3(grid), dim3(256), 0, s, lattices, frac, batch_ptr, B, src, dst, \
+                       image, grad_vec, grad_length, w.start, w.item_off, w.cm_off, w.boff, w.flag, grad_frac, acc, \
+                       w.rec)
+            if (grad_vec && grad_length) MG_BK(true, true);
+            else if (grad_vec) MG_BK(true, false);
+            else MG_BK(false, true);
+#undef MG_BK
+            const int64_t p3_grid = (N + BK_BLOCK - 1) / BK_BLOCK + B;   // >= the blocks of all structures
+            hipLaunchKernelGGL(k_bk_gather, dim3((unsigned)p3_grid), dim3(512), 0, s, batch_ptr, B, w.item_off,
+                               w.cm_off, w.p3_off, w.boff, w.flag, w.rec, grad_frac);
+        }
         const int64_t n3 = grad_frac ? 3 * N : 0, n9 = acc ? 9 * (int64_t)B : 0;
         hipLaunchKernelGGL(k_bwd_fix, dim3(grid_for(n3 + n9, 256, cu * 4)), dim3(256), 0, s, w.flag, grad_frac, n3,
                            acc, n9);
         hipLaunchKernelGGL(k_geom_bwd_any, dim3(grid), dim3(256), 0, s, lattices, frac, atom_struct, batch_ptr, B, N,
                            src, dst, image, E, num_edges, grad_vec, grad_length, w.start, w.item_off, w.flag,
-                           grad_frac, acc);
+                           wb.cm_off, grad_frac, acc);
     }
     if (grad_lattice && B > 0)
         hipLaunchKernelGGL(k_finalize_lattice, dim3(grid_for(9 * (int64_t)B, 256, 1 << 30)), dim3(256), 0, s,

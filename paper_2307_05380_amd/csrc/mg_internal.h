@@ -282,8 +282,6 @@ struct ImageTables {
     ImageEntry* table;
     int64_t cap;
 };
-// The cutoff sweep reads a structure's images in groups of IMG_GROUP entries.
-constexpr int IMG_GROUP = 4;
 // Workspace bytes per image slot (box entry, flag, scan value, compacted entry)
 // and a fixed allowance for scan partials and alignment.
 constexpr int64_t IMAGE_SLOT_BYTES = 45;
@@ -297,7 +295,7 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
                                const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
                                int32_t* src, int32_t* dst, int32_t* image, float* length, float* vec,
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
-                               hipStream_t s);
+                               int img_group, hipStream_t s);
 // src[e] = i for every edge e of source i (offsets = row_ptr), e < capacity.
 hipError_t launch_src_from_rows(const int64_t* offsets, int64_t N, int64_t capacity, int32_t* src, hipStream_t s);
 // Exclusive scan of counts[0..N) into offsets[0..N]; with a report, also
@@ -323,8 +321,28 @@ struct GeomBwdWs {
     double* acc;
     int64_t* start;
     int64_t* item_off;
-    int32_t* flag;   // [4]: order flag, structures of the middle LDS window, structures beyond it, spare
+    int32_t* flag;   // [4]: order flag, structures of the middle LDS window, structures beyond it,
+                     // bucket path active
+    // Bucket path of the backward pass for structures of more than 512 atoms
+    // (all null when the workspace has no room for it): per structure the
+    // offsets of its (dst block, chunk) counts and of its gather items, the
+    // counts, their exclusive scan, scan partials and one record per edge.
+    int64_t* cm_off;     // [B+1]
+    int64_t* p3_off;     // [B+1]
+    uint32_t* bcount;    // [m_cap]
+    int64_t* boff;       // [m_cap + 1]
+    int64_t* bsum;
+    float4* rec;         // [e_cap]
+    int64_t m_cap, e_cap;
 };
+// Bucket path sizes: atoms per destination block (one LDS accumulator block)
+// and the largest structure it takes (more blocks than the per-chunk LDS
+// histogram holds go to the atomic kernel).
+constexpr int BW_CHUNK = 16384;   // edges per backward item
+constexpr int BK_BLOCK = 1024;
+constexpr int BK_MAX_BLOCKS = 128;
+// Counts-matrix capacity for a batch of B structures and E edges.
+inline int64_t bk_count_capacity(int B, int64_t E) { return ((int64_t)B + E / BW_CHUNK + 1) * BK_MAX_BLOCKS; }
 hipError_t launch_geometry_fwd(const float* lattices, const float* frac, const int32_t* atom_struct,
                                const int64_t* batch_ptr, int B, int64_t N, const int32_t* src,
                                const int32_t* dst, const int32_t* image, int64_t E, const int64_t* num_edges,

@@ -61,8 +61,9 @@ __device__ inline Pair make_pair(const float* __restrict__ frac, const double* L
 // The image loop: every lane uses the same image, so the entries are read
 // through the constant address space (scalar loads into SGPRs, waited on by
 // their own counter, never behind the fill's vector stores) and the step's
-// shift operands are scalar registers. Entries are read in groups of
-// IMG_GROUP (one wait per group), the last few one at a time.
+// shift operands are scalar registers. Entries are read in groups of IG
+// (one wait per group; 2, 4 or 8, chosen by the tuning), the last few one at
+// a time.
 typedef const __attribute__((address_space(4))) ImageEntry* ConstTable;
 
 __device__ __forceinline__ ImageEntry image_at(ConstTable tab, int m) {
@@ -74,7 +75,7 @@ __device__ __forceinline__ ImageEntry image_at(ConstTable tab, int m) {
     return e;
 }
 
-template <class Step>
+template <int IG, class Step>
 __device__ __forceinline__ void for_images(const ImageEntry* __restrict__ table, int I, Step&& step) {
     // the table address is wave-uniform; make that explicit so the loads are scalar
     const uint64_t a = (uint64_t)table;
@@ -82,12 +83,12 @@ __device__ __forceinline__ void for_images(const ImageEntry* __restrict__ table,
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
     ConstTable tab = (ConstTable)(((uint64_t)hi << 32) | lo);
     int m = 0;
-    for (; m + IMG_GROUP <= I; m += IMG_GROUP) {
-        ImageEntry e[IMG_GROUP];
+    for (; m + IG <= I; m += IG) {
+        ImageEntry e[IG];
 #pragma unroll
-        for (int u = 0; u < IMG_GROUP; ++u) e[u] = image_at(tab, m + u);
+        for (int u = 0; u < IG; ++u) e[u] = image_at(tab, m + u);
 #pragma unroll
-        for (int u = 0; u < IMG_GROUP; ++u) step(e[u]);
+        for (int u = 0; u < IG; ++u) step(e[u]);
     }
     for (; m < I; ++m) step(image_at(tab, m));
 }
@@ -153,7 +154,7 @@ constexpr int MODE_COUNT = 0, MODE_FILL = 1;
 // k_chunk_prefix turns them into row totals (counts, scanned into row_ptr) and
 // offsets inside the row, and the fill starts chunk k of source i at
 // row_ptr[i] + that offset.
-template <int MODE, int SLOTS>
+template <int MODE, int SLOTS, int IG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_cutoff_sweep(
     int B, const StructInfo* __restrict__ info, const int64_t* __restrict__ item_off,
     uint32_t* __restrict__ ccount, const ImageEntry* __restrict__ table,
@@ -202,10 +203,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             const int k0 = (int)((int64_t)ck * I / C), k1 = (int)((int64_t)(ck + 1) * I / C);
             if (ck == 0) step_x(tab[zimg], true);
             if (zimg >= k0 && zimg < k1) {
-                for_images(tab + k0, zimg - k0, step);
-                for_images(tab + zimg + 1, k1 - zimg - 1, step);
+                for_images<IG>(tab + k0, zimg - k0, step);
+                for_images<IG>(tab + zimg + 1, k1 - zimg - 1, step);
             } else {
-                for_images(tab + k0, k1 - k0, step);
+                for_images<IG>(tab + k0, k1 - k0, step);
             }
         };
         {   // candidates of this item: images of its chunks
@@ -310,21 +311,28 @@ hipError_t launch_cutoff_sweep(int mode, int B, const StructInfo* info, const in
                                const float* thr, uint32_t* counts, const int64_t* offsets, int64_t capacity,
                                int32_t* src, int32_t* dst, int32_t* image, float* length, float* vec,
                                Counters* ctr, mg_report* report, int64_t* partials, int grid, int slots,
-                               hipStream_t s) {
+                               int img_group, hipStream_t s) {
     if (B == 0) return hipSuccess;
-#define MG_SWEEP(M, S)                                                                              \
-    hipLaunchKernelGGL((k_cutoff_sweep<M, S>), dim3(grid), dim3(256), 0, s, B, info, item_off, ccount, table, \
-                       frac, c2thr, thr, counts, offsets, capacity, src, dst, image, length, vec, ctr, report, \
+#define MG_SWEEP(M, S, G)                                                                                      \
+    hipLaunchKernelGGL((k_cutoff_sweep<M, S, G>), dim3(grid), dim3(256), 0, s, B, info, item_off, ccount, table, \
+                       frac, c2thr, thr, counts, offsets, capacity, src, dst, image, length, vec, ctr, report,   \
                        partials)
-    if (mode == MODE_COUNT) {
-        if (slots <= 1) MG_SWEEP(MODE_COUNT, 1);
-        else if (slots == 2) MG_SWEEP(MODE_COUNT, 2);
-        else MG_SWEEP(MODE_COUNT, 4);
-    } else {
-        if (slots <= 1) MG_SWEEP(MODE_FILL, 1);
-        else if (slots == 2) MG_SWEEP(MODE_FILL, 2);
-        else MG_SWEEP(MODE_FILL, 4);
-    }
+#define MG_SWEEP_G(M, S)                       \
+    do {                                       \
+        if (img_group <= 2) MG_SWEEP(M, S, 2); \
+        else if (img_group <= 4) MG_SWEEP(M, S, 4); \
+        else MG_SWEEP(M, S, 8);                \
+    } while (0)
+#define MG_SWEEP_SG(M)                       \
+    do {                                     \
+        if (slots <= 1) MG_SWEEP_G(M, 1);    \
+        else if (slots == 2) MG_SWEEP_G(M, 2); \
+        else MG_SWEEP_G(M, 4);               \
+    } while (0)
+    if (mode == MODE_COUNT) MG_SWEEP_SG(MODE_COUNT);
+    else MG_SWEEP_SG(MODE_FILL);
+#undef MG_SWEEP_SG
+#undef MG_SWEEP_G
 #undef MG_SWEEP
     return hipGetLastError();
 }

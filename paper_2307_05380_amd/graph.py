@@ -384,12 +384,22 @@ class CapturedStep:
 
 
 class GeometryRunner:
-    """Preallocated edge-geometry forward / backward for a fixed batch shape."""
+    """Preallocated edge-geometry forward / backward for a fixed batch shape.
 
-    def __init__(self, B: int, N: int, device=None):
+    The backward pass of a batch with structures of more than 512 atoms runs
+    faster with room for its bucket path (16 bytes per edge,
+    mg_geometry_backward_workspace_bytes): the runner grows its workspace for
+    that on the first backward call with more edges than it has room for
+    (``large=None`` reads the batch's largest structure once to decide;
+    True / False decide without reading it). Growing reallocates: a captured
+    graph that uses the runner must be captured after the first call."""
+
+    def __init__(self, B: int, N: int, device=None, large: bool | None = None):
         self.lib = _lib.load()
         self.device = torch.device(device or "cuda")
         self.B, self.N = int(B), int(N)
+        self.large = large
+        self.bucket_edges = 0
         nbytes = self.lib.mg_geometry_workspace_bytes(self.B, self.N)
         self.workspace = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
 
@@ -402,9 +412,21 @@ class GeometryRunner:
             self.workspace.numel(), _stream(self.device)), self.lib)
         return vec, length
 
+    def _room_for_buckets(self, batch_ptr, E: int):
+        if self.large is None:
+            counts = torch.diff(batch_ptr).max() if self.B > 0 else torch.zeros((), dtype=torch.int64)
+            self.large = bool(int(counts) > 512)
+        if not self.large or E <= self.bucket_edges:
+            return
+        nbytes = int(self.lib.mg_geometry_backward_workspace_bytes(self.B, self.N, E))
+        if nbytes > self.workspace.numel():
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.bucket_edges = E
+
     def backward(self, lattices, frac, batch_ptr, src, dst, image, grad_vec=None,
                  grad_length=None, grad_frac=None, grad_lattice=None, num_edges=None):
         E = int(src.shape[0])
+        self._room_for_buckets(batch_ptr, E)
         _lib.check(self.lib.mg_edge_geometry_backward(
             _ptr(lattices), _ptr(frac), _ptr(batch_ptr), self.B, self.N, _ptr(src), _ptr(dst),
             _ptr(image), E, _ptr(num_edges), _ptr(grad_vec), _ptr(grad_length), _ptr(grad_frac),

@@ -5,7 +5,7 @@ import torch
 
 import gpu_util as gu
 import oracle
-from paper_2307_05380_amd import graph, inputs
+from paper_2307_05380_amd import _lib, graph, inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -182,10 +182,13 @@ def _per_structure_check(b, gf, gL, rf, rL, tol=1e-4):
 
 
 @pytest.mark.parametrize("m", [6, 8])
-def test_backward_supercells(m):
+@pytest.mark.parametrize("buckets", [True, False])
+def test_backward_supercells(m, buckets):
     """Structures large enough that one structure's edges are split over
     several workgroups (m = 6: 1728 atoms, ~10^5 edges) or exceed the LDS
-    atom window (m = 8: 4096 atoms), next to a small structure."""
+    atom window (m = 8: 4096 atoms), next to a small structure; with the
+    workspace of the bucket path (destination side through per-block buckets)
+    and with the minimal workspace (global atomics)."""
     big = inputs.make_config5(B=1, m_lo=m, m_hi=m)
     small = inputs.random_batch(np.random.default_rng(30 + m), 2, 4, 30, 3.0, 7.0, cutoff=5.0)
     b = gu.concat([small, big], cutoff=5.0, k=16)
@@ -194,10 +197,11 @@ def test_backward_supercells(m):
     gv = rng.normal(size=(len(s), 3)).astype(np.float32)
     glen = rng.normal(size=len(s)).astype(np.float32)
     L, X, P = gu.dev(b)
-    run = graph.GeometryRunner(b.B, b.N)
+    run = graph.GeometryRunner(b.B, b.N, large=buckets)
     gf = torch.empty_like(X)
     gL = torch.empty_like(L)
     run.backward(L, X, P, g.src, g.dst, g.image, torch.from_numpy(gv).cuda(), torch.from_numpy(glen).cuda(), gf, gL)
+    assert (run.workspace.numel() >= _lib.load().mg_geometry_backward_workspace_bytes(b.B, b.N, len(s))) == buckets
     rf, rL = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, gv, glen)
     _per_structure_check(b, gf.cpu().numpy(), gL.cpu().numpy(), rf, rL)
 
@@ -282,3 +286,27 @@ def test_backward_config4_sampled_finite_differences():
         worst = max(worst, np.abs(gL[q] - fL[q]).max() / scale)
     print("worst relative error against finite differences", worst)
     assert worst <= 1e-4
+
+
+def test_backward_supercell_shuffled_with_buckets():
+    """A 1728-atom supercell whose edges are shuffled inside the structure,
+    with the bucket path's workspace: the scatter pass finds the sources out
+    of order, and the general kernel redoes the whole pass."""
+    big = inputs.make_config5(B=1, m_lo=6, m_hi=6)
+    small = inputs.random_batch(np.random.default_rng(36), 2, 4, 30, 3.0, 7.0, cutoff=5.0)
+    b = gu.concat([small, big], cutoff=5.0, k=16)
+    g, (s, d, t, ln) = _edges(b)
+    rng = np.random.default_rng(46)
+    blk = np.flatnonzero(s >= b.batch_ptr[2])
+    perm = np.arange(len(s))
+    perm[blk] = rng.permutation(blk)
+    s, d, t = s[perm], d[perm], t[perm]
+    glen = rng.normal(size=len(s)).astype(np.float32)
+    L, X, P = gu.dev(b)
+    run = graph.GeometryRunner(b.B, b.N, large=True)
+    gf = torch.empty_like(X)
+    gL = torch.empty_like(L)
+    ti = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.int32))).cuda()
+    run.backward(L, X, P, ti(s), ti(d), ti(t), None, torch.from_numpy(glen).cuda(), gf, gL)
+    rf, rL = oracle.edge_geometry_vjp64(b.lattices, b.frac, b.batch_ptr, s, d, t, None, glen)
+    _per_structure_check(b, gf.cpu().numpy(), gL.cpu().numpy(), rf, rL)
