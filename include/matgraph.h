@@ -262,6 +262,32 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac,
                                     void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * mg_edge_geometry_backward without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the scratch lives in a device
+ * array of the library, MG_STATIC_SCRATCH_BYTES per GPU, set up on the first
+ * call on each device (with that device current) and kept until the process
+ * ends. The call itself allocates nothing.
+ *  Arguments, results and device flags as mg_edge_geometry_backward.
+ *  Limit: B and N with mg_geometry_workspace_bytes(B, N) <= MG_STATIC_SCRATCH_BYTES
+ *  (about 4.1 million atoms with a few thousand structures); larger batches
+ *  return MG_ERR_UNSUPPORTED and enqueue nothing.
+ *  Every call on one GPU uses that GPU's single scratch array: calls that
+ *  overlap in time on one GPU (other streams or host threads) race and give
+ *  wrong gradients; serialise them. The scratch keeps the last call's contents;
+ *  the call clears what must start at zero itself.
+ * Errors: as mg_edge_geometry_backward, MG_ERR_UNSUPPORTED past the limit,
+ * MG_ERR_HIP when the scratch's device address cannot be obtained.
+ */
+#define MG_STATIC_SCRATCH_BYTES (16u << 20)
+mg_status mg_edge_geometry_backward_static(const float* lattices, const float* frac,
+                                           const int64_t* batch_ptr, int32_t B, int64_t N,
+                                           const int32_t* src, const int32_t* dst, const int32_t* image,
+                                           int64_t E, const int64_t* num_edges,
+                                           const float* grad_vec, const float* grad_length,
+                                           float* grad_frac, float* grad_lattice, void* stream);
+
+/*
  * KNN multigraph with ties kept (Sec. 2.2, Algorithm 2: every candidate with
  * d <= d_k): the k nearest of every source plus every further (j, t) whose FP32
  * length equals the k-th one, in (length, dst, t) key order. The search keeps 64

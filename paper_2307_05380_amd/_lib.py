@@ -73,6 +73,8 @@ SIGNATURES = {
     "mg_edge_geometry": (_I32, [_P, _P, _P, _I32, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "mg_edge_geometry_backward": (_I32, [_P, _P, _P, _I32, _I64, _P, _P, _P, _I64, _P, _P, _P, _P,
                                          _P, _P, _SZ, _P]),
+    "mg_edge_geometry_backward_static": (_I32, [_P, _P, _P, _I32, _I64, _P, _P, _P, _I64, _P, _P, _P, _P,
+                                                _P, _P]),
     "mg_triplets_workspace_bytes": (_SZ, [_I64]),
     "mg_symmetrize_workspace_bytes": (_SZ, [_I64, _I64]),
     "mg_knn_ties_workspace_bytes": (_SZ, [_I32, _I64, _I32, _I64]),

@@ -701,6 +701,84 @@ mg_status mg_edge_geometry_backward(const float* lattices, const float* frac, co
     return MG_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free backward
+
+namespace {
+
+// Scratch of mg_edge_geometry_backward_static: the same workspace layout as
+// mg_edge_geometry_backward's, in a device array of the library (one copy per
+// GPU, kept until the process ends). Host code never passes the array's name
+// to a kernel: it is a host-side stand-in, not a device address. The device
+// address comes from hipGetSymbolAddress, once per device with that device
+// current, and only that pointer is used.
+constexpr size_t kStaticScratchBytes = MG_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (set-up on the first call on
+// each device). Returns nullptr and sets the error message on failure.
+void* static_scratch(mg_status* st) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *st = hip_fail(e, "hipGetDevice");
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *st = fail(MG_ERR_UNSUPPORTED, "device %d beyond the %d devices the static scratch supports", dev,
+                   kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            *st = hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_edge_geometry_backward_static(const float* lattices, const float* frac, const int64_t* batch_ptr,
+                                           int32_t B, int64_t N, const int32_t* src, const int32_t* dst,
+                                           const int32_t* image, int64_t E, const int64_t* num_edges,
+                                           const float* grad_vec, const float* grad_length, float* grad_frac,
+                                           float* grad_lattice, void* stream) {
+    g_err.clear();
+    mg_status st = check_common(lattices, frac, batch_ptr, B, N);
+    if (st != MG_OK) return st;
+    if ((st = check_edges(src, dst, image, E)) != MG_OK) return st;
+    const size_t need = carve_geom(nullptr, B, N).fixed;
+    if (need > kStaticScratchBytes)
+        return fail(MG_ERR_UNSUPPORTED,
+                    "B = %d structures and N = %lld atoms need %zu bytes of scratch; the static scratch holds %zu "
+                    "(use mg_edge_geometry_backward with a workspace)",
+                    B, (long long)N, need, kStaticScratchBytes);
+    void* ws = static_scratch(&st);
+    if (!ws) return st;
+    GeomWs w = carve_geom(ws, B, N);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = phase("geometry.bwd", s, [&] {
+             return mg::launch_geometry_bwd(lattices, frac, w.atom_struct, batch_ptr, B, N, src, dst, image, E,
+                                            num_edges, grad_vec, grad_length, grad_frac, grad_lattice, w.bwd, s);
+         })) != hipSuccess)
+        return hip_fail(e, "geometry backward");
+    return MG_OK;
+}
+
 mg_status mg_knn_graph_ties(const float* lattices, const float* frac, const int64_t* batch_ptr, int32_t B,
                             int64_t N, int32_t k, int64_t capacity, int32_t* src, int32_t* dst, int32_t* image,
                             float* length, int64_t* row_ptr, mg_report* report, void* workspace,
