@@ -190,7 +190,7 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.update_loop_only:
-        res = update_loop(dev, args.update_loop or 10, cpu_sample=not args.no_cpu_baseline)
+        res = update_loop(dev, args.update_loop or 10, cpu_sample=not args.no_cpu_baseline, tune_first=not args.no_tune)
         print(json.dumps({"update_loop": res, "source_digest": source_digest()}))
         return 0
     batch = inputs.make_config(args.config)
@@ -439,7 +439,7 @@ def main(argv=None):
     if args.batch_sweep:
         out["batch_sweep"] = batch_sweep(dev)
     if args.update_loop > 0:
-        out["update_loop"] = update_loop(dev, args.update_loop)
+        out["update_loop"] = update_loop(dev, args.update_loop, tune_first=not args.no_tune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 2)
@@ -447,7 +447,7 @@ def main(argv=None):
     return 0
 
 
-def update_loop(dev, steps: int, warmup: int = 2, cpu_sample: bool = False):
+def update_loop(dev, steps: int, warmup: int = 2, cpu_sample: bool = False, tune_first: bool = True):
     """64 supercells (8-atom base cells tiled 8..16 times per direction, ~10^6
     atoms): every step adds a Cartesian N(0, 0.02 A) move to every atom, then
     rebuilds the cutoff graph (5 A, edge vectors and lengths from its fill) and
@@ -464,6 +464,11 @@ def update_loop(dev, steps: int, warmup: int = 2, cpu_sample: bool = False):
     L = torch.from_numpy(b.lattices).to(dev)
     X = torch.from_numpy(b.frac).to(dev)
     P = torch.from_numpy(b.batch_ptr).to(dev)
+    tuning = None
+    if tune_first:   # launch shapes and the cell-list KNN threshold for this workload
+        from paper_2307_05380_amd import tune
+        best = tune.autotune(L, X, P, b.cutoff, b.k, use_cache=False)
+        tuning = {**best["cutoff"], **best["knn"]}
     n_steps = warmup + steps
     deltas = torch.from_numpy(np.stack([inputs.config5_step_delta(b, s) for s in range(n_steps)])).to(dev)
     g0 = graph.cutoff_graph(L, X, P, b.cutoff)
@@ -506,7 +511,7 @@ def update_loop(dev, steps: int, warmup: int = 2, cpu_sample: bool = False):
     out = {"supercells": b.B, "atoms": b.N, "steps": steps, "ms_per_step": round(ms, 4),
            "cutoff_edges_mean": int(E), "knn_edges": b.N * b.k, "cutoff": b.cutoff, "k": b.k,
            "edges_per_s": round((E + b.N * b.k) / (ms / 1e3), 1),
-           "structures_per_s": round(b.B / (ms / 1e3), 1)}
+           "structures_per_s": round(b.B / (ms / 1e3), 1), "tuning": tuning}
     if cpu_sample:
         out["cpu_oracle_extrapolated"] = update_loop_cpu(b)
     return out

@@ -112,7 +112,7 @@ size_t mg_knn_workspace_bytes(int32_t B, int64_t N, int32_t k, int64_t image_cap
 size_t mg_geometry_workspace_bytes(int32_t B, int64_t N);
 
 /* Workspace bytes with which mg_edge_geometry_backward on E edges takes its
- * faster path for structures of more than 512 (and at most 131072) atoms: the
+ * faster path for structures of more than 512 (and at most 65536) atoms: the
  * destination side of those structures is transposed through per-block buckets
  * (16 bytes per edge and a small counts table) instead of global atomics.
  * Any workspace of at least mg_geometry_workspace_bytes(B, N) stays valid;

@@ -539,9 +539,8 @@ __global__ __launch_bounds__(256) void k_image_flags(int B, const StructInfo* __
         const int t0 = r / w1 - n0;
         const double* L = si->L;
         const double R = (double)si->R;
-        const double cx = t0 * L[0] + t1 * L[3] + t2 * L[6];
-        const double cy = t0 * L[1] + t1 * L[4] + t2 * L[7];
-        const double cz = t0 * L[2] + t1 * L[5] + t2 * L[8];
+        double cx, cy, cz;
+        cart64(L, (double)t0, (double)t1, (double)t2, cx, cy, cz);
         const double c2 = cx * cx + cy * cy + cz * cz;
         bool keep;
         if ((t0 | t1 | t2) == 0 || c2 <= R * R) {

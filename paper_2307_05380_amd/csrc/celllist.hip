@@ -226,25 +226,12 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                 lr = length + base;
                 vr = vec ? vec + 3 * base : nullptr;
             }
-            for (int cb = 0; cb < T; cb += WAVE) {
-                const int c = cb + lane;
-                bool hit = false;
-                float dx = 0.f, dy = 0.f, dz = 0.f, l2 = 0.f;
-                int32_t j = 0, ct = 0;
-                if (c < T) {
-                    const float4 e = cl_candidate(tile, it, w, c, ct);
-                    j = __float_as_int(e.w);
-                    dx = e.x - S.px;
-                    dy = e.y - S.py;
-                    dz = e.z - S.pz;
-                    l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    hit = l2 < c2 && (int64_t)j != S.i;
-                }
-                const uint64_t m = ballot(hit);
+            const int self = it.home + (int)(r - it.hs);   // the source's own candidate (excluded)
+            auto emit = [&](uint64_t m, float dx, float dy, float dz, float l2, int32_t j, int32_t ct) {
                 if (MODE == 0) {
                     cnt += (uint32_t)__popcll(m);
                 } else {
-                    if (hit) {
+                    if ((m >> lane) & 1ull) {
                         const uint32_t e = run + mbcnt(m);
                         if (e < room) {
                             const uint32_t b4 = e << 2, b12 = (e << 3) + (e << 2);
@@ -263,6 +250,32 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                         }
                     }
                     run += (uint32_t)__popcll(m);
+                }
+            };
+            if (it.staged) {   // full-wave steps over the padded tile
+                for (int cb = 0; cb < T; cb += WAVE) {
+                    const float4 e = tile.c[cb + lane];
+                    const float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
+                    const float l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    const uint64_t m = ballot(l2 < c2) & ~cl_self_bit(self, cb);
+                    emit(m, dx, dy, dz, l2, __float_as_int(e.w), MODE == 1 ? tile.ct[cb + lane] : 0);
+                }
+            } else {
+                for (int cb = 0; cb < T; cb += WAVE) {
+                    const int c = cb + lane;
+                    float dx = 0.f, dy = 0.f, dz = 0.f, l2 = 0.f;
+                    int32_t j = 0, ct = 0;
+                    bool hit = false;
+                    if (c < T) {
+                        const float4 e = cl_candidate(tile, it, w, c, ct);
+                        j = __float_as_int(e.w);
+                        dx = e.x - S.px;
+                        dy = e.y - S.py;
+                        dz = e.z - S.pz;
+                        l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        hit = l2 < c2;
+                    }
+                    emit(ballot(hit) & ~cl_self_bit(self, cb), dx, dy, dz, l2, j, ct);
                 }
             }
             if (MODE == 0) {

@@ -36,8 +36,16 @@ struct ClItem {
     double o[3];       // fractional origin of the home bin
     int64_t hs, he;    // slot range of the home bin (its atoms are the item's sources)
     int32_t total;     // candidates in the stencil
+    int32_t home;      // candidate index of the home bin's first atom (stencil bin 13, wrap 0)
     bool staged;       // total <= CL_TILE: the candidates are in the tile
 };
+
+// A source's own candidate (distance 0) sits at candidate index home + (its slot
+// - hs); this is its bit in the wave step starting at candidate cb.
+__device__ __forceinline__ uint64_t cl_self_bit(int self, int cb) {
+    const int sl = self - cb;
+    return (sl >= 0 && sl < WAVE) ? (1ull << sl) : 0ull;
+}
 
 // Position relative to the home bin origin o (FP64, rounded once) of an atom
 // with raw coordinates x and packed floor sh, seen through the wrap u; ct gets
@@ -84,6 +92,7 @@ struct ClSource {
     int64_t i;       // atom index
     int32_t sh;      // packed floor(x_i)
     float px, py, pz;
+    float x0, x1, x2;   // raw coordinates
 };
 
 __device__ __forceinline__ ClSource cl_source(const ClItem& it, const ClWs& w, int64_t r) {
@@ -97,6 +106,9 @@ __device__ __forceinline__ ClSource cl_source(const ClItem& it, const ClWs& w, i
     int32_t ct;
     const float4 p = cl_rel(it.L, it.o, xu, s.sh, 0, 0, 0, ct);
     s.i = (int64_t)__float_as_int(xu.w);
+    s.x0 = xu.x;
+    s.x1 = xu.y;
+    s.x2 = xu.z;
     s.px = p.x;
     s.py = p.y;
     s.pz = p.z;
@@ -146,16 +158,25 @@ __device__ __forceinline__ void cl_stage(int64_t q, int B, const StructInfo* __r
     }
     __syncthreads();
     it.total = tile.nb_cum[27];
+    it.home = tile.nb_cum[13];
     it.staged = it.total <= CL_TILE;
     if (it.staged) {
-        for (int c = t; c < it.total; c += blockDim.x) {
-            const int d = cl_bin_of(tile, c);
-            const int64_t p = tile.nb_start[d] + (c - tile.nb_cum[d]);
-            const int32_t u = tile.nb_u[d];
-            int32_t ct;
-            tile.c[c] = cl_rel(it.L, it.o, w.slot_x[p], w.slot_shift[p], unpack_t0(u), unpack_t1(u), unpack_t2(u),
-                               ct);
-            tile.ct[c] = ct;
+        // the tile is filled up to a multiple of the wave width with entries no
+        // threshold accepts (infinite distance), so full-wave steps need no bounds test
+        const int padded = (it.total + WAVE - 1) / WAVE * WAVE;
+        for (int c = t; c < padded; c += blockDim.x) {
+            if (c < it.total) {
+                const int d = cl_bin_of(tile, c);
+                const int64_t p = tile.nb_start[d] + (c - tile.nb_cum[d]);
+                const int32_t u = tile.nb_u[d];
+                int32_t ct;
+                tile.c[c] = cl_rel(it.L, it.o, w.slot_x[p], w.slot_shift[p], unpack_t0(u), unpack_t1(u),
+                                   unpack_t2(u), ct);
+                tile.ct[c] = ct;
+            } else {
+                tile.c[c] = make_float4(1e30f, 1e30f, 1e30f, __int_as_float(-1));
+                tile.ct[c] = 0;
+            }
         }
     }
     __syncthreads();

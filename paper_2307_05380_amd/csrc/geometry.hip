@@ -6,9 +6,11 @@
 // forward pass (abstract; Sec. 4):
 //   g_e = g_v + g_l v / l (0 when l = 0),
 //   grad_x[dst] += g L^T, grad_x[src] -= g L^T, grad_L[s] += f^T g.
-// Both kernels are bound by HBM traffic on the per-edge arrays; the per-edge
-// arithmetic is done in FP64 (full rate on CDNA) so that thin cells with large
-// image offsets lose no accuracy, and results are stored in FP32.
+// The kernels are bound by HBM traffic on the per-edge arrays. The forward
+// pass, whose lengths are held to 2e-5 A, does its per-edge arithmetic in FP64
+// (full rate on CDNA) so that thin cells with large image offsets lose no
+// accuracy; the backward passes, held to 1e-4 relative, work in FP32 per edge
+// with FP64 sums where many edges add up. Results are stored in FP32.
 #include "mg_internal.h"
 
 namespace mg {
@@ -321,7 +323,8 @@ __device__ __forceinline__ bool bwd_item(int64_t item, int B, const int64_t* __r
 // sources. The length term is evaluated with the metric tensor G = L L^T of
 // the structure: |v|^2 = f G f^T, g L^T = c G f^T and f^T g = c f^T f L, so
 // no per-edge v is formed and the lattice gradient of the length term is the
-// FP64 register sum M = sum c f^T f, multiplied by L once per item. The four
+// register sum M = sum c f^T f (FP32 per lane, FP64 over lanes and waves),
+// multiplied by L once per item. The four
 // copies are summed at the end and written with plain stores when the item is
 // the whole structure. Each wave walks a contiguous quarter of the item, four
 // groups of 64 edges per step with all their loads issued first. A dst outside
@@ -329,7 +332,7 @@ __device__ __forceinline__ bool bwd_item(int64_t item, int B, const int64_t* __r
 // sources, a src smaller than the previous lane's) sets bit 0 (the results are
 // then cleared and recomputed by the general kernel).
 template <bool GV, bool GL, int WIN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GV ? 5 : 8)))
 void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict__ frac,
                     const int64_t* __restrict__ batch_ptr, int B, const int32_t* __restrict__ src,
                     const int32_t* __restrict__ dst, const int32_t* __restrict__ image,
@@ -358,18 +361,16 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
     float Lf[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) Lf[q] = Lp[q];
-    // metric tensor G = L L^T (rows of L are the lattice vectors), wave-uniform
-    double Gm[6];
+    // metric tensor G = L L^T (rows of L are the lattice vectors), from FP64
+    // rounded once, wave-uniform
+    float Gm[6];
     {
         const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const double g = (double)Lf[3 * ia[q]] * Lf[3 * ib[q]] + (double)Lf[3 * ia[q] + 1] * Lf[3 * ib[q] + 1] +
                              (double)Lf[3 * ia[q] + 2] * Lf[3 * ib[q] + 2];
-            const int64_t bits = __double_as_longlong(g);
-            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)bits);
-            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)bits >> 32));
-            Gm[q] = __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+            Gm[q] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)g)));
         }
     }
     const int32_t a0 = (int32_t)it.atom0;
@@ -385,12 +386,14 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
     int src_cur = -1;   // wave's current source run (local index), -1: none
     float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f;
     // lattice gradient: sum f (x) g_v (upstream vector gradient) and the
-    // symmetric M = sum c f f^T of the length term (its part is M L)
-    double lv[9], M[6];
+    // symmetric M = sum c f f^T of the length term (its part is M L); each lane
+    // sums its own edges (at most a 64th of the item) in FP32, the lanes and
+    // waves are summed in FP64
+    float lv[9], M[6];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) lv[q] = 0.0;
+    for (int q = 0; q < 9; ++q) lv[q] = 0.0f;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) M[q] = 0.0;
+    for (int q = 0; q < 6; ++q) M[q] = 0.0f;
     bool bad = false, unsorted = false;
     auto add_src_run = [&]() {   // lane 0 adds the wave's source run
         if (src_cur >= 0) {
@@ -442,25 +445,26 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
             unsorted |= inr && !oki;                     // src outside the item's structure
             const bool act = inr && okj && oki;
             const int li = oki ? ai[u] : 0, lj = okj ? aj[u] : 0;
-            const double f0 = (double)xs[3 * lj] - (double)xs[3 * li] + (double)at[u][0];
-            const double f1 = (double)xs[3 * lj + 1] - (double)xs[3 * li + 1] + (double)at[u][1];
-            const double f2 = (double)xs[3 * lj + 2] - (double)xs[3 * li + 2] + (double)at[u][2];
+            // FP32 per edge: the gradient is held to 1e-4 relative, and every
+            // quantity here is a few roundings away from its FP64 value
+            const float f0 = (xs[3 * lj] - xs[3 * li]) + (float)at[u][0];
+            const float f1 = (xs[3 * lj + 1] - xs[3 * li + 1]) + (float)at[u][1];
+            const float f2 = (xs[3 * lj + 2] - xs[3 * li + 2]) + (float)at[u][2];
             float x0 = 0.f, x1 = 0.f, x2 = 0.f;
             if (GL) {
                 // v = f L, |v|^2 = f G f^T and g = c v with c = g_l / |v|; then
                 // g L^T = c (G f) and f (x) g = c f f^T L: no per-edge v
-                const double h0 = Gm[0] * f0 + Gm[1] * f1 + Gm[2] * f2;
-                const double h1 = Gm[1] * f0 + Gm[3] * f1 + Gm[4] * f2;
-                const double h2 = Gm[2] * f0 + Gm[4] * f1 + Gm[5] * f2;
-                const float l2 = (float)(f0 * h0 + f1 * h1 + f2 * h2);
+                const float h0 = Gm[0] * f0 + Gm[1] * f1 + Gm[2] * f2;
+                const float h1 = Gm[1] * f0 + Gm[3] * f1 + Gm[4] * f2;
+                const float h2 = Gm[2] * f0 + Gm[4] * f1 + Gm[5] * f2;
+                const float l2 = f0 * h0 + f1 * h1 + f2 * h2;
                 float c = l2 > 0.0f ? al[u] * __frsqrt_rn(l2) : 0.0f;
                 c = act ? c : 0.0f;
-                x0 = c * (float)h0;
-                x1 = c * (float)h1;
-                x2 = c * (float)h2;
+                x0 = c * h0;
+                x1 = c * h1;
+                x2 = c * h2;
                 if (acc) {
-                    const double cd = c;
-                    const double c0 = cd * f0, c1 = cd * f1, c2 = cd * f2;
+                    const float c0 = c * f0, c1 = c * f1, c2 = c * f2;
                     M[0] += c0 * f0; M[1] += c0 * f1; M[2] += c0 * f2;
                     M[3] += c1 * f1; M[4] += c1 * f2; M[5] += c2 * f2;
                 }
@@ -472,10 +476,9 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
                 x1 += g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
                 x2 += g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
                 if (acc) {
-                    const double d0 = g0, d1 = g1, d2 = g2;
-                    lv[0] += f0 * d0; lv[1] += f0 * d1; lv[2] += f0 * d2;
-                    lv[3] += f1 * d0; lv[4] += f1 * d1; lv[5] += f1 * d2;
-                    lv[6] += f2 * d0; lv[7] += f2 * d1; lv[8] += f2 * d2;
+                    lv[0] += f0 * g0; lv[1] += f0 * g1; lv[2] += f0 * g2;
+                    lv[3] += f1 * g0; lv[4] += f1 * g1; lv[5] += f1 * g2;
+                    lv[6] += f2 * g0; lv[7] += f2 * g1; lv[8] += f2 * g2;
                 }
             }
             if (gf) {
@@ -531,7 +534,7 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
     // block sums of lv and M (also orders the LDS updates before the reads below)
 #pragma unroll
     for (int q = 0; q < 15; ++q) {
-        const double t = wave_sum_f64(q < 9 ? lv[q] : M[q - 9]);
+        const double t = wave_sum_f64((double)(q < 9 ? lv[q] : M[q - 9]));
         if (lane == 0) red[wv][q] = t;
     }
     __syncthreads();
@@ -644,17 +647,14 @@ __global__ __launch_bounds__(256) void k_bk_scatter(const float* __restrict__ la
     float Lf[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) Lf[q] = Lp[q];
-    double Gm[6];   // metric tensor G = L L^T, wave-uniform
+    float Gm[6];   // metric tensor G = L L^T from FP64, rounded once, wave-uniform
     {
         const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const double g = (double)Lf[3 * ia[q]] * Lf[3 * ib[q]] + (double)Lf[3 * ia[q] + 1] * Lf[3 * ib[q] + 1] +
                              (double)Lf[3 * ia[q] + 2] * Lf[3 * ib[q] + 2];
-            const int64_t bits = __double_as_longlong(g);
-            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)bits);
-            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)bits >> 32));
-            Gm[q] = __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+            Gm[q] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)g)));
         }
     }
     const int32_t a0 = (int32_t)it.atom0;
@@ -671,11 +671,11 @@ __global__ __launch_bounds__(256) void k_bk_scatter(const float* __restrict__ la
     const float* glb = GL ? glen + it.c0 : nullptr;
     int src_cur = -1;
     float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f;
-    double lv[9], M[6];
+    float lv[9], M[6];   // per-lane FP32 sums of this item's edges (FP64 over lanes and waves)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) lv[q] = 0.0;
+    for (int q = 0; q < 9; ++q) lv[q] = 0.0f;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) M[q] = 0.0;
+    for (int q = 0; q < 6; ++q) M[q] = 0.0f;
     bool bad = false, unsorted = false;
     auto add_src_run = [&]() {   // lane 0 adds the wave's source run
         if (src_cur >= 0) {
@@ -723,23 +723,22 @@ __global__ __launch_bounds__(256) void k_bk_scatter(const float* __restrict__ la
             unsorted |= inr && !oki;
             const bool act = inr && okj && oki;
             const int li = oki ? ai[u] : 0, lj = okj ? aj[u] : 0;
-            const double f0 = (double)xb[3 * lj] - (double)xb[3 * li] + (double)at[u][0];
-            const double f1 = (double)xb[3 * lj + 1] - (double)xb[3 * li + 1] + (double)at[u][1];
-            const double f2 = (double)xb[3 * lj + 2] - (double)xb[3 * li + 2] + (double)at[u][2];
+            const float f0 = (xb[3 * lj] - xb[3 * li]) + (float)at[u][0];
+            const float f1 = (xb[3 * lj + 1] - xb[3 * li + 1]) + (float)at[u][1];
+            const float f2 = (xb[3 * lj + 2] - xb[3 * li + 2]) + (float)at[u][2];
             float x0 = 0.f, x1 = 0.f, x2 = 0.f;
             if (GL) {   // g = c v, c = g_l / |v|: g L^T = c (G f), f (x) g = c f f^T L
-                const double h0 = Gm[0] * f0 + Gm[1] * f1 + Gm[2] * f2;
-                const double h1 = Gm[1] * f0 + Gm[3] * f1 + Gm[4] * f2;
-                const double h2 = Gm[2] * f0 + Gm[4] * f1 + Gm[5] * f2;
-                const float l2 = (float)(f0 * h0 + f1 * h1 + f2 * h2);
+                const float h0 = Gm[0] * f0 + Gm[1] * f1 + Gm[2] * f2;
+                const float h1 = Gm[1] * f0 + Gm[3] * f1 + Gm[4] * f2;
+                const float h2 = Gm[2] * f0 + Gm[4] * f1 + Gm[5] * f2;
+                const float l2 = f0 * h0 + f1 * h1 + f2 * h2;
                 float c = l2 > 0.0f ? al[u] * __frsqrt_rn(l2) : 0.0f;
                 c = act ? c : 0.0f;
-                x0 = c * (float)h0;
-                x1 = c * (float)h1;
-                x2 = c * (float)h2;
+                x0 = c * h0;
+                x1 = c * h1;
+                x2 = c * h2;
                 if (acc) {
-                    const double cd = c;
-                    const double c0 = cd * f0, c1 = cd * f1, c2 = cd * f2;
+                    const float c0 = c * f0, c1 = c * f1, c2 = c * f2;
                     M[0] += c0 * f0; M[1] += c0 * f1; M[2] += c0 * f2;
                     M[3] += c1 * f1; M[4] += c1 * f2; M[5] += c2 * f2;
                 }
@@ -750,17 +749,18 @@ __global__ __launch_bounds__(256) void k_bk_scatter(const float* __restrict__ la
                 x1 += g0 * Lf[3] + g1 * Lf[4] + g2 * Lf[5];
                 x2 += g0 * Lf[6] + g1 * Lf[7] + g2 * Lf[8];
                 if (acc) {
-                    const double d0 = g0, d1 = g1, d2 = g2;
-                    lv[0] += f0 * d0; lv[1] += f0 * d1; lv[2] += f0 * d2;
-                    lv[3] += f1 * d0; lv[4] += f1 * d1; lv[5] += f1 * d2;
-                    lv[6] += f2 * d0; lv[7] += f2 * d1; lv[8] += f2 * d2;
+                    lv[0] += f0 * g0; lv[1] += f0 * g1; lv[2] += f0 * g2;
+                    lv[3] += f1 * g0; lv[4] += f1 * g1; lv[5] += f1 * g2;
+                    lv[6] += f2 * g0; lv[7] += f2 * g1; lv[8] += f2 * g2;
                 }
             }
             if (grad_frac) {
-                if (act) {   // destination side: a record in the destination block's bucket
-                    const int d = lj / BK_BLOCK;
-                    const int64_t pos = base[d] + (int64_t)atomicAdd(&cur[d], 1u);
-                    rec[pos] = make_float4(x0, x1, x2, __int_as_float(lj - d * BK_BLOCK));
+                // destination side: a record in the destination block's bucket at the
+                // block's LDS cursor (integer LDS atomics are cheap; float ones are not)
+                if (act) {
+                    const int db = lj / BK_BLOCK;
+                    const int64_t pos = base[db] + (int64_t)atomicAdd(&cur[db], 1u);
+                    rec[pos] = make_float4(x0, x1, x2, __int_as_float(lj - db * BK_BLOCK));
                 }
                 // source side: runs of one source summed in the wave
                 const int iu = __builtin_amdgcn_readfirstlane(li);
@@ -795,7 +795,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(const float* __restrict__ la
     if (acc) {
 #pragma unroll
         for (int q = 0; q < 15; ++q) {
-            const double t = wave_sum_f64(q < 9 ? lv[q] : M[q - 9]);
+            const double t = wave_sum_f64((double)(q < 9 ? lv[q] : M[q - 9]));
             if (lane == 0) red[wv][q] = t;
         }
         __syncthreads();
@@ -815,38 +815,59 @@ __global__ __launch_bounds__(256) void k_bk_scatter(const float* __restrict__ la
 }
 
 // Gather: one workgroup per destination block of a bucketed structure sums
-// its bucket's records in LDS and adds them to the block's rows of grad_frac
-// (which then hold only the source-side sums of the scatter pass).
-__global__ __launch_bounds__(512) void k_bk_gather(const int64_t* __restrict__ batch_ptr, int B,
+// its bucket's records and adds them to the block's rows of grad_frac (which
+// then hold only the source-side sums of the scatter pass). Each wave takes a
+// quarter of the bucket into its own LDS copy of the block, with plain
+// read-modify-writes in owner rounds (a lane whose atom another lane of the
+// same step also targets waits for a later round; LDS float atomics measured
+// several times slower); the four copies are summed at the end.
+__global__ __launch_bounds__(256) void k_bk_gather(const int64_t* __restrict__ batch_ptr, int B,
                                                    const int64_t* __restrict__ item_off,
                                                    const int64_t* __restrict__ cm_off,
                                                    const int64_t* __restrict__ p3_off,
                                                    const int64_t* __restrict__ boff, const int32_t* __restrict__ flag,
                                                    const float4* __restrict__ rec, float* __restrict__ grad_frac) {
-    __shared__ float accl[BK_BLOCK * 3];
+    __shared__ float accl[4][BK_BLOCK * 3];
+    __shared__ int tag[4][BK_BLOCK];
     if (flag[3] == 0 || flag[0] != 0) return;
     const int64_t q = blockIdx.x;
     if (q >= p3_off[B]) return;
-    const int tid = threadIdx.x;
-    const int st = __builtin_amdgcn_readfirstlane(wave_search_le(p3_off, B, q, lane_id()));
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int st = __builtin_amdgcn_readfirstlane(wave_search_le(p3_off, B, q, lane));
     const int d = (int)(q - p3_off[st]);
     const int64_t chunks = item_off[st + 1] - item_off[st];
     const int64_t cmb = cm_off[st];
     const int64_t r0 = boff[cmb + (int64_t)d * chunks], r1 = boff[cmb + (int64_t)(d + 1) * chunks];
-    for (int x = tid; x < 3 * BK_BLOCK; x += 512) accl[x] = 0.0f;
+    for (int x = tid; x < 4 * 3 * BK_BLOCK; x += 256) (&accl[0][0])[x] = 0.0f;
     __syncthreads();
+    float* my = accl[wv];
+    int* mytag = tag[wv];
+    const int64_t qlen = ((r1 - r0 + 3) / 4 + WAVE - 1) / WAVE * WAVE;
+    const int64_t w0 = r0 + wv * qlen, w1 = min(r1, w0 + qlen);
     constexpr int U = 4;
-    for (int64_t r = r0 + tid; r < r1; r += U * 512) {
+    for (int64_t rb = w0; rb < w1; rb += U * WAVE) {
         float4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = r + u * 512 < r1 ? rec[r + u * 512] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int u = 0; u < U; ++u) {
+            const int64_t r = rb + u * WAVE + lane;
+            v[u] = r < w1 ? rec[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (r + u * 512 < r1) {
-                const int li = __float_as_int(v[u].w);
-                atomicAdd(&accl[3 * li], v[u].x);
-                atomicAdd(&accl[3 * li + 1], v[u].y);
-                atomicAdd(&accl[3 * li + 2], v[u].z);
+            if (rb + u * WAVE >= w1) break;   // uniform
+            bool pend = rb + u * WAVE + lane < w1;
+            const int li = pend ? __float_as_int(v[u].w) : 0;
+            for (int round = 0; round < WAVE && ballot(pend) != 0; ++round) {
+                if (pend) mytag[li] = lane;
+                wave_lds_sync();
+                const bool own = pend && mytag[li] == lane;
+                if (own) {
+                    my[3 * li] += v[u].x;
+                    my[3 * li + 1] += v[u].y;
+                    my[3 * li + 2] += v[u].z;
+                }
+                wave_lds_sync();
+                pend = pend && !own;
             }
         }
     }
@@ -854,7 +875,7 @@ __global__ __launch_bounds__(512) void k_bk_gather(const int64_t* __restrict__ b
     const int64_t a0 = batch_ptr[st] + (int64_t)d * BK_BLOCK;
     const int cnt = (int)min((int64_t)BK_BLOCK, batch_ptr[st + 1] - a0);
     float* out = grad_frac + 3 * a0;
-    for (int x = tid; x < 3 * cnt; x += 512) out[x] += accl[x];
+    for (int x = tid; x < 3 * cnt; x += 256) out[x] += (accl[0][x] + accl[1][x]) + (accl[2][x] + accl[3][x]);
 }
 
 // After the grouped kernels: if the edges turned out not to be grouped (flag
@@ -1124,7 +1145,7 @@ hipError_t launch_geometry_bwd(const float* lattices, const float* frac, int32_t
             else MG_BK(false, true);
 #undef MG_BK
             const int64_t p3_grid = (N + BK_BLOCK - 1) / BK_BLOCK + B;   // >= the blocks of all structures
-            hipLaunchKernelGGL(k_bk_gather, dim3((unsigned)p3_grid), dim3(512), 0, s, batch_ptr, B, w.item_off,
+            hipLaunchKernelGGL(k_bk_gather, dim3((unsigned)p3_grid), dim3(256), 0, s, batch_ptr, B, w.item_off,
                                w.cm_off, w.p3_off, w.boff, w.flag, w.rec, grad_frac);
         }
         const int64_t n3 = grad_frac ? 3 * N : 0, n9 = acc ? 9 * (int64_t)B : 0;

@@ -204,10 +204,9 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
             d0 -= rint(d0);
             d1 -= rint(d1);
             d2 -= rint(d2);
-            P[jj] = make_float4((float)(d0 * L[0] + d1 * L[3] + d2 * L[6]),
-                                (float)(d0 * L[1] + d1 * L[4] + d2 * L[7]),
-                                (float)(d0 * L[2] + d1 * L[5] + d2 * L[8]),
-                                __int_as_float(jc0 + jj == il ? 1 : 0));
+            double px, py, pz;
+            cart64(L, d0, d1, d2, px, py, pz);
+            P[jj] = make_float4((float)px, (float)py, (float)pz, __int_as_float(jc0 + jj == il ? 1 : 0));
         }
         wave_lds_sync();
         const uint32_t nq = (uint32_t)nj * I;
@@ -258,9 +257,11 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
                 } else {
                     int t0, t1, t2;
                     image_t(S, img, t0, t1, t2);
-                    sx = (float)(t0 * L[0] + t1 * L[3] + t2 * L[6]);
-                    sy = (float)(t0 * L[1] + t1 * L[4] + t2 * L[7]);
-                    sz = (float)(t0 * L[2] + t1 * L[5] + t2 * L[8]);
+                    double cx, cy, cz;
+                    cart64(L, (double)t0, (double)t1, (double)t2, cx, cy, cz);
+                    sx = (float)cx;
+                    sy = (float)cy;
+                    sz = (float)cz;
                 }
                 const float dx = pp.x + sx, dy = pp.y + sy, dz = pp.z + sz;
                 l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
@@ -370,16 +371,20 @@ __global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInf
 // Cell-list pass: one workgroup per home bin of a cell-list structure, the 27
 // stencil bins staged in LDS (cl_tile.h), one wave per source of the home
 // bin. Key ordinal: local dst * 32768 + (t0+16, t1+16, t2+16) in 5 bits each,
-// which is the (dst, t) order. The stencil covers every candidate within wcl,
-// so a stack that holds >= k keys under a threshold at most wcl^2 is exact.
-// The first sweep uses a tighter threshold, tau_scale times the k-th
-// neighbour distance of a uniform density (fewer keys to sort); a source with
-// fewer than k keys under it is swept again at wcl^2, and one with fewer than
-// k under wcl^2 (or an image component outside [-16, 15]) goes to the
-// extended pass.
+// which is the (dst, t) order. The staged positions only pre-filter: a
+// candidate near or under the threshold gets its key distance from the raw
+// coordinates in the form every KNN path shares (knn_l2), so the graph does
+// not depend on the bins or on which pass resolved a source. The stencil
+// covers every candidate within wcl, so a stack that holds >= k keys under a
+// threshold at most wcl^2 is exact. The first sweep uses a tighter threshold,
+// tau_scale times the k-th neighbour distance of a uniform density (fewer keys
+// to sort); a source with fewer than k keys under it is swept again at wcl^2,
+// and one with fewer than k under wcl^2 (or an image component outside
+// [-16, 15]) goes to the extended pass.
 constexpr int KNN_CL_CAP = 128;
 
 __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* __restrict__ info, ClWs w,
+                                                const float* __restrict__ frac,
                                                 int32_t* __restrict__ src, int32_t* __restrict__ dst,
                                                 int32_t* __restrict__ image, float* __restrict__ length,
                                                 int32_t* __restrict__ ext_list, Counters* __restrict__ ctr,
@@ -413,6 +418,7 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
         for (int64_t r = it.hs + wv; r < it.he; r += 4) {
             const ClSource S = cl_source(it, w, r);
             const int s0 = unpack_t0(S.sh), s1 = unpack_t1(S.sh), s2 = unpack_t2(S.sh);
+            const int self = it.home + (int)(r - it.hs);   // the source's own candidate (excluded)
             float tau = first;
             bool done = false;
             int overflow = n >= 131072 ? 1 : 0;   // local dst index must fit 17 bits
@@ -423,20 +429,25 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                     bool pass = false;
                     float l2 = 0.0f;
                     uint32_t ord = 0;
-                    if (c < T) {
-                        int32_t ct;
-                        const float4 e = cl_candidate(tile, it, w, c, ct);
+                    if (it.staged || c < T) {   // the staged tile is padded to whole waves
+                        int32_t ct = 0;
+                        const float4 e = it.staged ? tile.c[c] : cl_candidate(tile, it, w, c, ct);
                         const int32_t j = __float_as_int(e.w);
                         const float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
                         l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        pass = l2 < st.tau2 && (int64_t)j != S.i;
+                        // pre-filter with a margin far above the two forms' difference
+                        pass = l2 < st.tau2 * (1.0f + 1e-4f) && c != self;
                         if (pass) {
+                            if (it.staged) ct = tile.ct[c];
                             const int t0 = unpack_t0(ct) + s0, t1 = unpack_t1(ct) + s1, t2 = unpack_t2(ct) + s2;
                             const bool fits = t0 >= -16 && t0 <= 15 && t1 >= -16 && t1 <= 15 && t2 >= -16 && t2 <= 15;
                             overflow |= fits ? 0 : 1;
                             ord = (uint32_t)(j - atom0) * 32768u +
                                   (uint32_t)(((t0 + 16) * 32 + (t1 + 16)) * 32 + (t2 + 16));
-                            pass = fits;
+                            const int64_t ja = j;
+                            l2 = knn_l2(it.L, (double)S.x0, (double)S.x1, (double)S.x2, (double)frac[3 * ja],
+                                        (double)frac[3 * ja + 1], (double)frac[3 * ja + 2], t0, t1, t2);
+                            pass = fits && l2 < st.tau2;
                         }
                     }
                     stack_push<KNN_CL_CAP>(st, pass, l2, ord, k, buf, lane);
@@ -562,9 +573,8 @@ hipError_t launch_cl_knn(int B, int k, const StructInfo* info, const ClWs& w, co
                          int32_t* src, int32_t* dst, int32_t* image, float* length,
                          int32_t* ext_list, Counters* ctr, mg_report* report, int64_t* partials,
                          int grid, float tau_scale, hipStream_t s) {
-    (void)frac;
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_knn_cl, dim3(grid), dim3(256), 0, s, B, k, info, w, src, dst, image, length,
+    hipLaunchKernelGGL(k_knn_cl, dim3(grid), dim3(256), 0, s, B, k, info, w, frac, src, dst, image, length,
                        ext_list, ctr, report, partials, tau_scale);
     return hipGetLastError();
 }

@@ -177,6 +177,36 @@ __device__ __forceinline__ float sqrt_rn_finite(float x) {
     return fmaf(-rp, r, x) > 0.0f ? rp : lo;             // x above the r..rp midpoint squared
 }
 
+// Cartesian vector f L of a fractional vector f (FP64; rows of L are the
+// lattice vectors). Every FP32 distance of the image sweeps and the KNN keys
+// is built from two such products, each rounded once to FP32: the pair offset
+// (x_j - x_i - w) L, w = rint(x_j - x_i), and the image shift t L. All paths
+// call this one function (the image tables, the sweeps, the KNN passes), so a
+// candidate gets bit for bit the same distance whichever path evaluates it.
+__device__ __forceinline__ void cart64(const double* L, double f0, double f1, double f2, double& x, double& y,
+                                       double& z) {
+    x = f0 * L[0] + f1 * L[3] + f2 * L[6];
+    y = f0 * L[1] + f1 * L[4] + f2 * L[7];
+    z = f0 * L[2] + f1 * L[5] + f2 * L[8];
+}
+
+// Squared KNN key distance of candidate (j, t) of source i (x_i, x_j raw
+// fractional coordinates, t the edge's image): pair offset plus image shift
+// as above, summed in FP32.
+__device__ __forceinline__ float knn_l2(const double* L, double xi0, double xi1, double xi2, double xj0, double xj1,
+                                        double xj2, int t0, int t1, int t2) {
+    double d0 = xj0 - xi0, d1 = xj1 - xi1, d2 = xj2 - xi2;
+    const double w0 = rint(d0), w1 = rint(d1), w2 = rint(d2);
+    d0 -= w0;
+    d1 -= w1;
+    d2 -= w2;
+    double px, py, pz, sx, sy, sz;
+    cart64(L, d0, d1, d2, px, py, pz);
+    cart64(L, (double)(t0 + (int)w0), (double)(t1 + (int)w1), (double)(t2 + (int)w2), sx, sy, sz);
+    const float dx = (float)px + (float)sx, dy = (float)py + (float)sy, dz = (float)pz + (float)sz;
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
 // Orders this wave's LDS writes before its later LDS reads (lanes exchange data
 // through LDS without a workgroup barrier).
 __device__ inline void wave_lds_sync() {
@@ -339,7 +369,7 @@ struct GeomBwdWs {
 // and the largest structure it takes (more blocks than the per-chunk LDS
 // histogram holds go to the atomic kernel).
 constexpr int BW_CHUNK = 16384;   // edges per backward item
-constexpr int BK_BLOCK = 1024;
+constexpr int BK_BLOCK = 512;
 constexpr int BK_MAX_BLOCKS = 128;
 // Counts-matrix capacity for a batch of B structures and E edges.
 inline int64_t bk_count_capacity(int B, int64_t E) { return ((int64_t)B + E / BW_CHUNK + 1) * BK_MAX_BLOCKS; }

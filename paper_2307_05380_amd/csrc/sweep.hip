@@ -49,9 +49,11 @@ __device__ inline Pair make_pair(const float* __restrict__ frac, const double* L
     d0 -= w0;
     d1 -= w1;
     d2 -= w2;
-    P.px = (float)(d0 * L[0] + d1 * L[3] + d2 * L[6]);
-    P.py = (float)(d0 * L[1] + d1 * L[4] + d2 * L[7]);
-    P.pz = (float)(d0 * L[2] + d1 * L[5] + d2 * L[8]);
+    double px, py, pz;
+    cart64(L, d0, d1, d2, px, py, pz);
+    P.px = (float)px;
+    P.py = (float)py;
+    P.pz = (float)pz;
     P.w0 = (int)w0 + TBIAS;
     P.w1 = (int)w1 + TBIAS;
     P.w2 = (int)w2 + TBIAS;
@@ -107,24 +109,29 @@ struct OutRel {
     float* length;
     float* vec;     // nullable
     uint32_t cap;   // capacity - base (clamped to 32 bits): relative edges >= cap are not written
+    bool fits;      // every edge of the item lies below capacity (no per-edge test)
 };
 
-__device__ __forceinline__ OutRel rebase(int64_t base, int64_t capacity, int32_t* src, int32_t* dst, int32_t* image,
-                                         float* length, float* vec) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)base >> 32));
-    const int64_t b = (int64_t)(((uint64_t)hi << 32) | lo);
+// item_end: the end of the rows the item writes into (row_ptr past its last source).
+__device__ __forceinline__ OutRel rebase(int64_t base, int64_t item_end, int64_t capacity, int32_t* src,
+                                         int32_t* dst, int32_t* image, float* length, float* vec) {
+    const int64_t b = uniform64(base);
     const int64_t room = capacity - b;
     const uint32_t cap = room <= 0 ? 0u : (room >= (int64_t)UINT32_MAX ? UINT32_MAX : (uint32_t)room);
-    return OutRel{src + b, dst + b, image + 3 * b, length + b, vec ? vec + 3 * b : nullptr, cap};
+    const bool fits = __builtin_amdgcn_readfirstlane(uniform64(item_end) <= capacity ? 1 : 0) != 0;
+    return OutRel{src + b, dst + b, image + 3 * b, length + b, vec ? vec + 3 * b : nullptr, cap, fits};
 }
 
 __device__ __forceinline__ void write_edge(uint32_t e, const OutRel& o, int32_t src_atom, int32_t dst_atom,
                                            const Pair& P, const ImageEntry& t, float l2) {
     const int32_t tpk = t.tpk;
-    if (e >= o.cap) return;
-    // 32-bit byte offsets from the scalar bases (an item's edges are far fewer than 2^28)
-    const uint32_t b4 = e << 2, b12 = (e << 3) + (e << 2);
+    if (!o.fits && e >= o.cap) return;   // (o.fits is wave-uniform: a scalar branch in the common case)
+    // 32-bit byte offsets from the scalar bases (an item's edges are far fewer than
+    // 2^28); 12 e as two shifts and an add, not a quarter-rate multiply
+    const uint32_t b4 = e << 2;
+    uint32_t b8 = e << 3;
+    asm volatile("" : "+v"(b8));
+    const uint32_t b12 = b8 + b4;
     (void)src_atom;   // src is written densely from row_ptr after the fill (k_src_from_rows)
     *(int32_t*)((char*)o.dst + b4) = dst_atom;
     int32_t* im = (int32_t*)((char*)o.image + b12);
@@ -234,7 +241,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             OutRel out{};
             if (MODE == MODE_FILL) {
                 const int64_t ibase = cstart(i_first);
-                out = rebase(ibase, capacity, src, dst, image, length, vec);
+                out = rebase(ibase, offsets[atom0 + i_first + nsrc], capacity, src, dst, image, length, vec);
                 base = act ? (uint32_t)(cstart(il) - ibase) : 0u;
                 seg = (n == WAVE) ? ~0ull : (((1ull << n) - 1ull) << (a * n));
             }
@@ -268,7 +275,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             uint32_t cnt = 0;   // wave-uniform in this path
             uint32_t run = 0;
             OutRel out{};
-            if (MODE == MODE_FILL) out = rebase(cstart(il), capacity, src, dst, image, length, vec);
+            if (MODE == MODE_FILL)
+                out = rebase(cstart(il), offsets[atom0 + il + 1], capacity, src, dst, image, length, vec);
             const int32_t sa = (int32_t)(atom0 + il);
             {
                 const int ck = ck_beg;
