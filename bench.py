@@ -78,33 +78,62 @@ def _parse(argv=None):
     return ap.parse_args(argv)
 
 
-def source_digest() -> str:
-    """Digest of the HIP sources: hardware counters recorded for an older build
-    no longer describe the kernels."""
+# The source files whose kernels make up each measured phase: hardware counters
+# recorded for other versions of these files no longer describe the kernels.
+PHASE_SOURCES = {
+    "cutoff.count": ("sweep.hip", "mg_internal.h"),
+    "cutoff.fill": ("sweep.hip", "mg_internal.h"),
+    "cutoff.src": ("sweep.hip", "mg_internal.h"),
+    "knn.select": ("knn.hip", "cl_tile.h", "mg_internal.h"),
+    "geometry.bwd": ("geometry.hip", "mg_internal.h"),
+}
+
+
+def source_digest(files=None) -> str:
+    """Digest of the HIP sources (all of them, or the given file names)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2307_05380_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(files if files is not None else os.listdir(csrc)):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(phase: str):
-    """HBM bytes per launch of a phase's kernels from the committed hardware-counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
-    device copy of known size), or None when the summary is missing or was taken
-    on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_4096_structures.json")
+def _counter_summary(name: str, phase: str):
+    """A phase's entry of a committed hardware-counter summary, or None when the
+    summary is missing or was taken on other versions of the phase's sources."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_digest") != source_digest():
-        return None
     v = t.get("phases", {}).get(phase)
+    if v is None or v.get("sources_digest") != source_digest(PHASE_SOURCES.get(phase, ())):
+        return None
+    return v
+
+
+def measured_traffic(phase: str):
+    """HBM bytes per launch of a phase's kernels from the committed hardware-counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    device copy of known size)."""
+    v = _counter_summary("hbm_traffic_4096_structures.json", phase)
     return None if v is None else v.get("bytes_per_launch")
+
+
+def measured_valu(phase: str, ms: float):
+    """FP32 VALU rate of a phase from the committed counter summary: the
+    SQ_INSTS_VALU_FLOPS_FP32 count of its kernels (x 64 lanes) over this run's
+    phase time, with the VALU issue fraction the counters gave on their run."""
+    v = _counter_summary("valu_4096_structures.json", phase)
+    if v is None or ms <= 0:
+        return None
+    tf = v["fp32_flops"] / (ms * 1e-3) / 1e12
+    return {"achieved": round(tf, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4), "valu_issue_frac": v.get("valu_issue_frac"),
+            "source": "SQ_INSTS_VALU_FLOPS_FP32, SQ_INSTS_VALU (rocprofv3 --pmc)"}
 
 
 def _log(args, *a):
@@ -281,12 +310,24 @@ def main(argv=None):
     # joins the main one; its work overlaps the cutoff sweeps and the geometry.
     knn_stream = None if args.no_overlap else torch.cuda.Stream()
 
+    # The KNN build forks either at the start of the step (it then shares the
+    # GPU with the cutoff count, which is VALU-bound like itself) or after the
+    # cutoff build (it then shares it with the geometry backward, which is
+    # bound by memory); the joint tuning below picks the faster schedule.
+    schedule = {"knn_fork": "start"}
+
     def step_overlap():
         main = torch.cuda.current_stream()
-        knn_stream.wait_stream(main)
-        with torch.cuda.stream(knn_stream):
-            kb.run(L, X, P, opts)
+        after = schedule["knn_fork"] == "after_cutoff"
+        if not after:
+            knn_stream.wait_stream(main)
+            with torch.cuda.stream(knn_stream):
+                kb.run(L, X, P, opts)
         cb.run(L, X, P, c, opts)
+        if after:
+            knn_stream.wait_stream(main)
+            with torch.cuda.stream(knn_stream):
+                kb.run(L, X, P, opts)
         if not fused:
             geo.forward(L, X, P, cb.src, cb.dst, cb.image, vec, length, num_edges=ne)
         geo.backward(L, X, P, cb.src, cb.dst, cb.image, None, glen, gf, gL, num_edges=ne)
@@ -311,27 +352,29 @@ def main(argv=None):
         # each build alone are not best together: time the captured step for a
         # few grid sizes of both sweeps (the KNN search radius stays as tuned).
         best_ms, best_cfg = None, None
-        for cw in (16, 32, 64):
-            for kw in (2, 4, 16):
-                cfg = {**tuning, "cutoff_wgs_per_cu": cw, "knn_wgs_per_cu": kw}
-                _lib.set_tuning(**cfg)
-                g = capture(step_timed)
-                for _ in range(3):
-                    g.replay()
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                for _ in range(10):
-                    g.replay()
-                e1.record()
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / 10
-                del g
-                if best_ms is None or ms < best_ms:
-                    best_ms, best_cfg = ms, cfg
-        tuning = best_cfg
+        for fork in ("start", "after_cutoff"):
+            schedule["knn_fork"] = fork
+            for cw in (16, 32, 64):
+                for kw in (2, 4, 16):
+                    cfg = {**tuning, "cutoff_wgs_per_cu": cw, "knn_wgs_per_cu": kw}
+                    _lib.set_tuning(**cfg)
+                    g = capture(step_timed)
+                    for _ in range(3):
+                        g.replay()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(10):
+                        g.replay()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / 10
+                    del g
+                    if best_ms is None or ms < best_ms:
+                        best_ms, best_cfg = ms, (cfg, fork)
+        tuning, schedule["knn_fork"] = best_cfg
         _lib.set_tuning(**tuning)
-        _log(args, "overlap tuning", tuning, round(best_ms, 4))
+        _log(args, "overlap tuning", tuning, schedule, round(best_ms, 4))
     run = step_timed
     if not args.no_graph:
         cg = capture(step_timed)
@@ -380,6 +423,10 @@ def main(argv=None):
                 ach = amount / (avg * 1e-3) / 1e12
                 d.update(bound="alu", achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                          frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4))
+            # executed FP32 work from the hardware counters, beside the algorithmic rate
+            cv = measured_valu(name, avg)
+            if cv is not None:
+                d["valu_counters"] = cv
         per[name] = d
     dom = max((n for n in per if n in work), key=lambda n: per[n]["ms_avg"], default=None)
     roof = None
@@ -410,7 +457,8 @@ def main(argv=None):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "ms_per_step_events": round(ms_step_ev, 4),
         "ms_per_step_eager": round(ms_eager, 4), "timed": "eager" if args.no_graph else "hip_graph",
-        "ms_loss_model_part": round(ms_loss, 4), "tuning": tuning, "source_digest": source_digest(),
+        "ms_loss_model_part": round(ms_loss, 4), "tuning": tuning,
+        "schedule": None if args.no_overlap else dict(schedule), "source_digest": source_digest(),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{B} structures, {N} atoms, cutoff {c} A, k {k}, one batched launch sequence "

@@ -370,10 +370,9 @@ typedef struct mg_tuning {
     int32_t cutoff_slots;         /* destination atoms per lane per image step (1, 2 or 4) */
     int32_t knn_wgs_per_cu;       /* persistent workgroups per CU for the KNN sweep */
     int32_t knn_lambda_x4;        /* KNN first-search radius targets (lambda_x4/4)*k + 6 candidates */
-    int32_t knn_cl_tau_x8;        /* cell-list KNN: the first sweep keeps candidates within (tau_x8/8)
-                                     times the k-th neighbour distance of a uniform density (sources
-                                     with fewer than k there are swept again at the full stencil
-                                     radius); default 10 */
+    int32_t knn_tau_x8;           /* KNN: the first sweep keeps candidates within (tau_x8/8) times the
+                                     k-th neighbour distance of a uniform density (sources with fewer
+                                     than k there are swept again at the full search radius); default 10 */
     int32_t cutoff_img_group;     /* image-table entries the cutoff sweep reads per scalar load group
                                      (2, 4 or 8; default 4) */
     int32_t reserved[2];

@@ -38,7 +38,7 @@ REPORT_BYTES = 64
 class MgTuning(ctypes.Structure):
     _fields_ = [("cutoff_wgs_per_cu", ctypes.c_int32), ("cutoff_slots", ctypes.c_int32),
                 ("knn_wgs_per_cu", ctypes.c_int32), ("knn_lambda_x4", ctypes.c_int32),
-                ("knn_cl_tau_x8", ctypes.c_int32), ("cutoff_img_group", ctypes.c_int32),
+                ("knn_tau_x8", ctypes.c_int32), ("cutoff_img_group", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
 
 

@@ -571,14 +571,14 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
         return hip_fail(e, "cell lists");
     if ((e = phase("knn.select", s, [&] {
              hipError_t r = mg::launch_knn(B, N, k, w.info, w.item_off, w.img.table, frac, src, dst, image, length,
-                                           w.ext_list, w.ctr, report, w.partials, grid, s);
+                                           w.ext_list, w.ctr, report, w.partials, grid, tu.knn_tau_x8 / 8.0f, s);
              if (r != hipSuccess || !sum) return r;
              return mg::launch_sum_partials(w.partials, grid * 4, report, s);
          })) != hipSuccess)
         return hip_fail(e, "knn");
     if (cl && (e = phase("knn.cells.select", s, [&] {
                    hipError_t r = mg::launch_cl_knn(B, k, w.info, w.cl, frac, src, dst, image, length, w.ext_list,
-                                                    w.ctr, report, w.partials, grid, tu.knn_cl_tau_x8 / 8.0f, s);
+                                                    w.ctr, report, w.partials, grid, tu.knn_tau_x8 / 8.0f, s);
                    if (r != hipSuccess || !sum) return r;
                    return mg::launch_sum_partials(w.partials, grid * 4, report, s);
                })) != hipSuccess)
@@ -879,8 +879,8 @@ mg_status mg_set_tuning(const mg_tuning* in) {
         return fail(MG_ERR_INVALID_ARG, "workgroups per CU must be in 0..64");
     if (in->knn_lambda_x4 < 0 || in->knn_lambda_x4 > 64)
         return fail(MG_ERR_INVALID_ARG, "knn_lambda_x4 must be in 0..64");
-    if (in->knn_cl_tau_x8 < 0 || in->knn_cl_tau_x8 > 64)
-        return fail(MG_ERR_INVALID_ARG, "knn_cl_tau_x8 must be in 0..64");
+    if (in->knn_tau_x8 < 0 || in->knn_tau_x8 > 64)
+        return fail(MG_ERR_INVALID_ARG, "knn_tau_x8 must be in 0..64");
     if (in->cutoff_img_group != 0 && in->cutoff_img_group != 2 && in->cutoff_img_group != 4 &&
         in->cutoff_img_group != 8)
         return fail(MG_ERR_INVALID_ARG, "cutoff_img_group must be 2, 4 or 8");
@@ -889,7 +889,7 @@ mg_status mg_set_tuning(const mg_tuning* in) {
     if (in->cutoff_slots) g_tune.cutoff_slots = in->cutoff_slots;
     if (in->knn_wgs_per_cu) g_tune.knn_wgs_per_cu = in->knn_wgs_per_cu;
     if (in->knn_lambda_x4) g_tune.knn_lambda_x4 = in->knn_lambda_x4;
-    if (in->knn_cl_tau_x8) g_tune.knn_cl_tau_x8 = in->knn_cl_tau_x8;
+    if (in->knn_tau_x8) g_tune.knn_tau_x8 = in->knn_tau_x8;
     if (in->cutoff_img_group) g_tune.cutoff_img_group = in->cutoff_img_group;
     return MG_OK;
 }

@@ -53,9 +53,9 @@ __device__ inline float cutoff_threshold_dev(float c) {
 
 // mode 0: cutoff, radius = cutoff (or the largest per-atom cutoff of the
 // structure); mode 1: KNN first search, radius from density.
-// One workgroup per structure: every thread scans coordinates for non-finite
-// values (and per-atom cutoffs), four atoms per round, thread 0 does the FP64
-// lattice work.
+// One workgroup per structure (one wave, or four for batches of large
+// structures): every thread scans coordinates for non-finite values (and
+// per-atom cutoffs), four atoms per round, thread 0 does the FP64 lattice work.
 __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattices,
                                                 const int64_t* __restrict__ ptr,
                                                 const float* __restrict__ frac, int B, float radius,
@@ -74,11 +74,12 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
     float rmax = 0.0f;
     auto out = [](float v) { return !(v >= -(float)CL_SHIFT_MAX && v < (float)(CL_SHIFT_MAX + 1)); };
     constexpr int U = 4;
-    for (int64_t a = a0 + tid; a < a1; a += U * 256) {
+    const int nt = blockDim.x;
+    for (int64_t a = a0 + tid; a < a1; a += U * nt) {
         float x[U][3];
 #pragma unroll
         for (int u = 0; u < U; ++u) {   // all loads of the round first
-            const int64_t q = a + u * 256 < a1 ? a + u * 256 : a;
+            const int64_t q = a + u * nt < a1 ? a + u * nt : a;
             x[u][0] = frac[3 * q];
             x[u][1] = frac[3 * q + 1];
             x[u][2] = frac[3 * q + 2];
@@ -89,8 +90,8 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
             far |= out(x[u][0]) || out(x[u][1]) || out(x[u][2]);
         }
         if (radii) {
-            for (int u = 0; u < U && a + u * 256 < a1; ++u) {
-                const int64_t q = a + u * 256;
+            for (int u = 0; u < U && a + u * nt < a1; ++u) {
+                const int64_t q = a + u * nt;
                 const float r = radii[q];
                 const bool ok = isfinite(r) && r > 0.0f;
                 bad |= !ok;
@@ -109,9 +110,12 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
     }
     __syncthreads();
     if (tid != 0) return;
-    const bool any_bad = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
-    const bool any_far = s_far[0] | s_far[1] | s_far[2] | s_far[3];
-    rmax = fmaxf(fmaxf(s_rmax[0], s_rmax[1]), fmaxf(s_rmax[2], s_rmax[3]));
+    bool any_bad = false, any_far = false;
+    for (int q = 0; q < nt / WAVE; ++q) {
+        any_bad |= s_bad[q] != 0;
+        any_far |= s_far[q] != 0;
+        rmax = fmaxf(rmax, s_rmax[q]);
+    }
 
     StructInfo si;
     uint32_t flags = any_bad ? (uint32_t)MG_FLAG_NONFINITE : 0u;
@@ -271,10 +275,11 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
                          int64_t N, float radius, const float* radii, float* thr, int knn_k,
                          float knn_lambda, StructInfo* info, PlanRow* plan, Counters* ctr, mg_report* report, int mode,
                          int opts, hipStream_t s) {
-    (void)N;
     (void)ctr;
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bounds, dim3(B), dim3(256), 0, s, lattices, batch_ptr, frac, B, radius, radii, thr,
+    // four waves per structure only when structures are large on average
+    const int nt = (B > 0 && N / B >= 256) ? 256 : 64;
+    hipLaunchKernelGGL(k_bounds, dim3(B), dim3(nt), 0, s, lattices, batch_ptr, frac, B, radius, radii, thr,
                        knn_k, knn_lambda, info, plan, report, mode, opts);
     return hipGetLastError();
 }

@@ -60,10 +60,12 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
 }
 
 // Ascending bitonic sort of 64*M keys held as v[r] of lane l = element r*64 + l.
-template <int M>
+// With MAXSZ < 64 only the blocks of MAXSZ consecutive lanes are sorted (block 0
+// ascending): enough when every key lies in lanes 0 .. MAXSZ-1.
+template <int M, int MAXSZ = WAVE * M>
 __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[M], int lane) {
 #pragma unroll
-    for (int size = 2; size <= WAVE * M; size <<= 1) {
+    for (int size = 2; size <= MAXSZ; size <<= 1) {
 #pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             if (stride >= WAVE) {
@@ -94,7 +96,7 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[M], int lane) {
     }
 }
 
-template <int M>
+template <int M, int MAXSZ = WAVE * M>
 __device__ __forceinline__ uint64_t sorted_rank(const uint64_t* buf, int cnt, int lane) {
     uint64_t v[M];
 #pragma unroll
@@ -102,12 +104,14 @@ __device__ __forceinline__ uint64_t sorted_rank(const uint64_t* buf, int cnt, in
         const int e = r * WAVE + lane;
         v[r] = e < cnt ? buf[e] : ~0ull;
     }
-    bitonic_sort<M>(v, lane);
+    bitonic_sort<M, MAXSZ>(v, lane);
     return v[0];
 }
 
-// Key of rank `lane` among buf[0..cnt) (cnt uniform, <= KNN_CAP).
+// Key of rank `lane` among buf[0..cnt) (cnt uniform, <= KNN_CAP); ranks below
+// min(cnt, 32) only when cnt <= 32 (a 32-key network, 15 stages instead of 21).
 __device__ __forceinline__ uint64_t sorted_head(const uint64_t* buf, int cnt, int lane) {
+    if (cnt <= WAVE / 2) return sorted_rank<1, WAVE / 2>(buf, cnt, lane);
     if (cnt <= WAVE) return sorted_rank<1>(buf, cnt, lane);
     if (cnt <= 2 * WAVE) return sorted_rank<2>(buf, cnt, lane);
     return sorted_rank<4>(buf, cnt, lane);
@@ -312,7 +316,8 @@ __global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInf
                                                    int32_t* __restrict__ src, int32_t* __restrict__ dst,
                                                    int32_t* __restrict__ image, float* __restrict__ length,
                                                    int32_t* __restrict__ ext_list, Counters* __restrict__ ctr,
-                                                   mg_report* __restrict__ rep, int64_t* __restrict__ partials) {
+                                                   mg_report* __restrict__ rep, int64_t* __restrict__ partials,
+                                                   float tau_scale) {
     __shared__ KnnShared sh;
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
@@ -354,8 +359,22 @@ __global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInf
         }
         wave_cand += (int64_t)n * S.I;
         const double R = (double)si->Rs;
-        const float tau2 = (float)(R * R) * (1.0f + 3e-6f);
-        const int cnt = collect(S, tau2, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
+        const float full = (float)(R * R) * (1.0f + 3e-6f);
+        // first threshold: tau_scale times the k-th neighbour distance of a
+        // uniform density (fewer keys to sort); swept again at the table's
+        // radius when fewer than k lie under it
+        float first = full;
+        {
+            const double det = L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
+                               L[2] * (L[3] * L[7] - L[4] * L[6]);
+            const double r = (double)tau_scale * cbrt(3.0 * (double)k * fabs(det) / (4.0 * 3.14159265358979323846 * (double)n));
+            if (tau_scale > 0.0f && r * r < (double)full) first = ufirstf((float)(r * r));
+        }
+        int cnt = collect(S, first, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
+        if (cnt < k && first < full) {
+            wave_cand += (int64_t)n * S.I;
+            cnt = collect(S, full, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
+        }
         if (cnt >= k) {
             emit(S, cnt, k, i, atom0, xi0, xi1, xi2, frac, buf, lane, src, dst, image, length);
         } else if (lane == 0) {
@@ -562,10 +581,10 @@ __global__ __launch_bounds__(256) void k_knn_extended(int k, const StructInfo* _
 hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const int64_t* item_off,
                       const ImageEntry* table, const float* frac, int32_t* src, int32_t* dst,
                       int32_t* image, float* length, int32_t* ext_list, Counters* ctr,
-                      mg_report* report, int64_t* partials, int grid, hipStream_t s) {
+                      mg_report* report, int64_t* partials, int grid, float tau_scale, hipStream_t s) {
     if (N == 0 || B == 0) return hipSuccess;
     hipLaunchKernelGGL(k_knn_first, dim3(grid), dim3(256), 0, s, B, k, info, item_off, table, frac, src, dst,
-                       image, length, ext_list, ctr, report, partials);
+                       image, length, ext_list, ctr, report, partials, tau_scale);
     return hipGetLastError();
 }
 

@@ -335,10 +335,12 @@ hipError_t launch_src_from_rows(const int64_t* offsets, int64_t N, int64_t capac
 hipError_t launch_scan_counts(const uint32_t* counts, int64_t N, int64_t* offsets, int64_t* bsum,
                               int64_t capacity, mg_report* report, hipStream_t s,
                               const int64_t* n_dev = nullptr, const int64_t* partials = nullptr, int np = 0);
+// tau_scale: the first sweep's threshold is tau_scale times the k-th
+// neighbour distance of a uniform density (0: the table's radius).
 hipError_t launch_knn(int B, int64_t N, int k, const StructInfo* info, const int64_t* item_off,
                       const ImageEntry* table, const float* frac, int32_t* src, int32_t* dst,
                       int32_t* image, float* length, int32_t* ext_list, Counters* ctr,
-                      mg_report* report, int64_t* partials, int grid, hipStream_t s);
+                      mg_report* report, int64_t* partials, int grid, float tau_scale, hipStream_t s);
 hipError_t launch_knn_extended(int B, int64_t N, int k, const StructInfo* info, const float* frac,
                                const int32_t* atom_struct, int32_t* src, int32_t* dst,
                                int32_t* image, float* length, const int32_t* ext_list,

@@ -10,9 +10,8 @@ Tunables (``mg_tuning`` in include/matgraph.h):
 - knn_lambda_x4:     4x the expected number of candidates per neighbour that
                      the first KNN search radius is sized for (for cell-list
                      structures it also sets the bin thickness);
-- knn_cl_tau_x8:     8x the factor on the uniform-density k-th neighbour
-                     distance of the first cell-list KNN threshold (tuned only
-                     when the batch has cell-list structures).
+- knn_tau_x8:        8x the factor on the uniform-density k-th neighbour
+                     distance of the first KNN threshold.
 
 Every candidate is timed with device events over repeated calls and must give
 the same graph as the first candidate: the KNN edges bit for bit, the cutoff
@@ -34,8 +33,7 @@ from . import _lib, graph
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "matgraph", "tune.json")
 
 CUTOFF_SPACE = {"cutoff_wgs_per_cu": [8, 16, 32, 64], "cutoff_slots": [1, 2, 4], "cutoff_img_group": [2, 4, 8]}
-KNN_SPACE = {"knn_wgs_per_cu": [2, 4, 8, 16], "knn_lambda_x4": [4, 6, 8, 12]}
-KNN_CL_SPACE = {"knn_cl_tau_x8": [8, 10, 12, 16]}   # added when the batch has cell-list structures
+KNN_SPACE = {"knn_wgs_per_cu": [2, 4, 8, 16], "knn_lambda_x4": [4, 6, 8, 12], "knn_tau_x8": [9, 10, 12, 16]}
 
 
 def _arch(device) -> str:
@@ -101,10 +99,7 @@ def tune(lattices, frac, batch_ptr, cutoff: float, k: int, reps: int = 5, space_
     base = _lib.get_tuning()
     space_cutoff = space_cutoff or CUTOFF_SPACE
     opts = graph.auto_opts(batch_ptr, None)
-    if space_knn is None:
-        space_knn = dict(KNN_SPACE)
-        if not (opts & _lib.MG_OPT_CELL_LIST_OFF):   # the batch has structures for cell lists
-            space_knn.update(KNN_CL_SPACE)
+    space_knn = space_knn or KNN_SPACE
     g = graph.cutoff_graph(lattices, frac, batch_ptr, cutoff, opts=opts)
     E, icap = g.num_edges, g.report.images_needed
     del g

@@ -23,7 +23,7 @@ def test_tune_and_cache(tmp_path, monkeypatch):
         ref_k = gu.knn(b)
         best = tune.autotune(L, X, P, b.cutoff, b.k, reps=2)
         assert set(best["cutoff"]) == {"cutoff_wgs_per_cu", "cutoff_slots", "cutoff_img_group"}
-        assert set(best["knn"]) == {"knn_wgs_per_cu", "knn_lambda_x4"}
+        assert set(best["knn"]) == {"knn_wgs_per_cu", "knn_lambda_x4", "knn_tau_x8"}
         cur = _lib.get_tuning()
         for key, v in {**best["cutoff"], **best["knn"]}.items():
             assert cur[key] == v
