@@ -262,7 +262,9 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
     si.wcl = (float)(wcl * (1.0 - 1e-6) - 1e-3);
     if (use_cl) si.groups = 0;
     si.chunks = 1;
-    si.pad0 = 0;
+    // (4/3) pi rk^3 n / V = k: the KNN passes start below a multiple of it
+    si.rk = (mode == 1 && valid) ? (float)cbrt(3.0 * (double)knn_k * fabs(det) / (4.0 * 3.14159265358979323846 * (double)n))
+                                 : 0.0f;
     si.xoff = 0;
     info[b] = si;
     const int64_t per = (n <= WAVE) ? (int64_t)min(si.G, n) : 1;   // sources of one group

@@ -1,24 +1,31 @@
 // k-nearest-neighbour multigraph (Sec. 1; Sec. 2.2, Algorithms 1 and 2).
 //
 // One wave per source atom. The candidates (j, t) of the source are streamed
-// in (j, t-lexicographic) order; a candidate survives when its FP32 length is
-// below the current threshold and is appended to a per-wave LDS buffer: the
-// paper's ordered stack ("concatenate new data, sort by distance, keep the
-// k nearest"), kept on chip. When the buffer is full it is sorted (bitonic,
-// in registers across the 64 lanes), cut to the k smallest keys and the
-// threshold drops to the k-th length, so the buffer only ever holds plausible
+// through a per-wave LDS buffer: the paper's ordered stack ("concatenate new
+// data, sort by distance, keep the k nearest"), kept on chip. A candidate
+// survives when its FP32 length is below the current threshold and is
+// appended to the buffer; when the buffer is full it is sorted (bitonic, in
+// registers across the 64 lanes), cut to the k smallest keys and the threshold
+// drops to the k-th length, so the buffer only ever holds plausible
 // neighbours. Keys are (length bits << 32 | candidate ordinal); the ordinal
 // j * I + image_index follows (dst, t) order because image tables are built in
-// lexicographic t order, which gives the tie order (length, dst, t).
+// lexicographic t order, which gives the tie order (length, dst, t). The
+// result is the k smallest keys whatever order the candidates arrive in.
+//
+// Lane layout: lane (u, jj) keeps the pair offset of one destination in
+// registers and takes every R-th image of the set (R = 64 / min(n, 64) image
+// slots), so a batch covers min(n, 64) destinations x R images.
 //
 // Search area (Algorithm 1). The first pass enumerates the image table built
 // for a radius R0 from the structure's density (about lambda * k candidates
-// expected). A source whose stack holds at least k keys is exact: every
-// candidate shorter than R0 lies in the table. Sources with fewer than k
-// survivors are queued for the extended pass, which enumerates the full image
-// box of radius 2 R0, 4 R0, ... (images computed on the fly in FP64) until k
-// are found inside the radius - the expanding search of Algorithm 1 with the
-// termination test "k-th distance inside the evaluated area".
+// expected), first under a tighter threshold (a multiple of the k-th
+// neighbour distance of a uniform density), then, if fewer than k keys lie
+// under it, under R0 itself. A source whose stack then holds at least k keys
+// is exact: every candidate shorter than R0 lies in the table. Sources with
+// fewer than k survivors are queued for the extended pass, which enumerates the
+// full image box of radius 2 R0, 4 R0, ... (images computed on the fly in FP64)
+// until k are found inside the radius - the expanding search of Algorithm 1
+// with the termination test "k-th distance inside the evaluated area".
 //
 // Every wave-level decision (loop bounds, stack size, threshold, the sort
 // branch) is taken on values made explicitly uniform with readfirstlane, every
@@ -33,13 +40,13 @@ namespace mg {
 namespace {
 
 constexpr int KNN_WAVES = 4;
-constexpr int KNN_JC = 256;    // destinations staged in LDS per chunk
 constexpr int KNN_CAP = 256;   // ordered-stack capacity per wave (keys)
+constexpr int KNN_PF = 2;      // table batches read ahead by the first pass
+constexpr int KNN_BUF = 256;   // stack room of the first pass (compressed above KNN_BUF - KNN_PF * WAVE keys)
 constexpr int KNN_MAX_ATTEMPTS = 24;
 
 struct KnnShared {
-    float4 p[KNN_WAVES][KNN_JC];
-    uint64_t buf[KNN_WAVES][KNN_CAP];
+    uint64_t buf[KNN_WAVES][KNN_BUF];
 };
 
 __device__ __forceinline__ int ufirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -163,6 +170,18 @@ struct Stack {
     float tau2;
 };
 
+// Keep the k smallest of the cnt <= CAP keys in buf (buf[0..k) afterwards) and
+// return the threshold their k-th length allows.
+template <int CAP>
+__device__ __forceinline__ float compress_stack(uint64_t* buf, int cnt, int k, int lane) {
+    wave_lds_sync();
+    const uint64_t v0 = sorted_rank<CAP / WAVE>(buf, cnt, lane);
+    wave_lds_sync();
+    if (lane < k) buf[lane] = v0;
+    const uint64_t kth = readlane_u64(v0, k - 1);
+    return ufirstf(thr_from_len(key_len(kth)));
+}
+
 // Push this lane's candidate (pass, l2, ordinal lo) onto the stack of CAP
 // keys; when the stack would overflow, keep the k smallest keys and lower the
 // threshold first.
@@ -173,12 +192,7 @@ __device__ __forceinline__ void stack_push(Stack& st, bool pass, float l2, uint3
     int c = ufirst(__popcll(m));
     if (c == 0) return;
     if (st.cnt + c > CAP) {
-        wave_lds_sync();
-        const uint64_t v0 = sorted_rank<CAP / WAVE>(buf, st.cnt, lane);
-        wave_lds_sync();
-        if (lane < k) buf[lane] = v0;
-        const uint64_t kth = readlane_u64(v0, k - 1);
-        st.tau2 = ufirstf(fminf(st.tau2, thr_from_len(key_len(kth))));
+        st.tau2 = ufirstf(fminf(st.tau2, compress_stack<CAP>(buf, st.cnt, k, lane)));
         st.cnt = k;
         pass = pass && l2 < st.tau2;
         m = ballot(pass);
@@ -189,103 +203,143 @@ __device__ __forceinline__ void stack_push(Stack& st, bool pass, float l2, uint3
     st.cnt = ufirst(st.cnt + c);
 }
 
+// The same push without the capacity test (the caller has made room).
+__device__ __forceinline__ void stack_append(Stack& st, bool pass, float l2, uint32_t lo, uint64_t* buf) {
+    const uint64_t m = ballot(pass);
+    const int c = ufirst(__popcll(m));
+    if (c == 0) return;
+    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(sqrt_rn_finite(l2)) << 32) | (uint64_t)lo;
+    st.cnt = ufirst(st.cnt + c);
+}
+
 // Stream every candidate (j, t) of source il through the ordered stack with the
-// initial threshold tau2. Returns the uniform number of keys left in buf.
-__device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int n, int il, int64_t atom0,
-                                       const double* L, double xi0, double xi1, double xi2,
-                                       const float* __restrict__ frac, float4* P, uint64_t* buf, int lane) {
+// initial threshold tau2. fr: the structure's fractional coordinates. Lane
+// (u, jj), lane = u * nn + jj with nn = min(n, 64), holds destination jc + jj
+// of the chunk and takes images u, u + R, u + 2R, ... (R = 64 / nn). TAB: the
+// images come from the structure's table, KNN_PF batches at a time with every
+// load issued before the first is used (indices clamped into the table; a
+// second buffer loaded a group ahead measured slower: it costs occupancy); the
+// stack is compressed before a group when more than KNN_CAP keys are held, so
+// the group's pushes need no test (buf holds KNN_BUF keys). Otherwise the
+// images come from the box, computed in FP64, with the test at every push.
+// Returns the uniform number of keys left in buf (at most KNN_BUF - KNN_PF * 64,
+// which is KNN_CAP).
+template <bool TAB>
+__device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int n, int il, const double* L,
+                                       double xi0, double xi1, double xi2, const float* __restrict__ fr,
+                                       uint64_t* buf, int lane) {
     Stack st{0, tau2};
     const uint32_t I = S.I;
-    const float invI = 1.0f / (float)I;
-    for (int jc0 = 0; jc0 < n; jc0 += KNN_JC) {
-        const int nj = min(KNN_JC, n - jc0);
-        wave_lds_sync();
-        for (int jj = lane; jj < nj; jj += WAVE) {
-            const int64_t aj = atom0 + jc0 + jj;
-            double d0 = (double)frac[3 * aj] - xi0;
-            double d1 = (double)frac[3 * aj + 1] - xi1;
-            double d2 = (double)frac[3 * aj + 2] - xi2;
+    const int nn = min(n, WAVE);
+    const uint32_t R = (uint32_t)(WAVE / nn);
+    const int u = lane / nn;
+    const int jj = lane - u * nn;
+    for (int jc = 0; jc < n; jc += nn) {
+        const int j = jc + jj;
+        const bool lok = (uint32_t)u < R && j < n;
+        float px = 0.f, py = 0.f, pz = 0.f;
+        if (lok) {
+            double d0 = (double)fr[3 * j] - xi0;
+            double d1 = (double)fr[3 * j + 1] - xi1;
+            double d2 = (double)fr[3 * j + 2] - xi2;
             d0 -= rint(d0);
             d1 -= rint(d1);
             d2 -= rint(d2);
-            double px, py, pz;
-            cart64(L, d0, d1, d2, px, py, pz);
-            P[jj] = make_float4((float)px, (float)py, (float)pz, __int_as_float(jc0 + jj == il ? 1 : 0));
+            double x, y, z;
+            cart64(L, d0, d1, d2, x, y, z);
+            px = (float)x;
+            py = (float)y;
+            pz = (float)z;
         }
-        wave_lds_sync();
-        const uint32_t nq = (uint32_t)nj * I;
-        // candidate ql = jl * I + img of this lane, advanced by WAVE per batch
-        // (jl += WAVE / I, img += WAVE % I with a carry); the table entry of the
-        // next batch is loaded while the current one is evaluated
-        auto split = [&](uint32_t ql, uint32_t& jl, uint32_t& img) {
-            jl = (uint32_t)((float)ql * invI);
-            if (jl * I > ql) --jl;
-            if ((jl + 1) * I <= ql) ++jl;
-            img = ql - jl * I;
+        const bool selfj = lok && j == il;
+        const uint32_t ordj = (uint32_t)j * I;
+        auto step = [&](uint32_t m, float sx, float sy, float sz) {
+            const bool valid = lok && m < I;
+            const float dx = px + sx, dy = py + sy, dz = pz + sz;
+            const float l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const bool pass = valid && l2 < st.tau2 && !(selfj && (int)m == S.zidx);
+            stack_push(st, pass, l2, ordj + m, k, buf, lane);
         };
-        const uint32_t dj = (uint32_t)WAVE / I, di = (uint32_t)WAVE - dj * I;
-        auto advance = [&](uint32_t& jl, uint32_t& img) {
-            jl += dj;
-            img += di;
-            if (img >= I) {
-                img -= I;
-                ++jl;
+        if (TAB) {
+            const ImageEntry* tab = S.tab;
+            for (uint32_t m0 = 0; m0 < I; m0 += KNN_PF * R) {
+                if (st.cnt > KNN_BUF - KNN_PF * WAVE) {
+                    st.tau2 = ufirstf(fminf(st.tau2, compress_stack<KNN_BUF>(buf, st.cnt, k, lane)));
+                    st.cnt = k;
+                    wave_lds_sync();
+                }
+                float e[KNN_PF][3];
+#pragma unroll
+                for (int d = 0; d < KNN_PF; ++d) {
+                    const uint32_t m = min(m0 + (uint32_t)d * R + (uint32_t)u, I - 1);
+                    const ImageEntry t = tab[m];
+                    e[d][0] = t.sx;
+                    e[d][1] = t.sy;
+                    e[d][2] = t.sz;
+                }
+#pragma unroll
+                for (int d = 0; d < KNN_PF; ++d) {
+                    const uint32_t mb = m0 + (uint32_t)d * R;
+                    if (mb >= I) break;   // uniform
+                    const uint32_t m = mb + (uint32_t)u;
+                    const bool valid = lok && m < I;
+                    const float dx = px + e[d][0], dy = py + e[d][1], dz = pz + e[d][2];
+                    const float l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    const bool pass = valid && l2 < st.tau2 && !(selfj && (int)m == S.zidx);
+                    stack_append(st, pass, l2, ordj + m, buf);
+                }
             }
-        };
-        uint32_t jl, img;
-        split((uint32_t)lane, jl, img);
-        uint32_t jn = jl, in = img;
-        advance(jn, in);
-        float4 ent = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (S.tab && (uint32_t)lane < nq) {
-            const ImageEntry e = S.tab[img];
-            ent = make_float4(e.sx, e.sy, e.sz, 0.f);
-        }
-        for (uint32_t b0 = 0; b0 < nq; b0 += WAVE, jl = jn, img = in, advance(jn, in)) {
-            const uint32_t ql = b0 + (uint32_t)lane;
-            const bool valid = ql < nq;
-            const float4 cur = ent;
-            if (S.tab && ql + WAVE < nq) {
-                const ImageEntry e = S.tab[in];
-                ent = make_float4(e.sx, e.sy, e.sz, 0.f);
-            }
-            bool pass = false;
-            float l2 = 0.0f;
-            if (valid) {
-                const float4 pp = P[jl];
-                float sx, sy, sz;
-                if (S.tab) {
-                    sx = cur.x;
-                    sy = cur.y;
-                    sz = cur.z;
-                } else {
+        } else {
+            for (uint32_t m = (uint32_t)u, m0 = 0; m0 < I; m0 += R, m += R) {
+                float sx = 0.f, sy = 0.f, sz = 0.f;
+                if (lok && m < I) {
                     int t0, t1, t2;
-                    image_t(S, img, t0, t1, t2);
+                    image_t(S, m, t0, t1, t2);
                     double cx, cy, cz;
                     cart64(L, (double)t0, (double)t1, (double)t2, cx, cy, cz);
                     sx = (float)cx;
                     sy = (float)cy;
                     sz = (float)cz;
                 }
-                const float dx = pp.x + sx, dy = pp.y + sy, dz = pp.z + sz;
-                l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                pass = l2 < st.tau2 && !(__float_as_int(pp.w) != 0 && (int)img == S.zidx);
+                step(m, sx, sy, sz);
             }
-            stack_push(st, pass, l2, (uint32_t)(jc0 + jl) * I + img, k, buf, lane);
         }
+    }
+    static_assert(KNN_BUF - KNN_PF * WAVE <= KNN_CAP, "the final sort takes at most KNN_CAP keys");
+    if (TAB && st.cnt > KNN_BUF - KNN_PF * WAVE) {
+        st.tau2 = ufirstf(fminf(st.tau2, compress_stack<KNN_BUF>(buf, st.cnt, k, lane)));
+        st.cnt = k;
     }
     wave_lds_sync();
     return st.cnt;
 }
 
-// Sort the stack and write the k edges of source i (requires cnt >= k).
+// The k smallest of the cnt keys in buf (cnt uniform, k <= cnt): returns the
+// rank of this lane's key (k or more: no key for this lane) and the key. Up to
+// 64 keys every lane ranks its own key against the others (the keys are
+// distinct, their ordinals are): cnt broadcasts and compares instead of a
+// sorting network's dependent cross-lane exchanges; more keys are sorted.
+__device__ __forceinline__ int ranked_key(const uint64_t* buf, int cnt, int k, int lane, uint64_t& key) {
+    if (cnt <= WAVE) {
+        key = lane < cnt ? buf[lane] : ~0ull;
+        int rank = 0;
+        for (int q = 0; q < cnt; ++q) rank += readlane_u64(key, q) < key ? 1 : 0;
+        return lane < cnt ? rank : k;
+    }
+    key = sorted_head(buf, cnt, lane);
+    return lane;
+}
+
+// Write the k edges of source i from the stack (requires cnt >= k), each key at
+// its rank.
 __device__ __forceinline__ void emit(const ImageSet& S, int cnt, int k, int64_t i, int64_t atom0,
                                      double xi0, double xi1, double xi2, const float* __restrict__ frac,
                                      const uint64_t* buf, int lane, int32_t* __restrict__ src,
                                      int32_t* __restrict__ dst, int32_t* __restrict__ image,
                                      float* __restrict__ length) {
-    const uint64_t key = sorted_head(buf, cnt, lane);
-    if (lane < k) {
+    uint64_t key;
+    const int slot = ranked_key(buf, cnt, k, lane, key);
+    if (slot < k) {
         const uint32_t qv = (uint32_t)key;
         const uint32_t j = qv / S.I;
         const uint32_t img = qv - j * S.I;
@@ -294,7 +348,7 @@ __device__ __forceinline__ void emit(const ImageSet& S, int cnt, int k, int64_t 
         const int64_t aj = atom0 + j;
         const double d0 = (double)frac[3 * aj] - xi0, d1 = (double)frac[3 * aj + 1] - xi1,
                      d2 = (double)frac[3 * aj + 2] - xi2;
-        const int64_t e = i * k + lane;
+        const int64_t e = i * k + slot;
         src[e] = (int32_t)i;
         dst[e] = (int32_t)aj;
         image[3 * e] = t0 - (int)rint(d0);
@@ -321,18 +375,12 @@ __global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInf
     __shared__ KnnShared sh;
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
-    float4* P = sh.p[wv];
     uint64_t* buf = sh.buf[wv];
     const uint32_t bad = MG_FLAG_SINGULAR | MG_FLAG_NONFINITE | MG_FLAG_RANGE | MG_FLAG_IMAGES;
     const int64_t total = item_off[B];
     int64_t wave_cand = 0;
     for (int64_t q = grid_wave(); q < total; q += grid_waves()) {
-        int lo = 0, hi = B;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (item_off[mid] <= q) lo = mid;
-            else hi = mid;
-        }
+        const int lo = ufirst(wave_search_le(item_off, B, q, lane));
         const StructInfo* si = info + lo;
         const int n = si->n;
         const int64_t atom0 = si->atom0;
@@ -365,15 +413,16 @@ __global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInf
         // radius when fewer than k lie under it
         float first = full;
         {
-            const double det = L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
-                               L[2] * (L[3] * L[7] - L[4] * L[6]);
-            const double r = (double)tau_scale * cbrt(3.0 * (double)k * fabs(det) / (4.0 * 3.14159265358979323846 * (double)n));
+            const double r = (double)tau_scale * (double)si->rk;
             if (tau_scale > 0.0f && r * r < (double)full) first = ufirstf((float)(r * r));
         }
-        int cnt = collect(S, first, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
-        if (cnt < k && first < full) {
+        const float* fr = frac + 3 * atom0;
+        int cnt = 0;
+        for (float thr = first;;) {   // one inlined sweep for both thresholds
+            cnt = collect<true>(S, thr, k, n, il, L, xi0, xi1, xi2, fr, buf, lane);
+            if (cnt >= k || !(thr < full)) break;
             wave_cand += (int64_t)n * S.I;
-            cnt = collect(S, full, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
+            thr = full;
         }
         if (cnt >= k) {
             emit(S, cnt, k, i, atom0, xi0, xi1, xi2, frac, buf, lane, src, dst, image, length);
@@ -425,12 +474,8 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
         const float wc = si->wcl;
         const float full = wc * wc;
         float first = full;
-        {   // k-th neighbour distance of a uniform density n / V: (4/3) pi r^3 n / V = k
-            const double* L = it.L;
-            const double det = L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
-                               L[2] * (L[3] * L[7] - L[4] * L[6]);
-            const double rk = cbrt(3.0 * (double)k * fabs(det) / (4.0 * 3.14159265358979323846 * (double)n));
-            const double r = (double)tau_scale * rk;
+        {   // a multiple of the k-th neighbour distance of a uniform density
+            const double r = (double)tau_scale * (double)si->rk;
             if (tau_scale > 0.0f && r * r < (double)full) first = ufirstf((float)(r * r));
         }
         const int T = it.total;
@@ -475,11 +520,12 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                 wave_cand += T;
                 const int any_overflow = ufirst(ballot(overflow != 0) != 0 ? 1 : 0);
                 if (st.cnt >= k && !any_overflow) {
-                    const uint64_t key = sorted_head(buf, st.cnt, lane);
-                    if (lane < k) {
+                    uint64_t key;
+                    const int slot = ranked_key(buf, st.cnt, k, lane, key);
+                    if (slot < k) {
                         const uint32_t qv = (uint32_t)key;
                         const uint32_t jl = qv >> 15, tc = qv & 32767u;
-                        const int64_t e = S.i * k + lane;
+                        const int64_t e = S.i * k + slot;
                         src[e] = (int32_t)S.i;
                         dst[e] = (int32_t)(atom0 + jl);
                         image[3 * e] = (int)(tc >> 10) - 16;
@@ -516,7 +562,6 @@ __global__ __launch_bounds__(256) void k_knn_extended(int k, const StructInfo* _
     __shared__ KnnShared sh;
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
-    float4* P = sh.p[wv];
     uint64_t* buf = sh.buf[wv];
     const uint32_t total = (uint32_t)ufirst((int)ctr->knn2_count);
     for (int64_t q = grid_wave(); q < (int64_t)total; q += grid_waves()) {
@@ -565,7 +610,7 @@ __global__ __launch_bounds__(256) void k_knn_extended(int k, const StructInfo* _
             S.I = (uint32_t)((2 * S.n0 + 1) * (2 * S.n1 + 1) * (2 * S.n2 + 1));
             S.zidx = (S.n0 * (2 * S.n1 + 1) + S.n1) * (2 * S.n2 + 1) + S.n2;
             const float tau2 = ufirstf((float)(R * R) * (1.0f + 3e-6f));
-            const int cnt = collect(S, tau2, k, n, il, atom0, L, xi0, xi1, xi2, frac, P, buf, lane);
+            const int cnt = collect<false>(S, tau2, k, n, il, L, xi0, xi1, xi2, frac + 3 * atom0, buf, lane);
             if (cnt >= k) {
                 emit(S, cnt, k, i, atom0, xi0, xi1, xi2, frac, buf, lane, src, dst, image, length);
                 done = 1;

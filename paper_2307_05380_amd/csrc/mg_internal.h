@@ -41,7 +41,7 @@ struct alignas(16) StructInfo {
     int32_t G;          // sources per work item
     int32_t groups;     // source groups (work items before image chunks)
     int32_t chunks;     // image chunks per source group in the cutoff sweeps (1 unless the plan splits)
-    int32_t pad0;
+    float rk;           // KNN: k-th neighbour distance of a uniform density n / V (Angstrom)
     int64_t xoff;       // chunks > 1: first of this structure's per-(source, chunk) counts
     float R;            // radius the table was built for, with rounding margin (Angstrom)
     float Rs;           // search radius before the margin (Angstrom)
