@@ -72,3 +72,25 @@ def test_single_atom_cells():
     b = inputs.random_batch(rng, 40, 1, 1, 2.5, 20.0, 30.0, 150.0, k=16)
     g = gu.knn(b)
     compare.knn_check(b, 16, *gu.np_graph(g))
+
+
+@pytest.mark.parametrize("k", [33, 64])
+def test_large_stacks_same_graph(k):
+    """A wide first radius (lambda = 8) and no tighter first threshold push
+    hundreds of keys per source: the ordered stack is compressed inside the
+    sweep and more than 64 keys are sorted at the end. The graph must equal the
+    oracle's and, bit for bit, the graph of the default search."""
+    rng = np.random.default_rng(70 + k)
+    b = inputs.random_batch(rng, 16, 20, 120, 4.0, 12.0, cutoff=5.0, k=k)
+    ref = gu.np_graph(gu.knn(b))
+    saved = _lib.get_tuning()
+    try:
+        _lib.set_tuning(**dict(saved, knn_lambda_x4=32, knn_tau_x8=64))
+        g = gu.knn(b)
+    finally:
+        _lib.set_tuning(**saved)
+    assert g.report.flags & ~_lib.MG_FLAG_KNN_EXTENDED == 0, g.report.flag_names()
+    got = gu.np_graph(g)
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
+    compare.knn_check(b, k, *got)
