@@ -375,10 +375,14 @@ typedef struct mg_tuning {
                                      than k there are swept again at the full search radius); default 10 */
     int32_t cutoff_img_group;     /* image-table entries the cutoff sweep reads per scalar load group
                                      (2, 4 or 8; default 4) */
-    int32_t reserved[2];
+    int32_t cutoff_cl_span;       /* cell lists of the cutoff calls: stencil half-width in bins, 1 (27
+                                     bins at least the radius thick, the default) or 2 (125 bins at
+                                     least half the radius thick: fewer candidates, smaller tiles) */
+    int32_t knn_cl_span;          /* the same for the KNN calls' cell lists */
 } mg_tuning;
 
-/* [host] Read / replace the tuning parameters used by later calls. */
+/* [host] Read / replace the tuning parameters used by later calls. A field set to 0 in
+ * mg_set_tuning keeps its current value. */
 mg_status mg_get_tuning(mg_tuning* out);
 mg_status mg_set_tuning(const mg_tuning* in);
 

@@ -39,7 +39,7 @@ class MgTuning(ctypes.Structure):
     _fields_ = [("cutoff_wgs_per_cu", ctypes.c_int32), ("cutoff_slots", ctypes.c_int32),
                 ("knn_wgs_per_cu", ctypes.c_int32), ("knn_lambda_x4", ctypes.c_int32),
                 ("knn_tau_x8", ctypes.c_int32), ("cutoff_img_group", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("cutoff_cl_span", ctypes.c_int32), ("knn_cl_span", ctypes.c_int32)]
 
 
 class MatgraphError(RuntimeError):
@@ -126,7 +126,7 @@ def get_tuning() -> dict:
     lib = load()
     t = MgTuning()
     check(lib.mg_get_tuning(ctypes.byref(t)), lib)
-    return {f: getattr(t, f) for f, _ in MgTuning._fields_ if f != "reserved"}
+    return {f: getattr(t, f) for f, _ in MgTuning._fields_}
 
 
 def set_tuning(**kw):

@@ -39,7 +39,7 @@ mg_status mg::api_fail(mg_status st, const char* msg) { return fail(st, "%s", ms
 namespace {
 
 std::mutex g_mu;
-mg_tuning g_tune = {32, 2, 8, 6, 10, 4, {0, 0}};
+mg_tuning g_tune = {32, 2, 8, 6, 10, 4, 1, 1};
 
 mg_tuning tuning() {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -426,7 +426,7 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
     const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
     if ((e = phase("cutoff.bounds", s, [&] {
              return mg::launch_bounds(lattices, batch_ptr, frac, B, N, cutoff, radii, thr, 0, 0.f, w.info,
-                                      w.plan, w.ctr, report, 0, opts, s);
+                                      w.plan, w.ctr, report, 0, opts, tu.cutoff_cl_span, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("cutoff.plan", s, [&] {
@@ -553,7 +553,7 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
     const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
     if ((e = phase("knn.bounds", s, [&] {
              return mg::launch_bounds(lattices, batch_ptr, frac, B, N, 0.f, nullptr, nullptr, k, lambda,
-                                      w.info, w.plan, w.ctr, report, 1, opts, s);
+                                      w.info, w.plan, w.ctr, report, 1, opts, tu.knn_cl_span, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("knn.plan", s, [&] {
@@ -630,7 +630,7 @@ mg_status mg_images_needed(const float* lattices, const float* frac, const int64
     if ((e = mg::launch_zero_report(report, ctr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
     if ((e = mg::launch_bounds(lattices, batch_ptr, frac, B, N, k == 0 ? (radii ? 1.0f : cutoff) : 0.f,
                                k == 0 ? radii : nullptr, thr, k, lambda, info, plan, ctr, report, k == 0 ? 0 : 1,
-                               opts, s)) != hipSuccess)
+                               opts, k == 0 ? tu.cutoff_cl_span : tu.knn_cl_span, s)) != hipSuccess)
         return hip_fail(e, "bounds");
     // the plan with an unbounded table: images_needed is the batch's total, no structure skipped
     if ((e = mg::launch_struct_scan(B, info, plan, 0, item_off, cl_off, box_off, ctr, report, INT64_MAX, s)) !=
@@ -884,6 +884,8 @@ mg_status mg_set_tuning(const mg_tuning* in) {
     if (in->cutoff_img_group != 0 && in->cutoff_img_group != 2 && in->cutoff_img_group != 4 &&
         in->cutoff_img_group != 8)
         return fail(MG_ERR_INVALID_ARG, "cutoff_img_group must be 2, 4 or 8");
+    if (in->cutoff_cl_span < 0 || in->cutoff_cl_span > 2 || in->knn_cl_span < 0 || in->knn_cl_span > 2)
+        return fail(MG_ERR_INVALID_ARG, "cell-list spans must be 1 or 2");
     std::lock_guard<std::mutex> lk(g_mu);
     if (in->cutoff_wgs_per_cu) g_tune.cutoff_wgs_per_cu = in->cutoff_wgs_per_cu;
     if (in->cutoff_slots) g_tune.cutoff_slots = in->cutoff_slots;
@@ -891,6 +893,8 @@ mg_status mg_set_tuning(const mg_tuning* in) {
     if (in->knn_lambda_x4) g_tune.knn_lambda_x4 = in->knn_lambda_x4;
     if (in->knn_tau_x8) g_tune.knn_tau_x8 = in->knn_tau_x8;
     if (in->cutoff_img_group) g_tune.cutoff_img_group = in->cutoff_img_group;
+    if (in->cutoff_cl_span) g_tune.cutoff_cl_span = in->cutoff_cl_span;
+    if (in->knn_cl_span) g_tune.knn_cl_span = in->knn_cl_span;
     return MG_OK;
 }
 

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
                                                 const float* __restrict__ radii, float* __restrict__ thr,
                                                 int knn_k, float knn_lambda,
                                                 StructInfo* __restrict__ info, PlanRow* __restrict__ plan,
-                                                mg_report* __restrict__ rep, int mode, int opts) {
+                                                mg_report* __restrict__ rep, int mode, int opts, int cl_span) {
     __shared__ int s_bad[4], s_far[4];
     __shared__ float s_rmax[4];
     const int b = blockIdx.x;
@@ -159,35 +159,46 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
     // Cell lists: m_k bins of thickness h_k / m_k >= Rb along every direction
     // (h_k = |det| / |a_{k+1} x a_{k+2}| is the spacing of the lattice planes),
     // so every neighbour within Rb lies in the 27 bins around the source's bin;
-    // m_k >= 3 keeps those 27 bins distinct. Bins are capped at 2n + 64.
+    // m_k >= 3 keeps those 27 bins distinct. With a stencil half-width S = 2
+    // the bins are at least Rb / 2 thick and the 125 bins within two of the
+    // source's bin hold every neighbour (m_k >= 5; otherwise S = 1). Bins are
+    // capped at 2n + 64.
     // Cell lists store every atom's cell floor(x) (and u - floor(x)) packed in
     // 10-bit fields; a structure with a coordinate outside [-510, 511) takes the
     // image sweep, which has no such limit.
     int cm[3] = {0, 0, 0};
     double wcl = 0.0;
     bool use_cl = false;
+    int cls = 1;
     if (valid && !any_far && !(opts & MG_OPT_CELL_LIST_OFF) &&
         (n >= CL_MIN_ATOMS || (opts & MG_OPT_CELL_LIST_FORCE))) {
         double h[3];
-        bool ok = true;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 3; ++k)
             h[k] = fabs(det) / sqrt(c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2]);
-            const double mk = floor(h[k] / Rb);
-            ok &= mk >= 3.0;
-            cm[k] = ok ? (int)fmin(mk, 1024.0) : 0;
-        }
-        if (ok) {
-            // shrink the largest direction until the bins fit 2n + 64 (27 always fits)
+        for (int S = cl_span >= 2 ? 2 : 1; S >= 1 && !use_cl; --S) {
+            const int mmin = 2 * S + 1;
+            bool ok = true;
+            for (int k = 0; k < 3; ++k) {
+                const double mk = floor(h[k] * S / Rb);
+                ok &= mk >= (double)mmin;
+                cm[k] = ok ? (int)fmin(mk, 1024.0) : 0;
+            }
+            if (!ok) continue;
+            // shrink the largest direction until the bins fit 2n + 64 (27 bins always fit;
+            // when 125 do not, the stencil falls back to 27)
             const double cap = 2.0 * n + 64.0;
             for (int it = 0; it < 4096; ++it) {
                 const double tot = (double)cm[0] * cm[1] * cm[2];
                 if (tot <= cap) break;
                 const int a = (cm[0] >= cm[1] && cm[0] >= cm[2]) ? 0 : (cm[1] >= cm[2] ? 1 : 2);
-                const int shrunk = max(3, (int)floor(cm[a] * cap / tot));
+                const int shrunk = max(mmin, (int)floor(cm[a] * cap / tot));
                 cm[a] = shrunk < cm[a] ? shrunk : cm[a] - 1;
+                if (cm[a] < mmin) break;
             }
-            wcl = fmin(fmin(h[0] / cm[0], h[1] / cm[1]), h[2] / cm[2]);
+            if ((double)cm[0] * cm[1] * cm[2] > cap || cm[0] < mmin || cm[1] < mmin || cm[2] < mmin) continue;
+            wcl = S * fmin(fmin(h[0] / cm[0], h[1] / cm[1]), h[2] / cm[2]);
             use_cl = true;
+            cls = S;
         }
     }
     // quantities of the image tests
@@ -260,6 +271,8 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
     si.bin_off = 0;
     si.cl_items = use_cl ? si.nbins : 0;   // one work item per bin
     si.wcl = (float)(wcl * (1.0 - 1e-6) - 1e-3);
+    si.cl_s = use_cl ? cls : 0;
+    si.pad1 = 0;
     if (use_cl) si.groups = 0;
     si.chunks = 1;
     // (4/3) pi rk^3 n / V = k: the KNN passes start below a multiple of it
@@ -276,13 +289,13 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
                          int64_t N, float radius, const float* radii, float* thr, int knn_k,
                          float knn_lambda, StructInfo* info, PlanRow* plan, Counters* ctr, mg_report* report, int mode,
-                         int opts, hipStream_t s) {
+                         int opts, int cl_span, hipStream_t s) {
     (void)ctr;
     if (B == 0) return hipSuccess;
     // four waves per structure only when structures are large on average
     const int nt = (B > 0 && N / B >= 256) ? 256 : 64;
     hipLaunchKernelGGL(k_bounds, dim3(B), dim3(nt), 0, s, lattices, batch_ptr, frac, B, radius, radii, thr,
-                       knn_k, knn_lambda, info, plan, report, mode, opts);
+                       knn_k, knn_lambda, info, plan, report, mode, opts, cl_span);
     return hipGetLastError();
 }
 

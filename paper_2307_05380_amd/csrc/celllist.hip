@@ -189,9 +189,15 @@ hipError_t launch_cl_build(int B, int64_t N, const float* frac, const int64_t* b
 // every source's edge count; after the scan the fill pass repeats the sweep
 // and writes each hit at offsets[src] + (its rank among the source's hits),
 // ranked with a wave ballot and mbcnt, with 32-bit offsets from a per-source
-// scalar base.
+// scalar base. A candidate whose staged distance lies within a relative 1e-4
+// of the threshold (far above the staged form's rounding) is decided, and
+// written, in the form the image sweeps use (canon_vec): the edge set does not
+// depend on the bins or on which sweep built it.
+constexpr float CL_BAND = 1e-4f;
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __restrict__ info, ClWs w,
+                                                  const float* __restrict__ frac,
                                                   float c2thr, const float* __restrict__ thr,
                                                   uint32_t* __restrict__ counts,
                                                   const int64_t* __restrict__ offsets, int64_t capacity,
@@ -227,6 +233,27 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                 vr = vec ? vec + 3 * base : nullptr;
             }
             const int self = it.home + (int)(r - it.hs);   // the source's own candidate (excluded)
+            // below lo: an edge; at or above hi: none; in between the canonical form decides
+            const float lo = c2 * (1.0f - CL_BAND), hi = c2 * (1.0f + CL_BAND);
+            // the hits of a step: lanes under lo, plus (rarely) the band lanes whose
+            // canonical length is under the threshold (they take its vector and length)
+            auto decide = [&](float l2, int32_t j, int32_t ct, int cs, float& dx, float& dy, float& dz,
+                              float& l2o, bool valid) -> uint64_t {   // cs >= 0: ct is tile.ct[cs]
+                const uint64_t sure = ballot(valid && l2 < lo);
+                const uint64_t band = ballot(valid && l2 < hi) & ~sure;
+                l2o = l2;
+                if (band == 0) return sure;   // wave-uniform, the common case
+                bool hit = (sure >> lane) & 1ull;
+                if ((band >> lane) & 1ull) {
+                    if (cs >= 0) ct = tile.ct[cs];
+                    const int64_t ja = j;
+                    l2o = canon_vec(it.L, (double)S.x0, (double)S.x1, (double)S.x2, (double)frac[3 * ja],
+                                    (double)frac[3 * ja + 1], (double)frac[3 * ja + 2], unpack_t0(ct) + s0,
+                                    unpack_t1(ct) + s1, unpack_t2(ct) + s2, dx, dy, dz);
+                    hit = l2o < c2;
+                }
+                return ballot(hit);
+            };
             auto emit = [&](uint64_t m, float dx, float dy, float dz, float l2, int32_t j, int32_t ct) {
                 if (MODE == 0) {
                     cnt += (uint32_t)__popcll(m);
@@ -255,17 +282,20 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
             if (it.staged) {   // full-wave steps over the padded tile
                 for (int cb = 0; cb < T; cb += WAVE) {
                     const float4 e = tile.c[cb + lane];
-                    const float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
+                    float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
                     const float l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    const uint64_t m = ballot(l2 < c2) & ~cl_self_bit(self, cb);
-                    emit(m, dx, dy, dz, l2, __float_as_int(e.w), MODE == 1 ? tile.ct[cb + lane] : 0);
+                    const int32_t j = __float_as_int(e.w);
+                    int32_t ct = MODE == 1 ? tile.ct[cb + lane] : 0;
+                    float l2o;
+                    const uint64_t m =
+                        decide(l2, j, ct, MODE == 1 ? -1 : cb + lane, dx, dy, dz, l2o, true) & ~cl_self_bit(self, cb);
+                    emit(m, dx, dy, dz, l2o, j, ct);
                 }
             } else {
                 for (int cb = 0; cb < T; cb += WAVE) {
                     const int c = cb + lane;
                     float dx = 0.f, dy = 0.f, dz = 0.f, l2 = 0.f;
                     int32_t j = 0, ct = 0;
-                    bool hit = false;
                     if (c < T) {
                         const float4 e = cl_candidate(tile, it, w, c, ct);
                         j = __float_as_int(e.w);
@@ -273,9 +303,10 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                         dy = e.y - S.py;
                         dz = e.z - S.pz;
                         l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        hit = l2 < c2;
                     }
-                    emit(ballot(hit) & ~cl_self_bit(self, cb), dx, dy, dz, l2, j, ct);
+                    float l2o;
+                    const uint64_t m = decide(l2, j, ct, -1, dx, dy, dz, l2o, c < T) & ~cl_self_bit(self, cb);
+                    emit(m, dx, dy, dz, l2o, j, ct);
                 }
             }
             if (MODE == 0) {
@@ -293,16 +324,15 @@ hipError_t launch_cl_cutoff_sweep(int mode, int B, const StructInfo* info, const
                                   const int64_t* offsets, int64_t capacity, int32_t* src,
                                   int32_t* dst, int32_t* image, float* length, float* vec, Counters* ctr,
                                   mg_report* report, int64_t* partials, int grid, hipStream_t s) {
-    (void)frac;
     (void)src;
     (void)ctr;
     (void)report;
     if (B == 0) return hipSuccess;
     if (mode == 0)
-        hipLaunchKernelGGL((k_cl_sweep<0>), dim3(grid), dim3(256), 0, s, B, info, w, c2thr, thr, counts, offsets,
+        hipLaunchKernelGGL((k_cl_sweep<0>), dim3(grid), dim3(256), 0, s, B, info, w, frac, c2thr, thr, counts, offsets,
                            capacity, dst, image, length, vec, partials);
     else
-        hipLaunchKernelGGL((k_cl_sweep<1>), dim3(grid), dim3(256), 0, s, B, info, w, c2thr, thr, counts, offsets,
+        hipLaunchKernelGGL((k_cl_sweep<1>), dim3(grid), dim3(256), 0, s, B, info, w, frac, c2thr, thr, counts, offsets,
                            capacity, dst, image, length, vec, partials);
     return hipGetLastError();
 }

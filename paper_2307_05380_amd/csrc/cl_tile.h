@@ -2,8 +2,9 @@
 // celllist.hip, KNN selection in knn.hip). Internal, not part of the ABI.
 //
 // A work item is one home bin of a cell-list structure. Its workgroup stages
-// the atoms of the 27 bins around it (the periodic stencil that holds every
-// neighbour within the bin thickness) once in LDS, as positions relative to
+// the atoms of the (2S+1)^3 bins around it (S = 1: 27 bins, S = 2: 125 bins;
+// the periodic stencil that holds every neighbour within S bin thicknesses)
+// once in LDS, as positions relative to
 // the home bin's origin, and then every source atom of the home bin is swept
 // against the staged candidates by one wave, lane = candidate. Staged
 // position of atom j in a stencil bin with periodic wrap u:
@@ -11,9 +12,9 @@
 // o the home bin's fractional origin; the source's own position p_i is the same
 // expression with u = 0, so d = c_j - p_i is the edge vector with t = u -
 // floor(x_j) + floor(x_i), and every FP32 quantity is a rounding of an FP64
-// value a few bin widths long. Candidates are in stencil order (27 bins in a
-// fixed order, each bin's atoms by ascending index), so the edges of a source
-// come out in a deterministic order.
+// value a few bin widths long. Candidates are in stencil order (the stencil's
+// bins in a fixed order, each bin's atoms by ascending index), so the edges of
+// a source come out in a deterministic order.
 #pragma once
 
 #include "mg_internal.h"
@@ -21,13 +22,15 @@
 namespace mg {
 
 constexpr int CL_TILE = 1024;   // candidates staged per item; larger stencils are read from global memory
+constexpr int CL_NB_MAX = 125;  // stencil bins at most (half-width 2)
 
 struct ClTile {
-    float4 c[CL_TILE];     // staged position (x, y, z) and the atom index (bits of w)
-    int32_t ct[CL_TILE];   // packed u - floor(x_j), biased 10-bit fields
-    int64_t nb_start[27];  // first slot of every stencil bin
-    int32_t nb_cum[28];    // exclusive prefix of the stencil bins' atom counts; nb_cum[27] = total
-    int32_t nb_u[27];      // packed wrap u of every stencil bin
+    float4 c[CL_TILE];            // staged position (x, y, z) and the atom index (bits of w)
+    int32_t ct[CL_TILE];          // packed u - floor(x_j), biased 10-bit fields
+    int64_t nb_start[CL_NB_MAX];  // first slot of every stencil bin
+    int32_t nb_cum[CL_NB_MAX + 1];   // exclusive prefix of the stencil bins' atom counts; nb_cum[nb] = total
+    int32_t nb_u[CL_NB_MAX];      // packed wrap u of every stencil bin
+    int32_t wsum;                 // atom count of the first 64 stencil bins (the scan's carry)
 };
 
 struct ClItem {
@@ -36,7 +39,8 @@ struct ClItem {
     double o[3];       // fractional origin of the home bin
     int64_t hs, he;    // slot range of the home bin (its atoms are the item's sources)
     int32_t total;     // candidates in the stencil
-    int32_t home;      // candidate index of the home bin's first atom (stencil bin 13, wrap 0)
+    int32_t home;      // candidate index of the home bin's first atom (the stencil's centre bin, wrap 0)
+    int32_t nb;        // stencil bins, (2S+1)^3
     bool staged;       // total <= CL_TILE: the candidates are in the tile
 };
 
@@ -61,9 +65,9 @@ __device__ __forceinline__ float4 cl_rel(const double* L, const double* o, const
                        (float)(f0 * L[2] + f1 * L[5] + f2 * L[8]), x.w);
 }
 
-// Stencil bin of concatenated candidate index c: the largest d with nb_cum[d] <= c.
-__device__ __forceinline__ int cl_bin_of(const ClTile& tile, int c) {
-    int lo = 0, hi = 27;
+// Stencil bin of concatenated candidate index c: the largest d < nb with nb_cum[d] <= c.
+__device__ __forceinline__ int cl_bin_of(const ClTile& tile, int nb, int c) {
+    int lo = 0, hi = nb;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (tile.nb_cum[mid] <= c) lo = mid;
@@ -80,7 +84,7 @@ __device__ __forceinline__ float4 cl_candidate(const ClTile& tile, const ClItem&
         ct = tile.ct[c];
         return tile.c[c];
     }
-    const int d = cl_bin_of(tile, c);
+    const int d = cl_bin_of(tile, it.nb, c);
     const int64_t p = tile.nb_start[d] + (c - tile.nb_cum[d]);
     const int32_t u = tile.nb_u[d];
     return cl_rel(it.L, it.o, w.slot_x[p], w.slot_shift[p], unpack_t0(u), unpack_t1(u), unpack_t2(u), ct);
@@ -135,30 +139,39 @@ __device__ __forceinline__ void cl_stage(int64_t q, int B, const StructInfo* __r
     const int64_t* bst = w.bin_start + si->bin_off;
     it.hs = bst[lb];
     it.he = bst[lb + 1];
+    // stencil bin t = (d0, d1, d2) offsets in [-S, S], d2 fastest; m_k >= 2S + 1, so one
+    // periodic wrap u in {-1, 0, 1} per direction reaches every stencil bin
+    const int S = si->cl_s, W = 2 * S + 1, NB = W * W * W;
     const int t = threadIdx.x;
-    if (t < 64) {
-        int cnt = 0;
-        if (t < 27) {
-            int n0 = b0 + t / 9 - 1, n1 = b1 + (t / 3) % 3 - 1, n2 = b2 + t % 3 - 1;
+    int cnt = 0, inc = 0;
+    if (t < 2 * WAVE) {
+        if (t < NB) {
+            int n0 = b0 + t / (W * W) - S, n1 = b1 + (t / W) % W - S, n2 = b2 + t % W - S;
             const int u0 = n0 < 0 ? -1 : (n0 >= m0 ? 1 : 0);
             const int u1 = n1 < 0 ? -1 : (n1 >= m1 ? 1 : 0);
             const int u2 = n2 < 0 ? -1 : (n2 >= m2 ? 1 : 0);
             n0 -= u0 * m0;
             n1 -= u1 * m1;
             n2 -= u2 * m2;
-            const int nb = (n0 * m1 + n1) * m2 + n2;
-            const int64_t s0 = bst[nb];
-            cnt = (int)(bst[nb + 1] - s0);
+            const int nbin = (n0 * m1 + n1) * m2 + n2;
+            const int64_t s0 = bst[nbin];
+            cnt = (int)(bst[nbin + 1] - s0);
             tile.nb_start[t] = s0;
             tile.nb_u[t] = pack_t(u0, u1, u2);
         }
-        const int inc = wave_incl_scan_i32(cnt);
-        if (t < 27) tile.nb_cum[t] = inc - cnt;
-        if (t == 26) tile.nb_cum[27] = inc;
+        inc = wave_incl_scan_i32(cnt);
+        if (t == WAVE - 1) tile.wsum = inc;
     }
     __syncthreads();
-    it.total = tile.nb_cum[27];
-    it.home = tile.nb_cum[13];
+    if (t < NB) {
+        const int carry = t >= WAVE ? tile.wsum : 0;
+        tile.nb_cum[t] = carry + inc - cnt;
+        if (t == NB - 1) tile.nb_cum[NB] = carry + inc;
+    }
+    __syncthreads();
+    it.nb = NB;
+    it.total = tile.nb_cum[NB];
+    it.home = tile.nb_cum[NB / 2];
     it.staged = it.total <= CL_TILE;
     if (it.staged) {
         // the tile is filled up to a multiple of the wave width with entries no
@@ -166,7 +179,7 @@ __device__ __forceinline__ void cl_stage(int64_t q, int B, const StructInfo* __r
         const int padded = (it.total + WAVE - 1) / WAVE * WAVE;
         for (int c = t; c < padded; c += blockDim.x) {
             if (c < it.total) {
-                const int d = cl_bin_of(tile, c);
+                const int d = cl_bin_of(tile, NB, c);
                 const int64_t p = tile.nb_start[d] + (c - tile.nb_cum[d]);
                 const int32_t u = tile.nb_u[d];
                 int32_t ct;

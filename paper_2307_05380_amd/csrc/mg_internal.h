@@ -59,6 +59,8 @@ struct alignas(16) StructInfo {
     double Gm[6];
     double rGd[3];      // 1 / G_kk
     double rD2[3];      // 1 / det of the 2x2 blocks of G on the index pairs (1,2), (0,2), (0,1)
+    int32_t cl_s;       // cell lists: stencil half-width S in bins ((2S+1)^3 bins, each >= R / S thick)
+    int32_t pad1;
 };
 
 constexpr int CL_MIN_ATOMS = 512;   // structures smaller than this use the image sweep
@@ -190,11 +192,15 @@ __device__ __forceinline__ void cart64(const double* L, double f0, double f1, do
     z = f0 * L[2] + f1 * L[5] + f2 * L[8];
 }
 
-// Squared KNN key distance of candidate (j, t) of source i (x_i, x_j raw
-// fractional coordinates, t the edge's image): pair offset plus image shift
-// as above, summed in FP32.
-__device__ __forceinline__ float knn_l2(const double* L, double xi0, double xi1, double xi2, double xj0, double xj1,
-                                        double xj2, int t0, int t1, int t2) {
+// FP32 vector and squared length of candidate (j, t) of source i in the form
+// the image sweeps compute them (x_i, x_j raw fractional coordinates, t the
+// edge's image): pair offset plus image shift as above, summed in FP32. The
+// KNN keys of every path use it, and the cell-list cutoff sweep decides with
+// it wherever its own staged distance lies near the threshold, so a graph does
+// not depend on the path or bin size that built it.
+__device__ __forceinline__ float canon_vec(const double* L, double xi0, double xi1, double xi2, double xj0,
+                                           double xj1, double xj2, int t0, int t1, int t2, float& dx, float& dy,
+                                           float& dz) {
     double d0 = xj0 - xi0, d1 = xj1 - xi1, d2 = xj2 - xi2;
     const double w0 = rint(d0), w1 = rint(d1), w2 = rint(d2);
     d0 -= w0;
@@ -203,8 +209,17 @@ __device__ __forceinline__ float knn_l2(const double* L, double xi0, double xi1,
     double px, py, pz, sx, sy, sz;
     cart64(L, d0, d1, d2, px, py, pz);
     cart64(L, (double)(t0 + (int)w0), (double)(t1 + (int)w1), (double)(t2 + (int)w2), sx, sy, sz);
-    const float dx = (float)px + (float)sx, dy = (float)py + (float)sy, dz = (float)pz + (float)sz;
+    dx = (float)px + (float)sx;
+    dy = (float)py + (float)sy;
+    dz = (float)pz + (float)sz;
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+// Squared KNN key distance of candidate (j, t) of source i (canon_vec's length).
+__device__ __forceinline__ float knn_l2(const double* L, double xi0, double xi1, double xi2, double xj0, double xj1,
+                                        double xj2, int t0, int t1, int t2) {
+    float dx, dy, dz;
+    return canon_vec(L, xi0, xi1, xi2, xj0, xj1, xj2, t0, t1, t2, dx, dy, dz);
 }
 
 // Orders this wave's LDS writes before its later LDS reads (lanes exchange data
@@ -261,10 +276,12 @@ namespace mg {
 
 // radii (nullable, cutoff mode only): per-atom cutoffs; then thr[a] receives
 // the per-atom threshold on l^2 and the structure's radius is its largest c_a.
+// cl_span: cell-list stencil half-width in bins (1: 27 bins at least the radius
+// thick; 2: 125 bins at least half the radius thick, where they fit).
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
                          int64_t N, float radius, const float* radii, float* thr, int knn_k,
                          float knn_lambda, StructInfo* info, PlanRow* plan, Counters* ctr, mg_report* report, int mode,
-                         int opts, hipStream_t s);
+                         int opts, int cl_span, hipStream_t s);
 hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t chunk_cap, int64_t* item_off,
                               int64_t* cl_off,
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,

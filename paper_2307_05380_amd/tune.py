@@ -11,12 +11,18 @@ Tunables (``mg_tuning`` in include/matgraph.h):
                      the first KNN search radius is sized for (for cell-list
                      structures it also sets the bin thickness);
 - knn_tau_x8:        8x the factor on the uniform-density k-th neighbour
-                     distance of the first KNN threshold.
+                     distance of the first KNN threshold;
+- cutoff_cl_span,
+  knn_cl_span:       cell-list stencil half-width in bins (1: 27 bins at least
+                     the radius thick; 2: 125 bins at least half of it), tried
+                     only when the batch has cell-list structures.
 
 Every candidate is timed with device events over repeated calls and must give
 the same graph as the first candidate: the KNN edges bit for bit, the cutoff
 edges as a set (the order of a source's edges may depend on the tile shape) with
-identical per-source counts; the fastest is kept. Results are
+identical per-source counts and lengths within 2e-5 A (cell-list tiles round
+their staged positions relative to the bin, so a length's last bits may depend
+on the bin size); the fastest is kept. Results are
 cached as JSON keyed by GPU architecture and workload signature
 (``MG_TUNE_CACHE`` or ``~/.cache/matgraph/tune.json``).
 """
@@ -34,6 +40,9 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "matgraph", "tun
 
 CUTOFF_SPACE = {"cutoff_wgs_per_cu": [8, 16, 32, 64], "cutoff_slots": [1, 2, 4], "cutoff_img_group": [2, 4, 8]}
 KNN_SPACE = {"knn_wgs_per_cu": [2, 4, 8, 16], "knn_lambda_x4": [4, 6, 8, 12], "knn_tau_x8": [9, 10, 12, 16]}
+# added when the batch has structures that take cell lists
+CL_SPAN_CUTOFF = {"cutoff_cl_span": [1, 2]}
+CL_SPAN_KNN = {"knn_cl_span": [1, 2]}
 
 
 def _arch(device) -> str:
@@ -70,13 +79,14 @@ def _mix(x: torch.Tensor) -> torch.Tensor:
 
 
 def _cutoff_signature(b, count):
-    """Per-source edge counts plus an order-independent checksum of the edges."""
+    """Per-source edge counts, the edges' identities (src, dst, image) as a sorted
+    hash list and their lengths in that order (compared within a tolerance)."""
     E = int(count)
     h = _mix(b.src[:E].long() * 1000003 + b.dst[:E].long())
     for c in range(3):
         h = _mix(h + b.image[:E, c].long() + 7 * (c + 1))
-    h = _mix(h + b.length[:E].view(torch.int32).long())
-    return [b.row_ptr.clone(), h.sum().view(1)]
+    hs, order = torch.sort(h)
+    return [b.row_ptr.clone(), hs, b.length[:E][order].clone()]
 
 
 def _knn_signature(b):
@@ -85,6 +95,11 @@ def _knn_signature(b):
 
 def _same(a, b):
     return all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+def _same_cutoff(a, b, tol: float = 2e-5):
+    return (torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+            and (a[2].numel() == 0 or float((a[2] - b[2]).abs().max()) <= tol))
 
 
 def _clean(rep) -> bool:
@@ -97,9 +112,10 @@ def tune(lattices, frac, batch_ptr, cutoff: float, k: int, reps: int = 5, space_
     B, N = int(lattices.shape[0]), int(frac.shape[0])
     dev = frac.device
     base = _lib.get_tuning()
-    space_cutoff = space_cutoff or CUTOFF_SPACE
     opts = graph.auto_opts(batch_ptr, None)
-    space_knn = space_knn or KNN_SPACE
+    big = bool((batch_ptr[1:] - batch_ptr[:-1] >= graph.CL_MIN_ATOMS).any())
+    space_cutoff = space_cutoff or dict(CUTOFF_SPACE, **(CL_SPAN_CUTOFF if big else {}))
+    space_knn = space_knn or dict(KNN_SPACE, **(CL_SPAN_KNN if big else {}))
     g = graph.cutoff_graph(lattices, frac, batch_ptr, cutoff, opts=opts)
     E, icap = g.num_edges, g.report.images_needed
     del g
@@ -120,7 +136,7 @@ def tune(lattices, frac, batch_ptr, cutoff: float, k: int, reps: int = 5, space_
         snap = _cutoff_signature(cb, E)
         if ref is None:
             ref = snap
-        ok = _same(ref, snap) and _clean(cb.report())
+        ok = _same_cutoff(ref, snap) and _clean(cb.report())
         results["cutoff"].append((ms, cfg, ok))
         if verbose:
             print("cutoff", cfg, f"{ms:.4f} ms", "ok" if ok else "MISMATCH", flush=True)

@@ -22,9 +22,25 @@ def supercells():
     return inputs.make_config5(B=2, m_lo=8, m_hi=9)
 
 
-def test_supercell_cutoff_cell_lists(supercells):
+class _span:
+    """Cell-list stencil half-width for the calls inside the block (1: 27 bins, 2: 125 bins)."""
+
+    def __init__(self, span):
+        self.span = span
+
+    def __enter__(self):
+        self.saved = _lib.get_tuning()
+        _lib.set_tuning(**dict(self.saved, cutoff_cl_span=self.span, knn_cl_span=self.span))
+
+    def __exit__(self, *a):
+        _lib.set_tuning(**self.saved)
+
+
+@pytest.mark.parametrize("span", [1, 2])
+def test_supercell_cutoff_cell_lists(supercells, span):
     b = supercells
-    g = gu.cutoff(b)
+    with _span(span):
+        g = gu.cutoff(b)
     assert g.report.flags == 0, g.report.flag_names()
     s, d, t, ln = gu.np_graph(g)
     for q in range(b.B):
@@ -35,9 +51,11 @@ def test_supercell_cutoff_cell_lists(supercells):
     assert np.array_equal(np.repeat(np.arange(b.N), np.diff(rp)), s)
 
 
-def test_supercell_knn_cell_lists(supercells):
+@pytest.mark.parametrize("span", [1, 2])
+def test_supercell_knn_cell_lists(supercells, span):
     b = supercells
-    g = gu.knn(b, k=32)
+    with _span(span):
+        g = gu.knn(b, k=32)
     assert g.report.flags & ~_lib.MG_FLAG_KNN_EXTENDED == 0, g.report.flag_names()
     s, d, t, ln = gu.np_graph(g)
     for q in range(b.B):
@@ -46,39 +64,58 @@ def test_supercell_knn_cell_lists(supercells):
     print(g.report)
 
 
+def test_stencil_spans_same_graph(supercells):
+    """27-bin and 125-bin stencils build the same cutoff edge set (lengths
+    within the length tolerance: the staged positions are rounded relative to
+    bins of another size) and bit-identical KNN graphs."""
+    b = supercells
+    out = {}
+    for span in (1, 2):
+        with _span(span):
+            out[span] = (gu.np_graph(gu.cutoff(b)), gu.np_graph(gu.knn(b, k=32)))
+    (c1, k1), (c2, k2) = out[1], out[2]
+    for x, y in zip(k1, k2):
+        assert np.array_equal(x, y)
+
+    def keyed(e):
+        s, d, t, ln = e
+        return dict(zip(zip(s.tolist(), d.tolist(), map(tuple, t.tolist())), ln.tolist()))
+    a, c = keyed(c1), keyed(c2)
+    assert a.keys() == c.keys()
+    assert max(abs(a[q] - c[q]) for q in a) <= compare.LEN_TOL
+
+
 def _large_cells(seed, B=6):
     rng = np.random.default_rng(seed)
     return inputs.random_batch(rng, B, 40, 220, 15.0, 26.0, 60.0, 120.0, cutoff=5.0, k=12)
 
 
-def test_forced_cell_lists_match_image_sweep():
+@pytest.mark.parametrize("span", [1, 2])
+def test_forced_cell_lists_match_image_sweep(span):
     """The same batch through cell lists (forced) and through the image sweep:
-    both agree with the oracle, and with each other as edge sets except for
-    edges whose FP64 length lies inside the 1e-4 A band of the cutoff (the two
-    paths round the vectors differently); the lengths of common edges agree to
-    twice the length tolerance."""
-    import oracle
+    both agree with the oracle and give the same edge set, the band of the
+    cutoff included (the cell-list sweep decides candidates near the threshold
+    in the image sweep's arithmetic); the lengths of common edges agree to twice
+    the length tolerance, and the KNN graphs bit for bit."""
     b = _large_cells(3)
-    gc = gu.cutoff(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    with _span(span):
+        gc = gu.cutoff(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+        kc_ = gu.knn(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
     gi = gu.cutoff(b, opts=_lib.MG_OPT_CELL_LIST_OFF)
     ec, ei = gu.np_graph(gc), gu.np_graph(gi)
     compare.cutoff_check(b, *ec)
     compare.cutoff_check(b, *ei)
+
     def keyed(e):
         s, d, t, ln = e
         return {(int(a), int(c), int(x), int(y), int(z)): float(l) for a, c, (x, y, z), l in zip(s, d, t, ln)}
     kc, ki = keyed(ec), keyed(ei)
-    only = [k for k in set(kc) ^ set(ki)]
-    if only:
-        a = np.array(only, np.int64)
-        _, l64 = oracle.edge_geometry64(b.lattices, b.frac, b.batch_ptr, a[:, 0], a[:, 1], a[:, 2:])
-        assert (np.abs(l64 - b.cutoff) <= compare.BAND).all(), f"paths differ outside the band: {only[:3]}"
-    common = set(kc) & set(ki)
-    assert max(abs(kc[k] - ki[k]) for k in common) <= 2 * compare.LEN_TOL
-    kc_ = gu.knn(b, opts=_lib.MG_OPT_CELL_LIST_FORCE)
+    assert set(kc) == set(ki), f"paths differ: {sorted(set(kc) ^ set(ki))[:3]}"
+    assert max(abs(kc[k] - ki[k]) for k in kc) <= 2 * compare.LEN_TOL
     ki_ = gu.knn(b, opts=_lib.MG_OPT_CELL_LIST_OFF)
     compare.knn_check(b, b.k, *gu.np_graph(kc_))
-    compare.knn_check(b, b.k, *gu.np_graph(ki_))
+    for x, y in zip(gu.np_graph(kc_), gu.np_graph(ki_)):
+        assert np.array_equal(x, y)
 
 
 def test_cell_lists_wrapped_coordinates():

@@ -41,3 +41,20 @@ def test_tune_and_cache(tmp_path, monkeypatch):
         assert ga == gr
     finally:
         _lib.set_tuning(**base)
+
+
+def test_tune_cell_list_spans():
+    """With cell-list structures in the batch the stencil half-widths join the
+    search; every candidate (27- or 125-bin stencils) gives the same graph."""
+    b = inputs.make_config5(B=2, m_lo=8, m_hi=8)
+    L, X, P = gu.dev(b)
+    base = _lib.get_tuning()
+    try:
+        best = tune.tune(L, X, P, b.cutoff, b.k, reps=1,
+                         space_cutoff={"cutoff_wgs_per_cu": [32], **tune.CL_SPAN_CUTOFF},
+                         space_knn={"knn_wgs_per_cu": [8], **tune.CL_SPAN_KNN})
+        assert set(best["cutoff"]) == {"cutoff_wgs_per_cu", "cutoff_cl_span"}
+        assert set(best["knn"]) == {"knn_wgs_per_cu", "knn_cl_span"}
+        assert len(best["all"]["cutoff"]) == 2 and len(best["all"]["knn"]) == 2
+    finally:
+        _lib.set_tuning(**base)
