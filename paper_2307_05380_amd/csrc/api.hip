@@ -422,8 +422,8 @@ mg_status cutoff_graph(const float* lattices, const float* frac, const int64_t* 
     const int grid = sweep_grid(tu.cutoff_wgs_per_cu);
     const bool sum = B > 0 && N > 0;
     hipError_t e;
-    if ((e = mg::launch_zero_report(report, w.ctr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
     const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
+    // (the plan kernel starts the report and the workspace counters)
     if ((e = phase("cutoff.bounds", s, [&] {
              return mg::launch_bounds(lattices, batch_ptr, frac, B, N, cutoff, radii, thr, 0, 0.f, w.info,
                                       w.plan, w.ctr, report, 0, opts, tu.cutoff_cl_span, s);
@@ -549,15 +549,16 @@ mg_status mg_knn_graph(const float* lattices, const float* frac, const int64_t* 
     const int grid = sweep_grid(tu.knn_wgs_per_cu);
     const bool sum = B > 0 && N > 0;
     hipError_t e;
-    if ((e = mg::launch_zero_report(report, w.ctr, N * (int64_t)k, s)) != hipSuccess) return hip_fail(e, "zero");
     const bool cl = !(opts & MG_OPT_CELL_LIST_OFF);
+    // (the plan kernel starts the report, num_edges = N k, and the workspace counters)
     if ((e = phase("knn.bounds", s, [&] {
              return mg::launch_bounds(lattices, batch_ptr, frac, B, N, 0.f, nullptr, nullptr, k, lambda,
                                       w.info, w.plan, w.ctr, report, 1, opts, tu.knn_cl_span, s);
          })) != hipSuccess)
         return hip_fail(e, "bounds");
     if ((e = phase("knn.plan", s, [&] {
-             return mg::launch_struct_scan(B, w.info, w.plan, 0, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s);
+             return mg::launch_struct_scan(B, w.info, w.plan, 0, w.item_off, w.cl.cl_off, w.box_off, w.ctr, report, w.img.cap, s,
+                                           N * (int64_t)k);
          })) != hipSuccess)
         return hip_fail(e, "plan");
     if ((e = phase("knn.images", s, [&] { return mg::launch_images(B, w.info, w.box_off, w.ctr, w.img, s); })) !=
@@ -627,7 +628,7 @@ mg_status mg_images_needed(const float* lattices, const float* frac, const int64
         ctr = w.ctr, info = w.info, plan = w.plan, item_off = w.item_off, cl_off = w.cl.cl_off, box_off = w.box_off;
     }
     const float lambda = (tu.knn_lambda_x4 > 0 ? tu.knn_lambda_x4 : 6) / 4.0f;
-    if ((e = mg::launch_zero_report(report, ctr, 0, s)) != hipSuccess) return hip_fail(e, "zero");
+    // (the plan kernel starts the report and the workspace counters)
     if ((e = mg::launch_bounds(lattices, batch_ptr, frac, B, N, k == 0 ? (radii ? 1.0f : cutoff) : 0.f,
                                k == 0 ? radii : nullptr, thr, k, lambda, info, plan, ctr, report, k == 0 ? 0 : 1,
                                opts, k == 0 ? tu.cutoff_cl_span : tu.knn_cl_span, s)) != hipSuccess)

@@ -282,8 +282,7 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ lattic
     info[b] = si;
     const int64_t per = (n <= WAVE) ? (int64_t)min(si.G, n) : 1;   // sources of one group
     const int64_t cost = (si.box > 0 && si.groups > 0) ? per * n * si.box : 0;
-    plan[b] = PlanRow{(int32_t)si.box, si.groups, (int32_t)si.cl_items, (int32_t)si.nbins, cost, n, 0};
-    if (flags) atomicOr(&rep->flags, flags);
+    plan[b] = PlanRow{(int32_t)si.box, si.groups, (int32_t)si.cl_items, (int32_t)si.nbins, cost, n, flags};
 }
 
 hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const float* frac, int B,
@@ -332,14 +331,17 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
                                                       int64_t* __restrict__ box_off,
                                                       Counters* __restrict__ ctr,
                                                       mg_report* __restrict__ rep,
-                                                      int64_t capacity) {
+                                                      int64_t capacity, int64_t num_edges0) {
     __shared__ int64_t s_part[SCAN_Q][16];
+    __shared__ uint32_t s_flags;
     __shared__ int64_t s_base[SCAN_Q];
     __shared__ int64_t s_red[16];
     __shared__ double s_redf[16];
     __shared__ int64_t s_target;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     if (t < SCAN_Q) s_base[t] = 0;
+    if (t == 0) s_flags = 0u;
+    uint32_t fl = 0u;   // this thread's structures' flags
     // chunk target: total cost, then doubled until the count slots fit
     int64_t target = 0;
     if (chunk_cap > 0) {
@@ -382,6 +384,7 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
             const int b = base + t * SCAN_PER + u;
             const bool in = b < B;
             const PlanRow pr = plan[in ? b : 0];   // four consecutive rows per thread: coalesced
+            fl |= in ? pr.flags : 0u;
             ch[u] = (in && chunk_cap > 0) ? plan_chunks(pr, target) : 1;
             v[u][0] = in ? pr.box : 0;
             v[u][1] = in ? (int64_t)pr.groups * ch[u] : 0;
@@ -433,7 +436,13 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
         }
         __syncthreads();
     }
-    if (overflow) atomicOr(&rep->flags, (uint32_t)MG_FLAG_IMAGES);
+    // the call's report and counters start here (the kernels after this one add to them)
+    if (overflow) fl |= (uint32_t)MG_FLAG_IMAGES;
+    if (fl) atomicOr(&s_flags, fl);
+    __syncthreads();
+    if (t < (int)(sizeof(Counters) / 4)) reinterpret_cast<uint32_t*>(ctr)[t] = 0u;
+    if (t >= 64 && t < 64 + (int)(sizeof(mg_report) / 4)) reinterpret_cast<uint32_t*>(rep)[t - 64] = 0u;
+    __syncthreads();
     if (t == 0) {
         item_off[B] = s_base[1];
         if (cl_off) cl_off[B] = s_base[2];
@@ -442,7 +451,9 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
         ctr->total_items = s_base[1];
         ctr->total_cl_items = s_base[2];
         ctr->total_bins = s_base[3];
+        rep->num_edges = num_edges0;
         rep->images_needed = s_base[0];
+        rep->flags = s_flags;
     }
 }
 
@@ -451,9 +462,9 @@ __global__ __launch_bounds__(1024) void k_struct_scan(int B, StructInfo* __restr
 hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t chunk_cap, int64_t* item_off,
                               int64_t* cl_off,
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
-                              hipStream_t s) {
+                              hipStream_t s, int64_t num_edges0) {
     hipLaunchKernelGGL(k_struct_scan, dim3(1), dim3(1024), 0, s, B, info, plan, chunk_cap, item_off, cl_off, box_off, ctr,
-                       report, image_capacity);
+                       report, image_capacity, num_edges0);
     return hipGetLastError();
 }
 

@@ -74,7 +74,7 @@ struct alignas(16) PlanRow {
     int32_t nbins;
     int64_t cost;       // candidates of one source group over the whole box (0: no image sweep)
     int32_t n;
-    int32_t pad;
+    uint32_t flags;     // StructInfo::flags (the plan kernel ORs them into the report)
 };
 
 // Image chunks: a structure whose source groups are heavy gets its image table
@@ -282,10 +282,13 @@ hipError_t launch_bounds(const float* lattices, const int64_t* batch_ptr, const 
                          int64_t N, float radius, const float* radii, float* thr, int knn_k,
                          float knn_lambda, StructInfo* info, PlanRow* plan, Counters* ctr, mg_report* report, int mode,
                          int opts, int cl_span, hipStream_t s);
+// Also starts the call's report (num_edges = num_edges0, images_needed, the
+// structures' flags, every other field 0) and zeroes the workspace counters:
+// no kernel before it may write either.
 hipError_t launch_struct_scan(int B, StructInfo* info, const PlanRow* plan, int64_t chunk_cap, int64_t* item_off,
                               int64_t* cl_off,
                               int64_t* box_off, Counters* ctr, mg_report* report, int64_t image_capacity,
-                              hipStream_t s);
+                              hipStream_t s, int64_t num_edges0 = 0);
 struct ClWs {
     int64_t* cl_off;        // [B+1] scan of cell-list items (one item per bin)
     uint32_t* bin_count;    // [cap] atoms per bin
