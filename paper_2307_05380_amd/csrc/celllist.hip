@@ -279,17 +279,24 @@ __global__ __launch_bounds__(256) void k_cl_sweep(int B, const StructInfo* __res
                     run += (uint32_t)__popcll(m);
                 }
             };
-            if (it.staged) {   // full-wave steps over the padded tile
-                for (int cb = 0; cb < T; cb += WAVE) {
-                    const float4 e = tile.c[cb + lane];
+            if (it.staged) {   // full-wave steps over the padded tile, two per trip
+                auto step = [&](int cb, const float4 e, int32_t ct) {
                     float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
                     const float l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     const int32_t j = __float_as_int(e.w);
-                    int32_t ct = MODE == 1 ? tile.ct[cb + lane] : 0;
                     float l2o;
                     const uint64_t m =
                         decide(l2, j, ct, MODE == 1 ? -1 : cb + lane, dx, dy, dz, l2o, true) & ~cl_self_bit(self, cb);
                     emit(m, dx, dy, dz, l2o, j, ct);
+                };
+                // both steps' candidates are read before the first is used (the
+                // tile is padded to whole pairs of steps): one LDS wait per trip
+                for (int cb = 0; cb < T; cb += 2 * WAVE) {
+                    const float4 e0 = tile.c[cb + lane], e1 = tile.c[cb + WAVE + lane];
+                    const int32_t c0 = MODE == 1 ? tile.ct[cb + lane] : 0;
+                    const int32_t c1 = MODE == 1 ? tile.ct[cb + WAVE + lane] : 0;
+                    step(cb, e0, c0);
+                    if (cb + WAVE < T) step(cb + WAVE, e1, c1);   // uniform
                 }
             } else {
                 for (int cb = 0; cb < T; cb += WAVE) {

@@ -21,7 +21,7 @@
 
 namespace mg {
 
-constexpr int CL_TILE = 1024;   // candidates staged per item; larger stencils are read from global memory
+constexpr int CL_TILE = 1024;   // candidates staged per item (a multiple of 128); larger stencils are read from global memory
 constexpr int CL_NB_MAX = 125;  // stencil bins at most (half-width 2)
 
 struct ClTile {
@@ -174,9 +174,10 @@ __device__ __forceinline__ void cl_stage(int64_t q, int B, const StructInfo* __r
     it.home = tile.nb_cum[NB / 2];
     it.staged = it.total <= CL_TILE;
     if (it.staged) {
-        // the tile is filled up to a multiple of the wave width with entries no
-        // threshold accepts (infinite distance), so full-wave steps need no bounds test
-        const int padded = (it.total + WAVE - 1) / WAVE * WAVE;
+        // the tile is filled up to a multiple of two wave widths with entries no
+        // threshold accepts (infinite distance), so full-wave steps (read in pairs)
+        // need no bounds test; CL_TILE is a multiple of 128
+        const int padded = (it.total + 2 * WAVE - 1) / (2 * WAVE) * (2 * WAVE);
         for (int c = t; c < padded; c += blockDim.x) {
             if (c < it.total) {
                 const int d = cl_bin_of(tile, NB, c);

@@ -316,11 +316,12 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
 
 // The k smallest of the cnt keys in buf (cnt uniform, k <= cnt): returns the
 // rank of this lane's key (k or more: no key for this lane) and the key. Up to
-// 64 keys every lane ranks its own key against the others (the keys are
+// 32 keys every lane ranks its own key against the others (the keys are
 // distinct, their ordinals are): cnt broadcasts and compares instead of a
-// sorting network's dependent cross-lane exchanges; more keys are sorted.
+// sorting network's dependent cross-lane exchanges; more keys are sorted (with
+// 33-64 keys the 21-stage network measured faster than 33-64 broadcasts).
 __device__ __forceinline__ int ranked_key(const uint64_t* buf, int cnt, int k, int lane, uint64_t& key) {
-    if (cnt <= WAVE) {
+    if (cnt <= WAVE / 2) {
         key = lane < cnt ? buf[lane] : ~0ull;
         int rank = 0;
         for (int q = 0; q < cnt; ++q) rank += readlane_u64(key, q) < key ? 1 : 0;
@@ -488,18 +489,16 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
             int overflow = n >= 131072 ? 1 : 0;   // local dst index must fit 17 bits
             for (int attempt = 0; attempt < 2; ++attempt) {
                 Stack st{0, tau};
-                for (int cb = 0; cb < T; cb += WAVE) {
-                    const int c = cb + lane;
+                // candidate c with staged (or recomputed) position e: pre-filter with a
+                // margin far above the two forms' difference, then the key distance
+                auto consider = [&](int c, const float4 e, int32_t ct, bool valid) {
                     bool pass = false;
                     float l2 = 0.0f;
                     uint32_t ord = 0;
-                    if (it.staged || c < T) {   // the staged tile is padded to whole waves
-                        int32_t ct = 0;
-                        const float4 e = it.staged ? tile.c[c] : cl_candidate(tile, it, w, c, ct);
+                    if (valid) {
                         const int32_t j = __float_as_int(e.w);
                         const float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
                         l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        // pre-filter with a margin far above the two forms' difference
                         pass = l2 < st.tau2 * (1.0f + 1e-4f) && c != self;
                         if (pass) {
                             if (it.staged) ct = tile.ct[c];
@@ -515,6 +514,20 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                         }
                     }
                     stack_push<KNN_CL_CAP>(st, pass, l2, ord, k, buf, lane);
+                };
+                if (it.staged) {   // the tile is padded to whole pairs of steps: both read first
+                    for (int cb = 0; cb < T; cb += 2 * WAVE) {
+                        const float4 e0 = tile.c[cb + lane], e1 = tile.c[cb + WAVE + lane];
+                        consider(cb + lane, e0, 0, true);
+                        if (cb + WAVE < T) consider(cb + WAVE + lane, e1, 0, true);   // uniform
+                    }
+                } else {
+                    for (int cb = 0; cb < T; cb += WAVE) {
+                        const int c = cb + lane;
+                        int32_t ct = 0;
+                        const float4 e = c < T ? cl_candidate(tile, it, w, c, ct) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        consider(c, e, ct, c < T);
+                    }
                 }
                 wave_lds_sync();
                 wave_cand += T;
