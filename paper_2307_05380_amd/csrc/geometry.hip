@@ -145,8 +145,13 @@ __device__ __forceinline__ int run_start(uint64_t heads, int lane) {
     return 63 - __builtin_clzll(heads & upto);
 }
 
+// key of the lane below (lane 0: its own), by a DPP wave shift
+__device__ __forceinline__ int32_t key_below(int32_t key) {
+    return __builtin_amdgcn_update_dpp(key, key, 0x138, 0xf, 0xf, false);   // wave_shr:1
+}
+
 __device__ __forceinline__ uint64_t run_heads(int32_t key, int lane) {
-    const int32_t prev = __shfl_up(key, 1, WAVE);
+    const int32_t prev = key_below(key);
     return ballot(lane == 0 || prev != key);
 }
 
@@ -162,6 +167,27 @@ __device__ __forceinline__ T seg_scan(T v, int rs, int lane) {
         const T y = __shfl_up(v, d, WAVE);
         if (lane - d >= rs) v += y;
     }
+    return v;
+}
+
+// The same for floats with DPP (VALU only): row shifts inside rows of 16
+// lanes, then the last lane of the row below (row_bcast:15) and lane 31
+// (row_bcast:31), each added where it lies inside this lane's run.
+template <>
+__device__ __forceinline__ float seg_scan<float>(float v, int rs, int lane) {
+    float y;
+    y = dpp_f32<0x111, 0xf>(v);
+    v += lane - 1 >= rs ? y : 0.0f;
+    y = dpp_f32<0x112, 0xf>(v);
+    v += lane - 2 >= rs ? y : 0.0f;
+    y = dpp_f32<0x114, 0xf>(v);
+    v += lane - 4 >= rs ? y : 0.0f;
+    y = dpp_f32<0x118, 0xf>(v);
+    v += lane - 8 >= rs ? y : 0.0f;
+    y = dpp_f32<0x142, 0xa>(v);
+    v += (lane & ~15) - 1 >= rs ? y : 0.0f;
+    y = dpp_f32<0x143, 0xc>(v);
+    v += 31 >= rs ? y : 0.0f;
     return v;
 }
 
@@ -484,19 +510,30 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
             if (gf) {
                 // destination side: rounds of owner lanes (bounded: every round
                 // retires at least the owner of each contended atom)
+                // (a wave's LDS operations complete in order, so the tag and the
+                // accumulator are read back together, one LDS round trip a round)
                 bool pend = act;
                 for (int round = 0; round < WAVE && ballot(pend) != 0; ++round) {
                     if (pend) mytag[lj] = lane;
-                    wave_lds_sync();
-                    const bool own = pend && mytag[lj] == lane;
-                    if (own) {
-                        my[3 * lj] += x0;
-                        my[3 * lj + 1] += x1;
-                        my[3 * lj + 2] += x2;
+                    __builtin_amdgcn_wave_barrier();
+                    int tg = -1;
+                    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+                    if (pend) {
+                        tg = mytag[lj];
+                        a0 = my[3 * lj];
+                        a1 = my[3 * lj + 1];
+                        a2 = my[3 * lj + 2];
                     }
-                    wave_lds_sync();
+                    const bool own = pend && tg == lane;
+                    if (own) {
+                        my[3 * lj] = a0 + x0;
+                        my[3 * lj + 1] = a1 + x1;
+                        my[3 * lj + 2] = a2 + x2;
+                    }
+                    __builtin_amdgcn_wave_barrier();
                     pend = pend && !own;
                 }
+                wave_lds_sync();
                 // source side
                 const int iu = __builtin_amdgcn_readfirstlane(li);   // lane 0 is always in range
                 const bool uni = ballot(act && li != iu) == 0;
@@ -512,7 +549,7 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
                     // mixed sources: with src non-decreasing over the lanes each
                     // source is one run (checked here: the merge needs it)
                     const int key = act ? li : -1 - lane;   // inactive lanes are runs of their own
-                    const int kprev = __shfl_up(key, 1, WAVE);
+                    const int kprev = key_below(key);
                     unsorted |= act && lane > 0 && kprev >= 0 && li < kprev;
                     const uint64_t heads = ballot(lane == 0 || kprev != key);
                     const int rs = run_start(heads, lane);
@@ -775,7 +812,7 @@ __global__ __launch_bounds__(256) void k_bk_scatter(const float* __restrict__ la
                     sa2 += x2;
                 } else {
                     const int key = act ? li : -1 - lane;
-                    const int kprev = __shfl_up(key, 1, WAVE);
+                    const int kprev = key_below(key);
                     unsorted |= act && lane > 0 && kprev >= 0 && li < kprev;
                     const uint64_t heads = ballot(lane == 0 || kprev != key);
                     const int rs = run_start(heads, lane);

@@ -252,10 +252,28 @@ __device__ inline double wave_sum_f64(double v) {
     return v;
 }
 
-__device__ inline float wave_sum_f32(float v) {
-#pragma unroll
-    for (int d = WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+// A DPP lane move of a float (rows of 16 lanes; lanes the pattern leaves
+// without a source, or in rows outside ROW_MASK, read 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Inclusive scan of v over the wave with DPP row shifts and row broadcasts
+// (VALU only; lane 63 ends with the total).
+__device__ __forceinline__ float wave_incl_scan_f32(float v) {
+    v += dpp_f32<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_f32<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_f32<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_f32<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_f32<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp_f32<0x143, 0xc>(v);   // row_bcast:31
     return v;
+}
+
+// Sum of v over the wave, on every lane (the scan's total read from lane 63).
+__device__ inline float wave_sum_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_incl_scan_f32(v)), 63));
 }
 
 // Structure owning atom `a`: largest b with ptr[b] <= a (ptr non-decreasing, B+1 entries).
