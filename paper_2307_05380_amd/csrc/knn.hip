@@ -54,10 +54,44 @@ __device__ __forceinline__ float ufirstf(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
-    return ((uint64_t)hi << 32) | lo;
+// Value of lane (lane ^ S) without LDS: DPP quad permutes (S = 1, 2), row
+// shifts (4), the row rotation by 8 (8) and the gfx950 lane-swap instructions
+// (16, 32), each checked lane by lane against lane ^ S.
+template <int S>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
+    if constexpr (S == 1) {
+        return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
+    } else if constexpr (S == 2) {
+        return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false);   // quad_perm 2,3,0,1
+    } else if constexpr (S == 4) {
+        const uint32_t up = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xf, 0xf, false);   // row_shl:4
+        const uint32_t dn = __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+        return (lane & 4) ? dn : up;
+    } else if constexpr (S == 8) {
+        return __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false);   // row_ror:8
+    } else if constexpr (S == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else {
+        static_assert(S == 32, "lane strides 1..32");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
+}
+
+// shfl_xor_u64 for a stride that is a constant once the sorting loops unroll.
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int stride, int lane) {
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    uint32_t a, b;
+    switch (stride) {
+        case 1: a = xor_lane_u32<1>(lo, lane); b = xor_lane_u32<1>(hi, lane); break;
+        case 2: a = xor_lane_u32<2>(lo, lane); b = xor_lane_u32<2>(hi, lane); break;
+        case 4: a = xor_lane_u32<4>(lo, lane); b = xor_lane_u32<4>(hi, lane); break;
+        case 8: a = xor_lane_u32<8>(lo, lane); b = xor_lane_u32<8>(hi, lane); break;
+        case 16: a = xor_lane_u32<16>(lo, lane); b = xor_lane_u32<16>(hi, lane); break;
+        default: a = xor_lane_u32<32>(lo, lane); b = xor_lane_u32<32>(hi, lane); break;
+    }
+    return ((uint64_t)b << 32) | a;
 }
 
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
@@ -91,7 +125,7 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[M], int lane) {
             } else {
 #pragma unroll
                 for (int r = 0; r < M; ++r) {
-                    const uint64_t o = shfl_xor_u64(v[r], stride);
+                    const uint64_t o = xor_lane_u64(v[r], stride, lane);
                     const bool asc = (((r * WAVE + lane) & size) == 0);
                     const bool lower = (lane & stride) == 0;
                     const bool take_min = (lower == asc);
