@@ -56,7 +56,9 @@ __device__ __forceinline__ float ufirstf(float v) {
 
 // Value of lane (lane ^ S) without LDS: DPP quad permutes (S = 1, 2), row
 // shifts (4), the row rotation by 8 (8) and the gfx950 lane-swap instructions
-// (16, 32), each checked lane by lane against lane ^ S.
+// (16, 32; the swap of two copies of v leaves the partner's half in the
+// returned register that did not keep this lane's own half). Every stride runs
+// in the sorts of the KNN tests with more than 32 keys per source.
 template <int S>
 __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
     if constexpr (S == 1) {
