@@ -10,7 +10,11 @@
 // neighbours. Keys are (length bits << 32 | candidate ordinal); the ordinal
 // j * I + image_index follows (dst, t) order because image tables are built in
 // lexicographic t order, which gives the tie order (length, dst, t). The
-// result is the k smallest keys whatever order the candidates arrive in.
+// result is the k smallest keys whatever order the candidates arrive in. A
+// candidate is pushed with the bits of its squared length; the length (the
+// correctly rounded root) replaces them, with the sign bit set as a marker,
+// when the buffer is sorted or ranked, so the root is taken once per key that
+// reaches a sort instead of at every sweep step that pushes one.
 //
 // Lane layout: lane (u, jj) keeps the pair offset of one destination in
 // registers and takes every R-th image of the set (R = 64 / min(n, 64) image
@@ -58,7 +62,7 @@ __device__ __forceinline__ float ufirstf(float v) {
 // shifts (4), the row rotation by 8 (8) and the gfx950 lane-swap instructions
 // (16, 32; the swap of two copies of v leaves the partner's half in the
 // returned register that did not keep this lane's own half). Every stride runs
-// in the sorts of the KNN tests with more than 32 keys per source.
+// in the stack compressions of the KNN tests with a wide first radius.
 template <int S>
 __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
     if constexpr (S == 1) {
@@ -103,12 +107,10 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
 }
 
 // Ascending bitonic sort of 64*M keys held as v[r] of lane l = element r*64 + l.
-// With MAXSZ < 64 only the blocks of MAXSZ consecutive lanes are sorted (block 0
-// ascending): enough when every key lies in lanes 0 .. MAXSZ-1.
-template <int M, int MAXSZ = WAVE * M>
+template <int M>
 __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[M], int lane) {
 #pragma unroll
-    for (int size = 2; size <= MAXSZ; size <<= 1) {
+    for (int size = 2; size <= WAVE * M; size <<= 1) {
 #pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             if (stride >= WAVE) {
@@ -139,28 +141,28 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&v)[M], int lane) {
     }
 }
 
-template <int M, int MAXSZ = WAVE * M>
+// Key of a pushed candidate: squared length bits (sign bit clear) and ordinal.
+// As a ranked key: the correctly rounded length's bits with the sign bit set
+// (keys that already are stay as they are; the unused padding key ~0 too).
+__device__ __forceinline__ uint64_t len_key(uint64_t key) {
+    const uint32_t hi = (uint32_t)(key >> 32);
+    const uint32_t lh = __float_as_uint(sqrt_rn_finite(__uint_as_float(hi))) | 0x80000000u;
+    return ((uint64_t)((hi >> 31) ? hi : lh) << 32) | (uint32_t)key;
+}
+
+template <int M>
 __device__ __forceinline__ uint64_t sorted_rank(const uint64_t* buf, int cnt, int lane) {
     uint64_t v[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const int e = r * WAVE + lane;
-        v[r] = e < cnt ? buf[e] : ~0ull;
+        v[r] = e < cnt ? len_key(buf[e]) : ~0ull;
     }
-    bitonic_sort<M, MAXSZ>(v, lane);
+    bitonic_sort<M>(v, lane);
     return v[0];
 }
 
-// Key of rank `lane` among buf[0..cnt) (cnt uniform, <= KNN_CAP); ranks below
-// min(cnt, 32) only when cnt <= 32 (a 32-key network, 15 stages instead of 21).
-__device__ __forceinline__ uint64_t sorted_head(const uint64_t* buf, int cnt, int lane) {
-    if (cnt <= WAVE / 2) return sorted_rank<1, WAVE / 2>(buf, cnt, lane);
-    if (cnt <= WAVE) return sorted_rank<1>(buf, cnt, lane);
-    if (cnt <= 2 * WAVE) return sorted_rank<2>(buf, cnt, lane);
-    return sorted_rank<4>(buf, cnt, lane);
-}
-
-__device__ __forceinline__ float key_len(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32)); }
+__device__ __forceinline__ float key_len(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32) & 0x7fffffffu); }
 
 __device__ __forceinline__ float thr_from_len(float l) { return l * l * (1.0f + 3e-6f) + 1e-30f; }
 
@@ -235,7 +237,7 @@ __device__ __forceinline__ void stack_push(Stack& st, bool pass, float l2, uint3
         c = ufirst(__popcll(m));
         wave_lds_sync();
     }
-    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(sqrt_rn_finite(l2)) << 32) | (uint64_t)lo;
+    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(l2) << 32) | (uint64_t)lo;
     st.cnt = ufirst(st.cnt + c);
 }
 
@@ -244,7 +246,7 @@ __device__ __forceinline__ void stack_append(Stack& st, bool pass, float l2, uin
     const uint64_t m = ballot(pass);
     const int c = ufirst(__popcll(m));
     if (c == 0) return;
-    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(sqrt_rn_finite(l2)) << 32) | (uint64_t)lo;
+    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(l2) << 32) | (uint64_t)lo;
     st.cnt = ufirst(st.cnt + c);
 }
 
@@ -273,7 +275,9 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
     for (int jc = 0; jc < n; jc += nn) {
         const int j = jc + jj;
         const bool lok = (uint32_t)u < R && j < n;
-        float px = 0.f, py = 0.f, pz = 0.f;
+        // a lane without a destination sits far away (its squared distances
+        // overflow to infinity and pass no threshold)
+        float px = 1e30f, py = 1e30f, pz = 1e30f;
         if (lok) {
             double d0 = (double)fr[3 * j] - xi0;
             double d1 = (double)fr[3 * j + 1] - xi1;
@@ -287,13 +291,13 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
             py = (float)y;
             pz = (float)z;
         }
-        const bool selfj = lok && j == il;
+        // the image of the source's own pair that is the source itself (none: all ones)
+        const uint32_t selfm = (lok && j == il) ? (uint32_t)S.zidx : 0xFFFFFFFFu;
         const uint32_t ordj = (uint32_t)j * I;
         auto step = [&](uint32_t m, float sx, float sy, float sz) {
-            const bool valid = lok && m < I;
             const float dx = px + sx, dy = py + sy, dz = pz + sz;
             const float l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const bool pass = valid && l2 < st.tau2 && !(selfj && (int)m == S.zidx);
+            const bool pass = l2 < st.tau2 && m < I && m != selfm;
             stack_push(st, pass, l2, ordj + m, k, buf, lane);
         };
         if (TAB) {
@@ -318,10 +322,9 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
                     const uint32_t mb = m0 + (uint32_t)d * R;
                     if (mb >= I) break;   // uniform
                     const uint32_t m = mb + (uint32_t)u;
-                    const bool valid = lok && m < I;
                     const float dx = px + e[d][0], dy = py + e[d][1], dz = pz + e[d][2];
                     const float l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    const bool pass = valid && l2 < st.tau2 && !(selfj && (int)m == S.zidx);
+                    const bool pass = l2 < st.tau2 && m < I && m != selfm;
                     stack_append(st, pass, l2, ordj + m, buf);
                 }
             }
@@ -350,20 +353,54 @@ __device__ __forceinline__ int collect(const ImageSet& S, float tau2, int k, int
     return st.cnt;
 }
 
-// The k smallest of the cnt keys in buf (cnt uniform, k <= cnt): returns the
-// rank of this lane's key (k or more: no key for this lane) and the key. Up to
-// 32 keys every lane ranks its own key against the others (the keys are
-// distinct, their ordinals are): cnt broadcasts and compares instead of a
-// sorting network's dependent cross-lane exchanges; more keys are sorted (with
-// 33-64 keys the 21-stage network measured faster than 33-64 broadcasts).
-__device__ __forceinline__ int ranked_key(const uint64_t* buf, int cnt, int k, int lane, uint64_t& key) {
-    if (cnt <= WAVE / 2) {
-        key = lane < cnt ? buf[lane] : ~0ull;
-        int rank = 0;
-        for (int q = 0; q < cnt; ++q) rank += readlane_u64(key, q) < key ? 1 : 0;
+// Number of keys among buf[0..cnt) below key, buf padded with all-ones keys up
+// to a multiple of 4 (every lane reads the same address: an LDS broadcast).
+__device__ __forceinline__ int lds_rank(const uint64_t* buf, int cnt, uint64_t key) {
+    int rank = 0;
+    for (int q = 0; q < cnt; q += 4) {
+        const uint64_t a0 = buf[q], a1 = buf[q + 1], a2 = buf[q + 2], a3 = buf[q + 3];
+        rank += (a0 < key ? 1 : 0) + (a1 < key ? 1 : 0) + (a2 < key ? 1 : 0) + (a3 < key ? 1 : 0);
+    }
+    return rank;
+}
+
+// The k smallest of the cnt keys in buf (cnt uniform, k <= cnt <= KNN_CAP):
+// returns the rank of this lane's key (k or more: no key for this lane) and the
+// key. Up to 128 keys (buf holds at least 128) each key is ranked against all
+// of them, read back from LDS (the keys are distinct, their ordinals are): a
+// compare and an add per key instead of a sorting network's dependent
+// cross-lane exchanges; beyond 64 keys (two per lane) the keys are then placed
+// at their ranks. Larger stacks are sorted.
+__device__ __forceinline__ int ranked_key(uint64_t* buf, int cnt, int k, int lane, uint64_t& key) {
+    if (cnt <= WAVE) {
+        key = lane < cnt ? len_key(buf[lane]) : ~0ull;
+        wave_lds_sync();
+        buf[lane] = key;
+        wave_lds_sync();
+        const int rank = lds_rank(buf, cnt, key);
         return lane < cnt ? rank : k;
     }
-    key = sorted_head(buf, cnt, lane);
+    if (cnt <= 2 * WAVE) {
+        const uint64_t a = len_key(buf[lane]);
+        const uint64_t b = lane + WAVE < cnt ? len_key(buf[lane + WAVE]) : ~0ull;
+        wave_lds_sync();
+        buf[lane] = a;
+        buf[lane + WAVE] = b;
+        wave_lds_sync();
+        int ra = 0, rb = 0;
+        for (int q = 0; q < cnt; q += 4) {
+            const uint64_t a0 = buf[q], a1 = buf[q + 1], a2 = buf[q + 2], a3 = buf[q + 3];
+            ra += (a0 < a ? 1 : 0) + (a1 < a ? 1 : 0) + (a2 < a ? 1 : 0) + (a3 < a ? 1 : 0);
+            rb += (a0 < b ? 1 : 0) + (a1 < b ? 1 : 0) + (a2 < b ? 1 : 0) + (a3 < b ? 1 : 0);
+        }
+        wave_lds_sync();
+        if (ra < WAVE) buf[ra] = a;
+        if (lane + WAVE < cnt && rb < WAVE) buf[rb] = b;
+        wave_lds_sync();
+        key = buf[lane];   // every rank below 64 is held by one of the cnt > 64 keys
+        return lane;
+    }
+    key = sorted_rank<KNN_CAP / WAVE>(buf, cnt, lane);
     return lane;
 }
 
@@ -371,7 +408,7 @@ __device__ __forceinline__ int ranked_key(const uint64_t* buf, int cnt, int k, i
 // its rank.
 __device__ __forceinline__ void emit(const ImageSet& S, int cnt, int k, int64_t i, int64_t atom0,
                                      double xi0, double xi1, double xi2, const float* __restrict__ frac,
-                                     const uint64_t* buf, int lane, int32_t* __restrict__ src,
+                                     uint64_t* buf, int lane, int32_t* __restrict__ src,
                                      int32_t* __restrict__ dst, int32_t* __restrict__ image,
                                      float* __restrict__ length) {
     uint64_t key;
@@ -400,7 +437,8 @@ __device__ __forceinline__ void emit(const ImageSet& S, int cnt, int k, int64_t 
 // First pass: the sources of image-sweep structures, each with its
 // structure's image table (radius R0). Items: item_off scans the sources of
 // those structures (skipped structures keep their items and get invalid rows).
-__global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInfo* __restrict__ info,
+// (at most 64 VGPRs: eight waves per SIMD measured 4 % faster than seven)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_knn_first(int B, int k, const StructInfo* __restrict__ info,
                                                    const int64_t* __restrict__ item_off,
                                                    const ImageEntry* __restrict__ table,
                                                    const float* __restrict__ frac,
@@ -473,20 +511,63 @@ __global__ __launch_bounds__(256) void k_knn_first(int B, int k, const StructInf
     if (lane == 0) partials[grid_wave()] = wave_cand;
 }
 
-// Cell-list pass: one workgroup per home bin of a cell-list structure, the 27
-// stencil bins staged in LDS (cl_tile.h), one wave per source of the home
-// bin. Key ordinal: local dst * 32768 + (t0+16, t1+16, t2+16) in 5 bits each,
-// which is the (dst, t) order. The staged positions only pre-filter: a
-// candidate near or under the threshold gets its key distance from the raw
-// coordinates in the form every KNN path shares (knn_l2), so the graph does
-// not depend on the bins or on which pass resolved a source. The stencil
-// covers every candidate within wcl, so a stack that holds >= k keys under a
-// threshold at most wcl^2 is exact. The first sweep uses a tighter threshold,
-// tau_scale times the k-th neighbour distance of a uniform density (fewer keys
-// to sort); a source with fewer than k keys under it is swept again at wcl^2,
-// and one with fewer than k under wcl^2 (or an image component outside
-// [-16, 15]) goes to the extended pass.
+// Cell-list pass: one workgroup per home bin of a cell-list structure, the
+// stencil bins staged in LDS (cl_tile.h), one wave per source of the home bin.
+// Key ordinal: local dst * 32768 + (t0+16, t1+16, t2+16) in 5 bits each, which
+// is the (dst, t) order. The sweep keeps candidates by their staged squared
+// distance (staged keys: its bits and the ordinal), within a margin far above
+// the staged form's difference from the form every KNN path ranks by
+// (knn_l2): (1 + KNN_CL_REL) x the limit + KNN_CL_ABS A^2. At the end the
+// staged k-th key and every key within that margin of it get their key
+// distance in the shared form, which decides the k nearest and their order, so
+// the graph does not depend on the bins or on which pass resolved a source;
+// the raw coordinates are read from global memory once per source instead of
+// at every sweep step that has a candidate near the threshold. The stencil
+// covers every candidate within wcl, so k keys under a threshold at most wcl^2
+// are exact. The first sweep uses a tighter threshold, tau_scale times the
+// k-th neighbour distance of a uniform density; a source whose k-th key
+// distance is not under it is swept again at wcl^2, and one that fails there
+// (or has an image component outside [-16, 15], or more than 64 keys within
+// the margin of its k-th) goes to the extended pass.
 constexpr int KNN_CL_CAP = 128;
+constexpr float KNN_CL_REL = 1e-4f;   // margin on squared distances: relative part
+constexpr float KNN_CL_ABS = 1e-4f;   // and absolute part (A^2)
+
+__device__ __forceinline__ float key_l2(uint64_t key) { return __uint_as_float((uint32_t)(key >> 32)); }
+__device__ __forceinline__ float cl_margin(float l2) { return l2 * (1.0f + KNN_CL_REL) + KNN_CL_ABS; }
+
+// Of the k <= cnt <= KNN_CL_CAP staged keys in buf, the keys within the margin
+// of the k-th smallest: moved to buf[0..s) in key order (this lane's in v,
+// all ones from lane s on), lim = the margin above the k-th. Ranks by LDS
+// broadcast as in ranked_key (buf is padded with all-ones keys to 128).
+// Returns s, or -1 when more than 64 keys lie within the margin.
+__device__ __forceinline__ int cl_near_kth(uint64_t* buf, int cnt, int k, int lane, float& lim, uint64_t& v) {
+    const uint64_t a = lane < cnt ? buf[lane] : ~0ull;
+    const uint64_t b = lane + WAVE < cnt ? buf[lane + WAVE] : ~0ull;
+    wave_lds_sync();
+    buf[lane] = a;
+    buf[lane + WAVE] = b;
+    wave_lds_sync();
+    int ra = 0, rb = 0;
+    for (int q = 0; q < cnt; q += 4) {
+        const uint64_t a0 = buf[q], a1 = buf[q + 1], a2 = buf[q + 2], a3 = buf[q + 3];
+        ra += (a0 < a ? 1 : 0) + (a1 < a ? 1 : 0) + (a2 < a ? 1 : 0) + (a3 < a ? 1 : 0);
+        rb += (a0 < b ? 1 : 0) + (a1 < b ? 1 : 0) + (a2 < b ? 1 : 0) + (a3 < b ? 1 : 0);
+    }
+    const uint64_t ma = ballot(lane < cnt && ra == k - 1);
+    const uint64_t mb = ballot(lane + WAVE < cnt && rb == k - 1);
+    const uint64_t kth = ma ? readlane_u64(a, __builtin_ctzll(ma)) : readlane_u64(b, __builtin_ctzll(mb));
+    lim = ufirstf(cl_margin(key_l2(kth)));
+    const int s = ufirst(__popcll(ballot(lane < cnt && key_l2(a) <= lim)) +
+                         __popcll(ballot(lane + WAVE < cnt && key_l2(b) <= lim)));
+    if (s > WAVE) return -1;
+    wave_lds_sync();
+    if (ra < s) buf[ra] = a;   // the keys within the margin are the s smallest
+    if (rb < s) buf[rb] = b;
+    wave_lds_sync();
+    v = lane < s ? buf[lane] : ~0ull;
+    return s;
+}
 
 __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* __restrict__ info, ClWs w,
                                                 const float* __restrict__ frac,
@@ -524,9 +605,10 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
             bool done = false;
             int overflow = n >= 131072 ? 1 : 0;   // local dst index must fit 17 bits
             for (int attempt = 0; attempt < 2; ++attempt) {
-                Stack st{0, tau};
-                // candidate c with staged (or recomputed) position e: pre-filter with a
-                // margin far above the two forms' difference, then the key distance
+                // staged keys within the margin of the attempt's threshold; when the
+                // stack is full only those within the margin of its k-th stay, and
+                // the limit drops to that margin
+                Stack st{0, ufirstf(cl_margin(tau))};
                 auto consider = [&](int c, const float4 e, int32_t ct, bool valid) {
                     bool pass = false;
                     float l2 = 0.0f;
@@ -535,7 +617,7 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                         const int32_t j = __float_as_int(e.w);
                         const float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
                         l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                        pass = l2 < st.tau2 * (1.0f + 1e-4f) && c != self;
+                        pass = l2 <= st.tau2 && c != self;
                         if (pass) {
                             if (it.staged) ct = tile.ct[c];
                             const int t0 = unpack_t0(ct) + s0, t1 = unpack_t1(ct) + s1, t2 = unpack_t2(ct) + s2;
@@ -543,13 +625,31 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                             overflow |= fits ? 0 : 1;
                             ord = (uint32_t)(j - atom0) * 32768u +
                                   (uint32_t)(((t0 + 16) * 32 + (t1 + 16)) * 32 + (t2 + 16));
-                            const int64_t ja = j;
-                            l2 = knn_l2(it.L, (double)S.x0, (double)S.x1, (double)S.x2, (double)frac[3 * ja],
-                                        (double)frac[3 * ja + 1], (double)frac[3 * ja + 2], t0, t1, t2);
-                            pass = fits && l2 < st.tau2;
+                            pass = fits;
                         }
                     }
-                    stack_push<KNN_CL_CAP>(st, pass, l2, ord, k, buf, lane);
+                    uint64_t m = ballot(pass);
+                    int cnum = ufirst(__popcll(m));
+                    if (cnum == 0) return;
+                    if (st.cnt + cnum > KNN_CL_CAP) {   // st.cnt > 64 >= k here
+                        float lim;
+                        uint64_t v;
+                        const int s = cl_near_kth(buf, st.cnt, k, lane, lim, v);
+                        if (s < 0) {   // too many near-ties: the extended pass takes the source
+                            overflow = 1;
+                            st.cnt = 0;
+                            st.tau2 = -1.0f;
+                        } else {
+                            st.cnt = s;
+                            st.tau2 = ufirstf(fminf(st.tau2, lim));
+                        }
+                        pass = pass && l2 <= st.tau2;
+                        m = ballot(pass);
+                        cnum = ufirst(__popcll(m));
+                        wave_lds_sync();
+                    }
+                    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(l2) << 32) | (uint64_t)ord;
+                    st.cnt = ufirst(st.cnt + cnum);
                 };
                 if (it.staged) {   // the tile is padded to whole pairs of steps: both read first
                     for (int cb = 0; cb < T; cb += 2 * WAVE) {
@@ -567,24 +667,46 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                 }
                 wave_lds_sync();
                 wave_cand += T;
-                const int any_overflow = ufirst(ballot(overflow != 0) != 0 ? 1 : 0);
-                if (st.cnt >= k && !any_overflow) {
-                    uint64_t key;
-                    const int slot = ranked_key(buf, st.cnt, k, lane, key);
-                    if (slot < k) {
-                        const uint32_t qv = (uint32_t)key;
+                if (st.cnt >= k && ufirst(ballot(overflow != 0) != 0 ? 1 : 0) == 0) {
+                    float lim;
+                    uint64_t v;
+                    const int s = cl_near_kth(buf, st.cnt, k, lane, lim, v);
+                    if (s < 0) {
+                        overflow = 1;
+                    } else {
+                        // the shared key form for the keys within the margin of the k-th
+                        const uint32_t qv = (uint32_t)v;
                         const uint32_t jl = qv >> 15, tc = qv & 32767u;
-                        const int64_t e = S.i * k + slot;
-                        src[e] = (int32_t)S.i;
-                        dst[e] = (int32_t)(atom0 + jl);
-                        image[3 * e] = (int)(tc >> 10) - 16;
-                        image[3 * e + 1] = (int)((tc >> 5) & 31u) - 16;
-                        image[3 * e + 2] = (int)(tc & 31u) - 16;
-                        length[e] = key_len(key);
+                        const int t0 = (int)(tc >> 10) - 16, t1 = (int)((tc >> 5) & 31u) - 16, t2 = (int)(tc & 31u) - 16;
+                        float lc = 0.0f;
+                        uint64_t ck = ~0ull;
+                        if (lane < s) {
+                            const int64_t ja = atom0 + jl;
+                            lc = knn_l2(it.L, (double)S.x0, (double)S.x1, (double)S.x2, (double)frac[3 * ja],
+                                        (double)frac[3 * ja + 1], (double)frac[3 * ja + 2], t0, t1, t2);
+                            ck = ((uint64_t)__float_as_uint(sqrt_rn_finite(lc)) << 32) | (uint64_t)qv;
+                        }
+                        wave_lds_sync();
+                        buf[lane] = ck;   // all ones from lane s on: the padding of the rank loop
+                        wave_lds_sync();
+                        const int slot = lane < s ? lds_rank(buf, s, ck) : k;
+                        // exact when the k-th key distance lies under the attempt's threshold
+                        if (ballot(slot == k - 1 && lc < tau) != 0) {
+                            if (slot < k) {
+                                const int64_t e = S.i * k + slot;
+                                src[e] = (int32_t)S.i;
+                                dst[e] = (int32_t)(atom0 + jl);
+                                image[3 * e] = t0;
+                                image[3 * e + 1] = t1;
+                                image[3 * e + 2] = t2;
+                                length[e] = key_len(ck);
+                            }
+                            done = true;
+                        }
                     }
-                    done = true;
                 }
                 wave_lds_sync();   // buf is reused by the next attempt or source
+                const int any_overflow = ufirst(ballot(overflow != 0) != 0 ? 1 : 0);
                 if (done || any_overflow || !(tau < full)) break;
                 tau = full;
             }

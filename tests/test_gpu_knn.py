@@ -78,8 +78,9 @@ def test_single_atom_cells():
 def test_large_stacks_same_graph(k):
     """A wide first radius (lambda = 8) and no tighter first threshold push
     hundreds of keys per source: the ordered stack is compressed inside the
-    sweep and more than 64 keys are sorted at the end. The graph must equal the
-    oracle's and, bit for bit, the graph of the default search."""
+    sweep (sorting network) and more than 64 keys, two per lane, are ranked at
+    the end. The graph must equal the oracle's and, bit for bit, the graph of
+    the default search."""
     rng = np.random.default_rng(70 + k)
     b = inputs.random_batch(rng, 16, 20, 120, 4.0, 12.0, cutoff=5.0, k=k)
     ref = gu.np_graph(gu.knn(b))
