@@ -526,7 +526,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // stencil bins staged in LDS (cl_tile.h), one wave per source of the home bin.
 // Key ordinal: local dst * 32768 + (t0+16, t1+16, t2+16) in 5 bits each, which
 // is the (dst, t) order. The sweep keeps candidates by their staged squared
-// distance (staged keys: its bits and the ordinal), within a margin far above
+// distance (staged keys: its bits and the candidate's index in the stencil, a
+// total order that only has to agree with the distance), within a margin far above
 // the staged form's difference from the form every KNN path ranks by
 // (knn_l2): (1 + KNN_CL_REL) x the limit + KNN_CL_ABS A^2. At the end the
 // staged k-th key and every key within that margin of it get their key
@@ -538,8 +539,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // are exact. The first sweep uses a tighter threshold, tau_scale times the
 // k-th neighbour distance of a uniform density; a source whose k-th key
 // distance is not under it is swept again at wcl^2, and one that fails there
-// (or has an image component outside [-16, 15], or more than 64 keys within
-// the margin of its k-th) goes to the extended pass.
+// (or has more than 64 keys within the margin of its k-th, or one of them with
+// an image component outside [-16, 15]) goes to the extended pass.
 constexpr int KNN_CL_CAP = 128;
 constexpr float KNN_CL_REL = 1e-4f;   // margin on squared distances: relative part
 constexpr float KNN_CL_ABS = 1e-4f;   // and absolute part (A^2)
@@ -559,11 +560,17 @@ __device__ __forceinline__ int cl_near_kth(uint64_t* buf, int cnt, int k, int la
     buf[lane] = a;
     buf[lane + WAVE] = b;
     wave_lds_sync();
-    int ra = 0, rb = 0;
-    for (int q = 0; q < cnt; q += 4) {
-        const uint64_t a0 = buf[q], a1 = buf[q + 1], a2 = buf[q + 2], a3 = buf[q + 3];
-        ra += (a0 < a ? 1 : 0) + (a1 < a ? 1 : 0) + (a2 < a ? 1 : 0) + (a3 < a ? 1 : 0);
-        rb += (a0 < b ? 1 : 0) + (a1 < b ? 1 : 0) + (a2 < b ? 1 : 0) + (a3 < b ? 1 : 0);
+    int ra, rb;
+    if (cnt <= WAVE) {   // one key per lane (b is the padding: rank cnt)
+        ra = lds_rank(buf, cnt, a);
+        rb = cnt;
+    } else {
+        ra = rb = 0;
+        for (int q = 0; q < cnt; q += 4) {
+            const uint64_t a0 = buf[q], a1 = buf[q + 1], a2 = buf[q + 2], a3 = buf[q + 3];
+            ra += (a0 < a ? 1 : 0) + (a1 < a ? 1 : 0) + (a2 < a ? 1 : 0) + (a3 < a ? 1 : 0);
+            rb += (a0 < b ? 1 : 0) + (a1 < b ? 1 : 0) + (a2 < b ? 1 : 0) + (a3 < b ? 1 : 0);
+        }
     }
     const uint64_t ma = ballot(lane < cnt && ra == k - 1);
     const uint64_t mb = ballot(lane + WAVE < cnt && rb == k - 1);
@@ -620,24 +627,13 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                 // stack is full only those within the margin of its k-th stay, and
                 // the limit drops to that margin
                 Stack st{0, ufirstf(cl_margin(tau))};
-                auto consider = [&](int c, const float4 e, int32_t ct, bool valid) {
+                auto consider = [&](int c, const float4 e, bool valid) {
                     bool pass = false;
                     float l2 = 0.0f;
-                    uint32_t ord = 0;
                     if (valid) {
-                        const int32_t j = __float_as_int(e.w);
                         const float dx = e.x - S.px, dy = e.y - S.py, dz = e.z - S.pz;
                         l2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                         pass = l2 <= st.tau2 && c != self;
-                        if (pass) {
-                            if (it.staged) ct = tile.ct[c];
-                            const int t0 = unpack_t0(ct) + s0, t1 = unpack_t1(ct) + s1, t2 = unpack_t2(ct) + s2;
-                            const bool fits = t0 >= -16 && t0 <= 15 && t1 >= -16 && t1 <= 15 && t2 >= -16 && t2 <= 15;
-                            overflow |= fits ? 0 : 1;
-                            ord = (uint32_t)(j - atom0) * 32768u +
-                                  (uint32_t)(((t0 + 16) * 32 + (t1 + 16)) * 32 + (t2 + 16));
-                            pass = fits;
-                        }
                     }
                     uint64_t m = ballot(pass);
                     int cnum = ufirst(__popcll(m));
@@ -659,21 +655,21 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                         cnum = ufirst(__popcll(m));
                         wave_lds_sync();
                     }
-                    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(l2) << 32) | (uint64_t)ord;
+                    if (pass) buf[st.cnt + (int)mbcnt(m)] = ((uint64_t)__float_as_uint(l2) << 32) | (uint32_t)c;
                     st.cnt = ufirst(st.cnt + cnum);
                 };
                 if (it.staged) {   // the tile is padded to whole pairs of steps: both read first
                     for (int cb = 0; cb < T; cb += 2 * WAVE) {
                         const float4 e0 = tile.c[cb + lane], e1 = tile.c[cb + WAVE + lane];
-                        consider(cb + lane, e0, 0, true);
-                        if (cb + WAVE < T) consider(cb + WAVE + lane, e1, 0, true);   // uniform
+                        consider(cb + lane, e0, true);
+                        if (cb + WAVE < T) consider(cb + WAVE + lane, e1, true);   // uniform
                     }
                 } else {
                     for (int cb = 0; cb < T; cb += WAVE) {
                         const int c = cb + lane;
                         int32_t ct = 0;
                         const float4 e = c < T ? cl_candidate(tile, it, w, c, ct) : make_float4(0.f, 0.f, 0.f, 0.f);
-                        consider(c, e, ct, c < T);
+                        consider(c, e, c < T);
                     }
                 }
                 wave_lds_sync();
@@ -685,28 +681,39 @@ __global__ __launch_bounds__(256) void k_knn_cl(int B, int k, const StructInfo* 
                     if (s < 0) {
                         overflow = 1;
                     } else {
-                        // the shared key form for the keys within the margin of the k-th
-                        const uint32_t qv = (uint32_t)v;
-                        const uint32_t jl = qv >> 15, tc = qv & 32767u;
-                        const int t0 = (int)(tc >> 10) - 16, t1 = (int)((tc >> 5) & 31u) - 16, t2 = (int)(tc & 31u) - 16;
+                        // the keys within the margin of the k-th: their candidates' image
+                        // (each component must fit [-16, 15]) and the shared key form
+                        int t0 = 0, t1 = 0, t2 = 0;
+                        int64_t ja = 0;
                         float lc = 0.0f;
                         uint64_t ck = ~0ull;
                         if (lane < s) {
-                            const int64_t ja = atom0 + jl;
+                            const int c = (int)(uint32_t)v;
+                            int32_t ct;
+                            const float4 e = cl_candidate(tile, it, w, c, ct);
+                            ja = (int64_t)__float_as_int(e.w);
+                            t0 = unpack_t0(ct) + s0;
+                            t1 = unpack_t1(ct) + s1;
+                            t2 = unpack_t2(ct) + s2;
+                            const bool fits = t0 >= -16 && t0 <= 15 && t1 >= -16 && t1 <= 15 && t2 >= -16 && t2 <= 15;
+                            overflow |= fits ? 0 : 1;
+                            const uint32_t ord = (uint32_t)(ja - atom0) * 32768u +
+                                                 (uint32_t)(((t0 + 16) * 32 + (t1 + 16)) * 32 + (t2 + 16));
                             lc = knn_l2(it.L, (double)S.x0, (double)S.x1, (double)S.x2, (double)frac[3 * ja],
                                         (double)frac[3 * ja + 1], (double)frac[3 * ja + 2], t0, t1, t2);
-                            ck = ((uint64_t)__float_as_uint(sqrt_rn_finite(lc)) << 32) | (uint64_t)qv;
+                            ck = ((uint64_t)__float_as_uint(sqrt_rn_finite(lc)) << 32) | (uint64_t)ord;
                         }
                         wave_lds_sync();
                         buf[lane] = ck;   // all ones from lane s on: the padding of the rank loop
                         wave_lds_sync();
                         const int slot = lane < s ? lds_rank(buf, s, ck) : k;
                         // exact when the k-th key distance lies under the attempt's threshold
-                        if (ballot(slot == k - 1 && lc < tau) != 0) {
+                        // and every image fits the ordinal
+                        if (ballot(overflow != 0) == 0 && ballot(slot == k - 1 && lc < tau) != 0) {
                             if (slot < k) {
                                 const int64_t e = S.i * k + slot;
                                 src[e] = (int32_t)S.i;
-                                dst[e] = (int32_t)(atom0 + jl);
+                                dst[e] = (int32_t)ja;
                                 image[3 * e] = t0;
                                 image[3 * e + 1] = t1;
                                 image[3 * e + 2] = t2;
