@@ -74,6 +74,9 @@ def _parse(argv=None):
     ap.add_argument("--batch-sweep", action="store_true",
                     help="also time KNN k = 32 with ties kept on batches of 32..512 structures "
                          "(n ~ U{4..64}), with peak device memory")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="time only the rows past the hot path on the 4096-structure batch: symmetric "
+                         "closure and triplets of its KNN graph, the cutoff graph with per-atom cutoffs")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args(argv)
 
@@ -221,6 +224,9 @@ def main(argv=None):
     if args.update_loop_only:
         res = update_loop(dev, args.update_loop or 10, cpu_sample=not args.no_cpu_baseline, tune_first=not args.no_tune)
         print(json.dumps({"update_loop": res, "source_digest": source_digest()}))
+        return 0
+    if args.extras_only:
+        print(json.dumps({"extras": extras(dev), "source_digest": source_digest()}))
         return 0
     batch = inputs.make_config(args.config)
     B, N, k, c = batch.B, batch.N, batch.k, batch.cutoff
@@ -594,6 +600,114 @@ def update_loop_cpu(b, sources: int = 24):
             "sample": f"{len(srcs)} sources of the {n}-atom supercell, {dt:.1f} s; per-source time scaled "
                       f"by n_s / {n} for every supercell s (the oracle compares a source with all n_s atoms)",
             "seconds_per_step": round(step_s, 1)}
+
+
+def _time_calls(call, reps: int = 20) -> float:
+    """Milliseconds per call of `call` (device events around `reps` calls, after one)."""
+    import torch
+
+    call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _hbm(ms: float, nbytes: float) -> dict:
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 4), "algorithmic_bytes": int(nbytes), "achieved": round(gbs, 1), "peak": 8000.0,
+            "unit": "GB/s", "frac": round(gbs / 8000.0, 4)}
+
+
+def extras(dev, reps: int = 20):
+    """The rows past the hot path on the 4096-structure batch (cutoff 8 A, k = 16),
+    one library call per timing with preallocated buffers (device events):
+    symmetric closure of the KNN graph (read dst, image, length = 20 B per input
+    edge; write src, dst, image, length = 24 B per output edge), triplets with
+    angles of the KNN graph (12 B per triplet written, the edge vectors read
+    once), and the cutoff graph with per-atom cutoffs c_i ~ U(6, 8) A (seeded)
+    against the same call at one cutoff of 8 A (dst, image, length and src: 24 B
+    per edge)."""
+    import numpy as np
+    import torch
+
+    from paper_2307_05380_amd import _lib, graph, inputs
+    from paper_2307_05380_amd.graph import _ptr, _stream
+
+    lib = _lib.load()
+    b = inputs.make_config3()
+    L = torch.from_numpy(b.lattices).to(dev)
+    X = torch.from_numpy(b.frac).to(dev)
+    P = torch.from_numpy(b.batch_ptr).to(dev)
+    N, k = b.N, b.k
+    opts = _lib.MG_OPT_CELL_LIST_OFF
+    out = {}
+    g = graph.knn_graph(L, X, P, k, opts=opts)
+    E = N * k
+    row_ptr = torch.arange(0, E + 1, k, dtype=torch.int64, device=dev)
+    dst, image, length = g.dst.contiguous(), g.image.contiguous(), g.length.contiguous()
+    rep = torch.zeros(_lib.REPORT_BYTES // 8, dtype=torch.int64, device=dev)
+
+    # symmetric closure (f1)
+    cap = 2 * E
+    ws = torch.empty(max(int(lib.mg_symmetrize_workspace_bytes(N, E)), 256), dtype=torch.uint8, device=dev)
+    so = [torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+          torch.empty((cap, 3), dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.float32, device=dev)]
+    optr = torch.empty(N + 1, dtype=torch.int64, device=dev)
+
+    def sym():
+        _lib.check(lib.mg_symmetrize(_ptr(row_ptr), N, _ptr(dst), _ptr(image), _ptr(length), E, cap,
+                                     *[_ptr(o) for o in so], _ptr(optr), _ptr(rep), _ptr(ws), ws.numel(),
+                                     _stream(dev)), lib)
+
+    ms = _time_calls(sym, reps)
+    S = graph.Report.from_tensor(rep).num_edges
+    out["symmetrize"] = {"input_edges": E, "output_edges": S,
+                         **_hbm(ms, 20.0 * E + 24.0 * S + 16.0 * (N + 1))}
+    del ws, so, optr
+
+    # triplets with angles (f2)
+    geo = graph.GeometryRunner(b.B, N, dev)
+    vec = torch.empty((E, 3), dtype=torch.float32, device=dev)
+    lv = torch.empty(E, dtype=torch.float32, device=dev)
+    geo.forward(L, X, P, g.src, dst, image, vec, lv)
+    T = N * k * (k - 1)
+    ws = torch.empty(max(int(lib.mg_triplets_workspace_bytes(N)), 256), dtype=torch.uint8, device=dev)
+    to = [torch.empty(T, dtype=torch.int32, device=dev), torch.empty(T, dtype=torch.int32, device=dev),
+          torch.empty(T, dtype=torch.float32, device=dev)]
+    tptr = torch.empty(N + 1, dtype=torch.int64, device=dev)
+
+    def trip():
+        _lib.check(lib.mg_triplets(_ptr(row_ptr), N, E, _ptr(vec), T, *[_ptr(o) for o in to], _ptr(tptr),
+                                   _ptr(rep), _ptr(ws), ws.numel(), _stream(dev)), lib)
+
+    ms = _time_calls(trip, reps)
+    got = graph.Report.from_tensor(rep).num_edges
+    out["triplets"] = {"edges": E, "triplets": got, **_hbm(ms, 12.0 * got + 12.0 * E + 16.0 * (N + 1))}
+    del ws, to, tptr, vec, lv, g
+
+    # per-atom cutoffs (f3) against one cutoff
+    radii = torch.from_numpy(np.random.default_rng(230705380 + 60).uniform(6.0, 8.0, N).astype(np.float32)).to(dev)
+    gr = graph.cutoff_graph(L, X, P, radii, opts=opts)
+    Er, icap = gr.num_edges, gr.report.images_needed
+    del gr
+    cb = graph.CutoffBuilder(b.B, N, Er, icap, dev)
+    ms_r = _time_calls(lambda: cb.run(L, X, P, radii, opts), reps)
+    assert cb.report().num_edges == Er
+    g8 = graph.cutoff_graph(L, X, P, 8.0, opts=opts)
+    E8, icap8 = g8.num_edges, g8.report.images_needed
+    del g8, cb
+    cb = graph.CutoffBuilder(b.B, N, E8, icap8, dev)
+    ms_8 = _time_calls(lambda: cb.run(L, X, P, 8.0, opts), reps)
+    out["per_atom_cutoffs"] = {"edges": Er, "edges_per_s": round(Er / (ms_r * 1e-3), 1), **_hbm(ms_r, 24.0 * Er),
+                               "one_cutoff_8A": {"edges": E8, "edges_per_s": round(E8 / (ms_8 * 1e-3), 1),
+                                                 **_hbm(ms_8, 24.0 * E8)}}
+    return out
 
 
 def batch_sweep(dev, sizes=(32, 64, 128, 256, 512), k=32, reps=10):
