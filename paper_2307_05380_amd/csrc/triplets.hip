@@ -34,13 +34,26 @@ __global__ __launch_bounds__(256) void k_trip_fill(const int64_t* __restrict__ r
                                                    const int64_t* __restrict__ offsets, int64_t capacity,
                                                    const float* __restrict__ vec, int32_t* __restrict__ e1,
                                                    int32_t* __restrict__ e2, float* __restrict__ cosv) {
+    // a row of at most 64 edges: its vectors and their norms staged once per
+    // source (the per-triplet arithmetic is the same as from global memory)
+    __shared__ float4 sv[4][WAVE];
     const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (int64_t i = grid_wave(); i < N; i += grid_waves()) {
         const uint32_t cnt = counts[i];
         if (cnt == 0) continue;
         const int64_t r0 = row_ptr[i];
         const uint32_t dm1 = (uint32_t)(row_ptr[i + 1] - r0) - 1u;   // d - 1 >= 1
         const int64_t o0 = offsets[i];
+        const bool staged = cosv != nullptr && dm1 < (uint32_t)WAVE;
+        if (staged) {
+            if ((uint32_t)lane <= dm1) {
+                const int64_t e = r0 + lane;
+                const float x = vec[3 * e], y = vec[3 * e + 1], z = vec[3 * e + 2];
+                sv[wv][lane] = make_float4(x, y, z, sqrtf(fmaf(z, z, fmaf(y, y, x * x))));
+            }
+            wave_lds_sync();
+        }
         for (uint32_t p = (uint32_t)lane; p < cnt; p += WAVE) {
             const int64_t q = o0 + p;
             if (q >= capacity) break;
@@ -50,7 +63,12 @@ __global__ __launch_bounds__(256) void k_trip_fill(const int64_t* __restrict__ r
             const int64_t ea = r0 + a, eb = r0 + b;
             e1[q] = (int32_t)ea;
             e2[q] = (int32_t)eb;
-            if (cosv) {
+            if (staged) {
+                const float4 va = sv[wv][a], vb = sv[wv][b];
+                const float num = fmaf(va.z, vb.z, fmaf(va.y, vb.y, va.x * vb.x));
+                const float den = va.w * vb.w;
+                cosv[q] = den > 0.0f ? num / den : 0.0f;
+            } else if (cosv) {
                 const float ax = vec[3 * ea], ay = vec[3 * ea + 1], az = vec[3 * ea + 2];
                 const float bx = vec[3 * eb], by = vec[3 * eb + 1], bz = vec[3 * eb + 2];
                 const float num = fmaf(az, bz, fmaf(ay, by, ax * bx));
@@ -58,6 +76,7 @@ __global__ __launch_bounds__(256) void k_trip_fill(const int64_t* __restrict__ r
                 cosv[q] = den > 0.0f ? num / den : 0.0f;
             }
         }
+        if (staged) wave_lds_sync();   // the next source overwrites the staged row
     }
 }
 
@@ -72,7 +91,10 @@ hipError_t launch_triplets(const int64_t* row_ptr, int64_t N, int64_t E, const f
     }
     hipError_t e = launch_scan_counts(counts, N, offsets, bsum, capacity, report, s);
     if (e != hipSuccess || N == 0) return e;
-    hipLaunchKernelGGL(k_trip_fill, dim3(cu * 8), dim3(256), 0, s, row_ptr, N, counts, offsets, capacity, vec,
+    // up to four times the resident grid (the dispatcher refills)
+    const int64_t gf = (N + 3) / 4;
+    hipLaunchKernelGGL(k_trip_fill, dim3((unsigned)(gf < cu * 32 ? gf : cu * 32)), dim3(256), 0, s, row_ptr, N,
+                       counts, offsets, capacity, vec,
                        e1, e2, cosv);
     return hipGetLastError();
 }
