@@ -51,6 +51,32 @@ def test_supercell_cutoff_cell_lists(supercells, span):
     assert np.array_equal(np.repeat(np.arange(b.N), np.diff(rp)), s)
 
 
+@pytest.mark.parametrize("k", [32, 64])
+def test_supercell_knn_large_stacks_same_graph(supercells, k):
+    """A wide search radius (lambda = 8: stencils beyond what the tile stages,
+    candidates read from the slot arrays) and no tighter first threshold push
+    hundreds of staged keys per source: the cell-list stack keeps only the keys
+    near its k-th inside the sweep, and more than 64 keys are ranked two per
+    lane. The graph must equal the default search's bit for bit and the
+    oracle's on sampled sources."""
+    b = supercells
+    ref = gu.np_graph(gu.knn(b, k=k))
+    saved = _lib.get_tuning()
+    try:
+        _lib.set_tuning(**dict(saved, knn_lambda_x4=32, knn_tau_x8=64))
+        g = gu.knn(b, k=k)
+    finally:
+        _lib.set_tuning(**saved)
+    assert g.report.flags & ~_lib.MG_FLAG_KNN_EXTENDED == 0, g.report.flag_names()
+    got = gu.np_graph(g)
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
+    s, d, t, ln = got
+    for q in range(b.B):
+        n = int(b.batch_ptr[q + 1] - b.batch_ptr[q])
+        compare.knn_sources_check(b, q, k, _sample(n, 16, 30 + q), s, d, t, ln)
+
+
 @pytest.mark.parametrize("span", [1, 2])
 def test_supercell_knn_cell_lists(supercells, span):
     b = supercells
