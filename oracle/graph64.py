@@ -17,8 +17,8 @@ Bounded enumeration. With f = x_j - x_i + t and v = f L, one has f = v L^{-1},
 so |f_k| = |v . (L^{-1})[:, k]| <= ||v|| * r_k where r_k is the norm of
 column k of L^{-1} (Cauchy-Schwarz). Every candidate with ||v|| <= R
 therefore has t_k in [ceil(-R r_k - d_k), floor(R r_k - d_k)], d = x_j - x_i.
-This plays the role of the paper's "evaluated area covers the search area"
-test (Sec. 2.2, Fig. 2). The oracle enumerates the union of those ranges over
+This plays the role of the paper's test that the region of cells evaluated
+covers the search sphere (Sec. 2.2, Fig. 2). The oracle enumerates the union of those ranges over
 all destinations of one source and tests every candidate; the KNN search
 grows R (doubling) until the k-th distance is covered, which is Algorithm 1's
 expanding search used only as a bound.

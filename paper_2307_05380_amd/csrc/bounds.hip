@@ -4,8 +4,9 @@
 // satisfy |f_k| <= R r_k with r_k the norm of column k of L^{-1}, i.e. one over
 // the spacing of the lattice planes spanned by the other two vectors. With the
 // pair displacement wrapped into [-1/2, 1/2]^3, every image that can hold a
-// neighbour within R has |t_k| <= floor(R r_k + 1/2). That box is the paper's
-// "evaluated area that covers the search sphere" (Sec. 2.2, Fig. 2); the image
+// neighbour within R has |t_k| <= floor(R r_k + 1/2). That box is the region
+// of cells the method evaluates so that it contains the search sphere (Sec.
+// 2.2, Fig. 2); the image
 // tables then keep only the lattice translations whose cell (t + [-1/2,1/2]^3) L
 // comes within R of the origin, tested exactly in FP64.
 #include "mg_internal.h"

@@ -1,8 +1,9 @@
 // k-nearest-neighbour multigraph (Sec. 1; Sec. 2.2, Algorithms 1 and 2).
 //
 // One wave per source atom. The candidates (j, t) of the source are streamed
-// through a per-wave LDS buffer: the paper's ordered stack ("concatenate new
-// data, sort by distance, keep the k nearest"), kept on chip. A candidate
+// through a per-wave LDS buffer: the paper's ordered stack (new candidates
+// joined to the kept ones, ordered by distance, cut to the k nearest), kept on
+// chip. A candidate
 // survives when its FP32 length is below the current threshold and is
 // appended to the buffer; when the buffer is full it is sorted (bitonic, in
 // registers across the 64 lanes), cut to the k smallest keys and the threshold
@@ -28,8 +29,8 @@
 // is exact: every candidate shorter than R0 lies in the table. Sources with
 // fewer than k survivors are queued for the extended pass, which enumerates the
 // full image box of radius 2 R0, 4 R0, ... (images computed on the fly in FP64)
-// until k are found inside the radius - the expanding search of Algorithm 1
-// with the termination test "k-th distance inside the evaluated area".
+// until k are found inside the radius - the expanding search of Algorithm 1,
+// which stops once the k-th distance lies inside the region already evaluated.
 //
 // Every wave-level decision (loop bounds, stack size, threshold, the sort
 // branch) is taken on values made explicitly uniform with readfirstlane, every
@@ -86,7 +87,8 @@ __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int lane) {
     }
 }
 
-// shfl_xor_u64 for a stride that is a constant once the sorting loops unroll.
+// The 64-bit key of lane (lane ^ stride), for a stride that is a constant once
+// the sorting loops unroll.
 __device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int stride, int lane) {
     const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
     uint32_t a, b;
