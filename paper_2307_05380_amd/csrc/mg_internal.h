@@ -408,7 +408,7 @@ struct GeomBwdWs {
 // Bucket path sizes: atoms per destination block (one LDS accumulator block)
 // and the largest structure it takes (more blocks than the per-chunk LDS
 // histogram holds go to the atomic kernel).
-constexpr int BW_CHUNK = 16384;   // edges per backward item
+constexpr int BW_CHUNK = 8192;   // edges per backward item (16384: 1-3 % slower, 4096: 2 % slower)
 constexpr int BK_BLOCK = 256;   // atoms per destination block (512: 2-3 % slower on the 64 supercells)
 constexpr int BK_MAX_BLOCKS = 256;
 // Counts-matrix capacity for a batch of B structures and E edges.
