@@ -352,7 +352,7 @@ __device__ __forceinline__ bool bwd_item(int64_t item, int B, const int64_t* __r
 // register sum M = sum c f^T f (FP32 per lane, FP64 over lanes and waves),
 // multiplied by L once per item. The four
 // copies are summed at the end and written with plain stores when the item is
-// the whole structure. Each wave walks a contiguous quarter of the item, four
+// the whole structure. Each wave walks a contiguous quarter of the item, three
 // groups of 64 edges per step with all their loads issued first. A dst outside
 // the structure sets flag bit 1, a src outside it (or, where a step mixes
 // sources, a src smaller than the previous lane's) sets bit 0 (the results are
@@ -433,7 +433,7 @@ void k_geom_bwd_lds(const float* __restrict__ lattices, const float* __restrict_
         }
         sa0 = sa1 = sa2 = 0.f;
     };
-    constexpr int U = 4;
+    constexpr int U = 3;   // edge groups in flight per wave (4: 4 % slower, 2: about the same)
     for (int rb = (int)(w0 - it.c0); rb < r1; rb += WAVE * U) {
         int ai[U], aj[U], at[U][3];
         float ag[U][3], al[U];
