@@ -479,9 +479,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             write_invalid(i, k, lane, src, dst, image, length);
             continue;
         }
-        double L[9];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) L[r] = si->L[r];
+        const double* L = si->L;   // read where the pair offsets are formed
         const double xi0 = frac[3 * i], xi1 = frac[3 * i + 1], xi2 = frac[3 * i + 2];
         ImageSet S;
         S.tab = table + si->img_off;

@@ -193,9 +193,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         const int I = si->box == 0 ? 0 : si->images;
         const int zimg = si->zero_img;
         const ImageEntry* tab = table + si->img_off;
-        double L[9];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) L[r] = si->L[r];
+        // the lattice is read where the pair offsets are formed (held in scalar
+        // registers through the image loop it made the sweep spill more of them)
+        const double* L = si->L;
         // (count) where the count of local source a in this item's chunk goes
         auto cslot = [&](int a) -> uint32_t* {
             return C == 1 ? counts + atom0 + a : ccount + xoff + (int64_t)a * C + ck_beg;
