@@ -361,7 +361,7 @@ def main(argv=None):
         for fork in ("start", "after_cutoff"):
             schedule["knn_fork"] = fork
             for cw in (16, 32, 64):
-                for kw in (2, 4, 16):
+                for kw in (1, 2, 4, 16):
                     cfg = {**tuning, "cutoff_wgs_per_cu": cw, "knn_wgs_per_cu": kw}
                     _lib.set_tuning(**cfg)
                     g = capture(step_timed)
